@@ -1,0 +1,240 @@
+"""Oracle: the plain definitions behind Algorithm 1 (Compress / Decompress).
+
+TEST INFRASTRUCTURE ONLY -- see the package docstring.  float64 throughout.
+
+Conventions (readings of the paper where it is silent or inconsistent):
+* indices are 0-based; h1/s1 hash the row index i of A, h2/s2 the column
+  index j of B (Section 3.1);
+* a hash table entry is a uint32 holding the bucket in bits [0, log2b) and
+  the sign in bit 31 (1 means -1);
+* the transform is the unnormalised Walsh-Hadamard transform in natural
+  (Sylvester) order, H[u, r] = (-1)^popcount(u & r), so H H = b I; the
+  inverse transform of Algorithm 1 is applied with the exact scale 2^-log2b,
+  which makes p the XOR convolution of eq. (fwhtxorconvolution) exactly;
+* the median needs an odd number of repetitions d (the formula for d in
+  Section 5.6 always gives an odd number).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SIGN_BIT = np.uint32(1 << 31)
+
+
+# --------------------------------------------------------------------- hashing
+def multiply_add_shift(a: int, c: int, x: np.ndarray, out_bits: int) -> np.ndarray:
+    """Section 4.2: h_{a,c}(x) = floor(((a x + c) mod 2^64) / 2^(64 - out_bits)).
+
+    NumPy uint64 arithmetic wraps modulo 2^64, which is the "mod 2^64" of the
+    64-bit multiplication and addition."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        v = np.uint64(a) * x + np.uint64(c)
+    return (v >> np.uint64(64 - out_bits)).astype(np.uint64)
+
+
+def hash_tables(keys: np.ndarray, n_rows: int, n_cols: int, log2b: int):
+    """Algorithm 1, Compress (the draws of s1, s2, h1, h2 per repetition) with
+    the Section 4.2 family; the sign hash is the same family with b = 2.
+
+    keys: uint64 [d][4][2], rows (a, c) for h1, h2, s1, s2.
+    Returns tab1 uint32[d][n_rows], tab2 uint32[d][n_cols]."""
+    keys = np.asarray(keys, dtype=np.uint64)
+    d = keys.shape[0]
+    tab1 = np.zeros((d, n_rows), dtype=np.uint32)
+    tab2 = np.zeros((d, n_cols), dtype=np.uint32)
+    xr = np.arange(n_rows, dtype=np.uint64)
+    xc = np.arange(n_cols, dtype=np.uint64)
+    for t in range(d):
+        (a1, c1), (a2, c2), (as1, cs1), (as2, cs2) = [(int(k[0]), int(k[1])) for k in keys[t]]
+        h1 = multiply_add_shift(a1, c1, xr, log2b)
+        h2 = multiply_add_shift(a2, c2, xc, log2b)
+        s1 = multiply_add_shift(as1, cs1, xr, 1)   # 1 means sign -1
+        s2 = multiply_add_shift(as2, cs2, xc, 1)
+        tab1[t] = (h1 | (s1 << np.uint64(31))).astype(np.uint32)
+        tab2[t] = (h2 | (s2 << np.uint64(31))).astype(np.uint32)
+    return tab1, tab2
+
+
+def bucket(tab: np.ndarray) -> np.ndarray:
+    """Bucket index of a table entry."""
+    return (np.asarray(tab) & np.uint32(0x7FFFFFFF)).astype(np.int64)
+
+
+def sign(tab: np.ndarray) -> np.ndarray:
+    """Sign (+1.0 / -1.0) of a table entry."""
+    return np.where(np.asarray(tab) & SIGN_BIT, -1.0, 1.0)
+
+
+# ------------------------------------------------------------------ sketching
+def count_sketch(M: np.ndarray, tab: np.ndarray, side: int, k0: int, kc: int,
+                 log2b: int) -> np.ndarray:
+    """Algorithm 1, the two inner loops of Compress, for kc consecutive k.
+
+    side 0 (A, n_rows x n_inner): out[t][kk][x] = sum_{i: h1(i)=x} s1(i) A[i, k0+kk]
+    side 1 (B, n_inner x n_cols): out[t][kk][x] = sum_{j: h2(j)=x} s2(j) B[k0+kk, j]
+    Rows (columns) are added in ascending index order."""
+    d = tab.shape[0]
+    b = 1 << log2b
+    out = np.zeros((d, kc, b), dtype=np.float64)
+    for t in range(d):
+        h = bucket(tab[t])
+        s = sign(tab[t])
+        for idx in range(tab.shape[1]):
+            vals = M[idx, k0:k0 + kc] if side == 0 else M[k0:k0 + kc, idx]
+            out[t, :, h[idx]] += s[idx] * vals
+    return out
+
+
+# ------------------------------------------------------------------ transform
+def wht(x: np.ndarray, scale: float = 1.0) -> np.ndarray:
+    """Walsh-Hadamard transform along the last axis (Section 3.2): the
+    textbook radix-2 butterflies (a, b) -> (a + b, a - b) over strides
+    1, 2, 4, ..., giving natural order; then multiplied by ``scale``.
+    Returns a new array."""
+    y = np.array(x, dtype=np.float64, copy=True)
+    b = y.shape[-1]
+    assert b & (b - 1) == 0, "length must be a power of two"
+    lead = y.shape[:-1]
+    h = 1
+    while h < b:
+        v = y.reshape(lead + (b // (2 * h), 2, h))
+        lo = v[..., 0, :].copy()
+        hi = v[..., 1, :].copy()
+        v[..., 0, :] = lo + hi
+        v[..., 1, :] = lo - hi
+        h *= 2
+    if scale != 1.0:
+        y *= scale
+    return y
+
+
+def wht_matrix(log2b: int) -> np.ndarray:
+    """The definition H[u, r] = (-1)^popcount(u & r) (natural order)."""
+    b = 1 << log2b
+    u = np.arange(b, dtype=np.int64)
+    and_ = u[:, None] & u[None, :]
+    pop = np.zeros_like(and_)
+    for bit in range(log2b):
+        pop += (and_ >> bit) & 1
+    return np.where(pop & 1, -1.0, 1.0)
+
+
+def xor_convolution(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """eq. (fwhtxorconvolution): (x *xor y)[k] = sum_{i xor j = k} x[i] y[j]."""
+    b = x.shape[-1]
+    out = np.zeros(b)
+    for i in range(b):
+        for j in range(b):
+            out[i ^ j] += x[i] * y[j]
+    return out
+
+
+# ----------------------------------------------------------------- accumulate
+def accumulate(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Algorithm 1, p[t] += H{p_A} o H{p_B} summed over k (ascending):
+    p_hat[t][u] = sum_kk X[t][kk][u] * Y[t][kk][u]."""
+    d, kc, b = X.shape
+    p_hat = np.zeros((d, b))
+    for kk in range(kc):
+        p_hat += X[:, kk, :] * Y[:, kk, :]
+    return p_hat
+
+
+# ------------------------------------------------------------------- compress
+def compress_alg1(A: np.ndarray, B: np.ndarray, tab1: np.ndarray, tab2: np.ndarray,
+                  log2b: int, k_chunk: int = 256) -> np.ndarray:
+    """Algorithm 1, Compress, in the paper's order: per repetition, sketch
+    column k of A and row k of B, transform both, add the pointwise product
+    into p[t]; finally p[t] <- 2^-log2b H{p[t]}.  Returns p float64[d][b]."""
+    d = tab1.shape[0]
+    n_inner = A.shape[1]
+    b = 1 << log2b
+    p_hat = np.zeros((d, b))
+    for k0 in range(0, n_inner, k_chunk):
+        kc = min(k_chunk, n_inner - k0)
+        X = wht(count_sketch(A, tab1, 0, k0, kc, log2b))
+        Y = wht(count_sketch(B, tab2, 1, k0, kc, log2b))
+        p_hat += accumulate(X, Y)
+    return wht(p_hat, 2.0 ** -log2b)
+
+
+def bucket_sums(C: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, log2b: int,
+                row_block: int = 512) -> np.ndarray:
+    """The plain definition of the sketch p that Compress reaches (Section 3.2
+    with eq. (fwhtxorconvolution), and the estimator decomposition of
+    Section 6.4): p_t[x] = sum over (i, j) with h1(i) xor h2(j) = x of
+    s1(i) s2(j) C[i, j].  Summed in row-major (i, j) order within blocks of
+    ``row_block`` rows, blocks added in ascending order."""
+    d = tab1.shape[0]
+    b = 1 << log2b
+    n_rows, n_cols = C.shape
+    p = np.zeros((d, b))
+    for t in range(d):
+        h1, s1 = bucket(tab1[t]), sign(tab1[t])
+        h2, s2 = bucket(tab2[t]), sign(tab2[t])
+        for r0 in range(0, n_rows, row_block):
+            r1 = min(n_rows, r0 + row_block)
+            idx = (h1[r0:r1, None] ^ h2[None, :]).ravel()
+            w = (s1[r0:r1, None] * s2[None, :] * C[r0:r1]).ravel()
+            p[t] += np.bincount(idx, weights=w, minlength=b)
+    return p
+
+
+def product(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """C = A B in float64 (library matmul as a step)."""
+    return np.asarray(A, dtype=np.float64) @ np.asarray(B, dtype=np.float64)
+
+
+# -------------------------------------------------------------------- extract
+def gather_reps(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray,
+                rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
+    """Algorithm 1, Decompress: x_t = s1[t](i) s2[t](j) p[t][h1[t](i) xor h2[t](j)]
+    for every (i, j) in rows x cols.  Returns float64[d][len(rows)][len(cols)]."""
+    d = p.shape[0]
+    out = np.empty((d, len(rows), len(cols)))
+    for t in range(d):
+        h1, s1 = bucket(tab1[t][rows]), sign(tab1[t][rows])
+        h2, s2 = bucket(tab2[t][cols]), sign(tab2[t][cols])
+        out[t] = s1[:, None] * s2[None, :] * p[t][h1[:, None] ^ h2[None, :]]
+    return out
+
+
+def extract(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, estimator: str = "median",
+            rows=None, cols=None, row_block: int = 256) -> np.ndarray:
+    """Algorithm 1, Decompress, for a dense block of entries: Median(x) over
+    the d repetitions (odd d), or the mean over d (the mean-over-d estimator;
+    each repetition is unbiased, Section 3.1)."""
+    d = p.shape[0]
+    rows = np.arange(tab1.shape[1]) if rows is None else np.asarray(rows)
+    cols = np.arange(tab2.shape[1]) if cols is None else np.asarray(cols)
+    if estimator == "median" and d % 2 == 0:
+        raise ValueError("median estimator needs an odd number of repetitions")
+    out = np.empty((len(rows), len(cols)))
+    for r0 in range(0, len(rows), row_block):
+        x = gather_reps(p, tab1, tab2, rows[r0:r0 + row_block], cols)
+        out[r0:r0 + row_block] = np.median(x, axis=0) if estimator == "median" else x.mean(axis=0)
+    return out
+
+
+def estimate(A: np.ndarray, B: np.ndarray, keys: np.ndarray, log2b: int,
+             estimator: str = "median"):
+    """Compress + dense Decompress through the plain definition.
+    Returns (C_hat, p, tab1, tab2)."""
+    tab1, tab2 = hash_tables(keys, A.shape[0], B.shape[1], log2b)
+    p = bucket_sums(product(A, B), tab1, tab2, log2b)
+    return extract(p, tab1, tab2, estimator), p, tab1, tab2
+
+
+# ------------------------------------------------------------------- gradient
+def grad_mean(A: np.ndarray, B: np.ndarray, W: np.ndarray, tab1: np.ndarray,
+              tab2: np.ndarray, log2b: int):
+    """Gradient of L = sum(W o C_hat) for the mean-over-d estimator.
+
+    C_hat = (1/d) sum_t L_t(A B) with L_t(C)[i, j] = s1 s2 p_t[h1(i) xor h2(j)]
+    and p_t the bucket sums of C.  L_t is self-adjoint (its kernel
+    s(i,j) s(i',j') [h(i,j) = h(i',j')] is symmetric), so dL/dC = G =
+    (1/d) sum_t L_t(W), and by the product rule dA = G B^T, dB = A^T G."""
+    q = bucket_sums(W, tab1, tab2, log2b)
+    G = extract(q, tab1, tab2, "mean")
+    return G @ B.T, A.T @ G, G

@@ -1,0 +1,341 @@
+"""Pins for the CPU oracle: each check compares the oracle with something
+other than itself (hand-worked values, closed forms, brute force, library
+routines, invariants of the mathematics)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+from workloads import draw_keys, exact_sparse_256, hadamard_sparse, small_random
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _tables(h, s, log2b):
+    """Build table entries from explicit buckets and signs (no hashing)."""
+    h = np.asarray(h, dtype=np.uint32)
+    s = np.asarray(s)
+    return (h | np.where(s < 0, np.uint32(1 << 31), np.uint32(0))).astype(np.uint32)[None, :]
+
+
+# ---------------------------------------------------------------------- hash
+def test_hash_golden():
+    g = _load("hash_small.json")
+    for case in g["cases"]:
+        got = O.multiply_add_shift(int(case["a"]), int(case["c"]), np.array(case["x"]), case["log2b"])
+        assert got.tolist() == case["h"], case
+
+
+@pytest.mark.parametrize("m", [1, 4, 12, 16, 18, 31])
+def test_hash_identity_special_case(m):
+    # a = 2^(64-m), c = 0  =>  h(x) = x mod 2^m  (the shift undoes the multiply)
+    x = np.arange(0, 5000, 7, dtype=np.uint64)
+    got = O.multiply_add_shift(1 << (64 - m), 0, x, m)
+    assert np.array_equal(got, x % (1 << m))
+
+
+def test_hash_constant_and_wrap():
+    x = np.arange(100, dtype=np.uint64)
+    # a = 0: constant bucket c >> (64 - m)
+    assert np.all(O.multiply_add_shift(0, 0xDEADBEEF00000000, x, 8) == (0xDEADBEEF00000000 >> 56))
+    # a = 2^64 - 1 (i.e. -1): (-x mod 2^64) >> (64 - m) = 2^m - 1 for 1 <= x < 2^(64-m)
+    got = O.multiply_add_shift((1 << 64) - 1, 0, x[1:], 10)
+    assert np.all(got == (1 << 10) - 1)
+    # sign hash with a = 2^63: top bit = x & 1
+    assert np.array_equal(O.multiply_add_shift(1 << 63, 0, x, 1), x & 1)
+
+
+def test_hash_tables_encoding_matches_python_ints():
+    keys = draw_keys(3, 99)
+    t1, t2 = O.hash_tables(keys, 300, 200, 13)
+    for t in range(3):
+        (a1, c1), (a2, c2), (as1, cs1), (as2, cs2) = [(int(k[0]), int(k[1])) for k in keys[t]]
+        for i in (0, 1, 17, 299):
+            v = (a1 * i + c1) % (1 << 64)
+            sv = (as1 * i + cs1) % (1 << 64)
+            assert int(t1[t, i]) == (v >> 51) | ((sv >> 63) << 31)
+        for j in (0, 5, 199):
+            v = (a2 * j + c2) % (1 << 64)
+            sv = (as2 * j + cs2) % (1 << 64)
+            assert int(t2[t, j]) == (v >> 51) | ((sv >> 63) << 31)
+
+
+@pytest.mark.slow
+def test_hash_pairwise_collisions_theorem1():
+    # Theorem 1: h(i,j) = h1(i) xor h2(j) is 2-wise independent, so two
+    # distinct pairs collide with probability 1/b.  Estimate over key draws.
+    log2b, draws = 6, 4000
+    b = 1 << log2b
+    hits = np.zeros(3)
+    pairs = [((0, 0), (1, 0)), ((0, 0), (0, 1)), ((2, 3), (5, 7))]
+    for s in range(draws):
+        t1, t2 = O.hash_tables(draw_keys(1, 50_000 + s), 8, 8, log2b)
+        h1, h2 = O.bucket(t1[0]), O.bucket(t2[0])
+        for q, ((i, j), (k, l)) in enumerate(pairs):
+            hits[q] += (h1[i] ^ h2[j]) == (h1[k] ^ h2[l])
+    rate = hits / draws
+    # binomial sd at p=1/64, N=4000 is ~0.002; allow 4 sd
+    assert np.all(np.abs(rate - 1 / b) < 4 * np.sqrt((1 / b) * (1 - 1 / b) / draws)), rate
+
+
+def test_hash_uniformity_chi_square():
+    log2b = 8
+    t1, _ = O.hash_tables(draw_keys(1, 4242), 1 << 16, 1, log2b)
+    counts = np.bincount(O.bucket(t1[0]), minlength=1 << log2b)
+    expected = (1 << 16) / (1 << log2b)
+    chi2 = ((counts - expected) ** 2 / expected).sum()
+    assert chi2 < 255 + 6 * np.sqrt(2 * 255)   # mean dof, +6 sd
+    signs = O.sign(t1[0])
+    assert abs(signs.mean()) < 0.02
+
+
+# ------------------------------------------------------------------ transform
+def test_wht_golden_and_matrix():
+    g = _load("wht_h4.json")
+    assert O.wht(np.array(g["x"], float)).tolist() == g["Hx"]
+    assert O.wht_matrix(2).tolist() == g["H"]
+
+
+@pytest.mark.parametrize("m", [1, 3, 6, 9])
+def test_wht_matches_scipy_hadamard_and_definition(m):
+    b = 1 << m
+    H = scipy.linalg.hadamard(b).astype(float)     # Sylvester construction
+    assert np.array_equal(O.wht_matrix(m), H)
+    rng = np.random.default_rng(m)
+    x = rng.integers(-50, 50, size=(3, b)).astype(float)
+    assert np.array_equal(O.wht(x), x @ H.T)
+    # basis vector e_r -> row r of H (symmetric)
+    for r in (0, 1, b - 1, b // 3):
+        e = np.zeros(b); e[r] = 1
+        assert np.array_equal(O.wht(e), H[r])
+
+
+@pytest.mark.parametrize("m", [4, 10, 16])
+def test_wht_self_inverse_up_to_b(m):
+    rng = np.random.default_rng(100 + m)
+    x = rng.integers(-1000, 1000, size=(2, 1 << m)).astype(float)
+    assert np.array_equal(O.wht(O.wht(x)), (1 << m) * x)            # H H = b I (exact on integers)
+    assert np.array_equal(O.wht(O.wht(x), 2.0 ** -m), x)
+    y = rng.standard_normal(1 << m)
+    assert np.isclose(np.sum(O.wht(y) ** 2), (1 << m) * np.sum(y ** 2))   # Parseval
+
+
+def test_xor_convolution_golden_and_theorem():
+    g = _load("xor_conv_4.json")
+    x, y = np.array(g["x"], float), np.array(g["y"], float)
+    assert O.xor_convolution(x, y).tolist() == g["z"]
+    rng = np.random.default_rng(7)
+    for m in (1, 4, 7):
+        x = rng.integers(-9, 10, 1 << m).astype(float)
+        y = rng.integers(-9, 10, 1 << m).astype(float)
+        brute = np.array([sum(x[i] * y[i ^ k] for i in range(1 << m)) for k in range(1 << m)])
+        via_wht = O.wht(O.wht(x) * O.wht(y), 2.0 ** -m)
+        assert np.array_equal(via_wht, brute)
+        assert np.array_equal(O.xor_convolution(x, y), brute)
+
+
+# ------------------------------------------------------------------ sketching
+def test_count_sketch_against_dense_sketch_matrix():
+    rng = np.random.default_rng(3)
+    A = rng.integers(-5, 6, size=(40, 12)).astype(float)
+    B = rng.integers(-5, 6, size=(12, 30)).astype(float)
+    log2b = 5
+    t1, t2 = O.hash_tables(draw_keys(2, 77), 40, 30, log2b)
+    for t in range(2):
+        S1 = np.zeros((32, 40)); S1[O.bucket(t1[t]), np.arange(40)] = O.sign(t1[t])
+        S2 = np.zeros((32, 30)); S2[O.bucket(t2[t]), np.arange(30)] = O.sign(t2[t])
+        got_a = O.count_sketch(A, t1, 0, 3, 7, log2b)[t]      # [kc][b]
+        got_b = O.count_sketch(B, t2, 1, 3, 7, log2b)[t]
+        assert np.array_equal(got_a, (S1 @ A[:, 3:10]).T)
+        assert np.array_equal(got_b, (S2 @ B[3:10, :].T).T)
+
+
+def test_accumulate_is_sum_of_products():
+    rng = np.random.default_rng(4)
+    X = rng.integers(-9, 9, (2, 5, 8)).astype(float)
+    Y = rng.integers(-9, 9, (2, 5, 8)).astype(float)
+    want = np.einsum("tku,tku->tu", X, Y)
+    assert np.array_equal(O.accumulate(X, Y), want)
+
+
+# ------------------------------------------------------------------- compress
+def test_pipeline_golden_2x2():
+    g = _load("pipeline_2x2.json")
+    A, B = np.array(g["A"], float), np.array(g["B"], float)
+    for case in g["cases"]:
+        t1 = _tables(case["h1"], case["s1"], g["log2b"])
+        t2 = _tables(case["h2"], case["s2"], g["log2b"])
+        p_alg1 = O.compress_alg1(A, B, t1, t2, g["log2b"])
+        p_def = O.bucket_sums(O.product(A, B), t1, t2, g["log2b"])
+        assert p_alg1[0].tolist() == case["p"], case["name"]
+        assert p_def[0].tolist() == case["p"], case["name"]
+        assert O.extract(p_def, t1, t2, "median").tolist() == case["C_hat"]
+
+
+def test_alg1_route_equals_bucket_sums_integer_exact():
+    w = small_random(48, 40, 56, 7, 3, seed=11, integer=True)
+    t1, t2 = O.hash_tables(w.keys, 48, 56, 7)
+    p1 = O.compress_alg1(w.A, w.B, t1, t2, 7, k_chunk=16)
+    p2 = O.bucket_sums(O.product(w.A, w.B), t1, t2, 7)
+    assert np.array_equal(p1, p2)
+
+
+def test_alg1_route_equals_bucket_sums_real():
+    w = small_random(64, 50, 64, 9, 5, seed=12)
+    t1, t2 = O.hash_tables(w.keys, 64, 64, 9)
+    p1 = O.compress_alg1(w.A, w.B, t1, t2, 9)
+    C = O.product(w.A, w.B)
+    p2 = O.bucket_sums(C, t1, t2, 9)
+    assert np.max(np.abs(p1 - p2)) <= 1e-13 * np.linalg.norm(C) / 64 * 64
+
+
+def test_identity_hash_reduces_to_matmul():
+    # h1(i) = i * n, h2(j) = j, signs +1, b = n^2: h1 xor h2 = i n + j is
+    # injective, so p[i n + j] = C[i, j] and the estimate equals A B exactly.
+    n = 8
+    rng = np.random.default_rng(5)
+    A = rng.integers(-20, 20, (n, n)).astype(float)
+    B = rng.integers(-20, 20, (n, n)).astype(float)
+    log2b = 6
+    t1 = _tables(np.arange(n) * n, np.ones(n), log2b).repeat(3, 0)
+    t2 = _tables(np.arange(n), np.ones(n), log2b).repeat(3, 0)
+    brute = np.array([[sum(int(A[i, k]) * int(B[k, j]) for k in range(n)) for j in range(n)]
+                      for i in range(n)], dtype=float)
+    p = O.compress_alg1(A, B, t1, t2, log2b)
+    assert np.array_equal(p[0].reshape(n, n), brute)
+    assert np.array_equal(O.extract(p, t1, t2, "median"), brute)
+    assert np.array_equal(O.extract(p, t1, t2, "mean"), brute)
+
+
+def test_bucket_sums_brute_force_tiny():
+    rng = np.random.default_rng(6)
+    C = rng.integers(-9, 9, (5, 6)).astype(float)
+    t1, t2 = O.hash_tables(draw_keys(2, 31), 5, 6, 3)
+    p = O.bucket_sums(C, t1, t2, 3)
+    for t in range(2):
+        want = np.zeros(8)
+        for i in range(5):
+            for j in range(6):
+                x = (int(t1[t, i]) & 7) ^ (int(t2[t, j]) & 7)
+                s = (-1 if t1[t, i] >> 31 else 1) * (-1 if t2[t, j] >> 31 else 1)
+                want[x] += s * C[i, j]
+        assert np.array_equal(p[t], want)
+
+
+def test_exact_recovery_thm34_regime():
+    # b >= 8 nnz(C), d >= 6 log2 n: every entry recovered (Section 5.6).
+    n, nnz, log2b, d = 64, 8, 10, 37
+    rng = np.random.default_rng(8)
+    A, B, C_exact = hadamard_sparse(n, nnz, rng)
+    C_hat, p, t1, t2 = O.estimate(A, B, draw_keys(d, 123), log2b)
+    tol = 1e-12 * np.linalg.norm(C_exact) / n
+    assert np.max(np.abs(C_hat - C_exact)) <= tol
+
+
+def test_hadamard_workload_product_is_sparse():
+    w = exact_sparse_256(0)
+    C = O.product(w.A, w.B)
+    assert np.max(np.abs(C - w.C_exact)) < 1e-10
+    assert np.count_nonzero(w.C_exact) == 256
+
+
+def test_metamorphic_invariants():
+    w = small_random(32, 24, 40, 8, 5, seed=13, integer=True)
+    t1, t2 = O.hash_tables(w.keys, 32, 40, 8)
+    C = O.product(w.A, w.B)
+    p = O.bucket_sums(C, t1, t2, 8)
+    C_hat = O.extract(p, t1, t2, "median")
+    # transpose symmetry: (B^T, A^T) with the roles of the tables swapped gives C_hat^T
+    pT = O.bucket_sums(O.product(w.B.T, w.A.T), t2, t1, 8)
+    assert np.array_equal(O.extract(pT, t2, t1, "median"), C_hat.T)
+    # flipping every sign of s1 and of s2 leaves the estimate unchanged
+    f1, f2 = t1 ^ np.uint32(1 << 31), t2 ^ np.uint32(1 << 31)
+    assert np.array_equal(O.extract(O.bucket_sums(C, f1, f2, 8), f1, f2, "median"), C_hat)
+    # XOR-shifting both bucket hashes by the same delta leaves it unchanged
+    g1, g2 = t1 ^ np.uint32(0x5A), t2 ^ np.uint32(0x5A)
+    assert np.array_equal(O.extract(O.bucket_sums(C, g1, g2, 8), g1, g2, "median"), C_hat)
+    # the mean estimator is linear in A
+    A2 = w.A * 3 - 1
+    m1 = O.extract(O.bucket_sums(O.product(w.A, w.B), t1, t2, 8), t1, t2, "mean")
+    m2 = O.extract(O.bucket_sums(O.product(A2, w.B), t1, t2, 8), t1, t2, "mean")
+    m3 = O.extract(O.bucket_sums(O.product(w.A + A2, w.B), t1, t2, 8), t1, t2, "mean")
+    assert np.allclose(m1 + m2, m3, atol=1e-9)
+
+
+def test_median_matches_sorted_middle():
+    rng = np.random.default_rng(9)
+    p = rng.standard_normal((7, 64))
+    t1, t2 = O.hash_tables(draw_keys(7, 3), 10, 12, 6)
+    got = O.extract(p, t1, t2, "median")
+    x = O.gather_reps(p, t1, t2, np.arange(10), np.arange(12))
+    assert np.array_equal(got, np.sort(x, axis=0)[3])
+    with pytest.raises(ValueError):
+        O.extract(p[:6], t1[:6], t2[:6], "median")
+
+
+@pytest.mark.slow
+def test_unbiased_and_variance_bound():
+    # Section 3.1 / 5.3: with d = 1 the estimate is unbiased with variance
+    # at most ||C||_F^2 / b.  1000 independent hash draws at n = 32.
+    n, log2b, draws = 32, 6, 1000
+    rng = np.random.default_rng(10)
+    A = rng.standard_normal((n, n)); B = rng.standard_normal((n, n))
+    C = A @ B
+    i, j = 3, 5
+    ests = []
+    for s in range(draws):
+        t1, t2 = O.hash_tables(draw_keys(1, 10_000 + s), n, n, log2b)
+        p = O.bucket_sums(C, t1, t2, log2b)
+        ests.append(O.extract(p, t1, t2, "median", rows=[i], cols=[j])[0, 0])
+    ests = np.array(ests)
+    bound = np.sum(C ** 2) / (1 << log2b)
+    assert abs(ests.mean() - C[i, j]) < 4 * np.sqrt(bound / draws)
+    assert ests.var() <= 1.2 * bound
+
+
+# ------------------------------------------------------------------- gradient
+def test_gradient_closed_form_vs_finite_differences():
+    # L is bilinear in (A, B) for fixed hashes, so central differences are
+    # exact up to rounding.
+    n_r, n_i, n_c, log2b, d = 12, 10, 14, 6, 3
+    rng = np.random.default_rng(14)
+    A = rng.standard_normal((n_r, n_i)); B = rng.standard_normal((n_i, n_c))
+    W = rng.standard_normal((n_r, n_c))
+    t1, t2 = O.hash_tables(draw_keys(d, 555), n_r, n_c, log2b)
+
+    def loss(A_, B_):
+        p = O.bucket_sums(O.product(A_, B_), t1, t2, log2b)
+        return np.sum(W * O.extract(p, t1, t2, "mean"))
+
+    dA, dB, _ = O.grad_mean(A, B, W, t1, t2, log2b)
+    h = 1e-3
+    for (i, k) in [(0, 0), (3, 7), (11, 9), (5, 2)]:
+        Ap, Am = A.copy(), A.copy(); Ap[i, k] += h; Am[i, k] -= h
+        fd = (loss(Ap, B) - loss(Am, B)) / (2 * h)
+        assert abs(fd - dA[i, k]) <= 1e-9 * (1 + abs(fd))
+    for (k, j) in [(0, 0), (9, 13), (4, 6)]:
+        Bp, Bm = B.copy(), B.copy(); Bp[k, j] += h; Bm[k, j] -= h
+        fd = (loss(A, Bp) - loss(A, Bm)) / (2 * h)
+        assert abs(fd - dB[k, j]) <= 1e-9 * (1 + abs(fd))
+
+
+def test_gradient_brute_force_jacobian():
+    # dL/dC[i,j] computed by perturbing C directly (the estimator is linear in C).
+    n, log2b, d = 6, 4, 3
+    rng = np.random.default_rng(15)
+    W = rng.standard_normal((n, n))
+    t1, t2 = O.hash_tables(draw_keys(d, 777), n, n, log2b)
+    _, _, G = O.grad_mean(np.eye(n), np.eye(n), W, t1, t2, log2b)
+    for i in range(n):
+        for j in range(n):
+            E = np.zeros((n, n)); E[i, j] = 1.0
+            est = O.extract(O.bucket_sums(E, t1, t2, log2b), t1, t2, "mean")
+            assert np.isclose(np.sum(W * est), G[i, j], atol=1e-12)
