@@ -1,0 +1,173 @@
+/*
+ * cmm.h -- C ABI of the MI355X (gfx950) library for compressed matrix
+ * multiplication in the Fast Walsh-Hadamard Transform form (Pagh's
+ * Compress / Decompress with the FFT replaced by the FWHT; Andersson &
+ * Karppa, "Engineering Compressed Matrix Multiplication with the Fast
+ * Walsh-Hadamard Transform", Algorithm 1 and Section 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrix and vector pointers are DEVICE pointers owned by the caller.
+ *   The library keeps no pointer after a call returns and allocates no
+ *   device memory in any entry point; scratch memory comes from an explicit
+ *   workspace argument where one is needed.
+ * - `stream` is a hipStream_t passed as void*; NULL means the default
+ *   stream.  Every call only enqueues work on that stream and returns; the
+ *   results are valid once the stream has reached that point.
+ * - Dense matrices are row-major with a leading dimension (elements
+ *   between consecutive rows), ld >= number of columns.
+ * - Indices are 0-based.  h1/s1 hash the row index i of A, h2/s2 the column
+ *   index j of B (Section 3.1).
+ * - A hash TABLE entry is a uint32: bits [0, log2b) hold the bucket, bit 31
+ *   the sign (1 means -1); bits [log2b, 31) are ignored.  Hence
+ *   1 <= log2b <= 30.
+ * - The Walsh-Hadamard transform is unnormalised and in natural (Sylvester)
+ *   order, H[u][r] = (-1)^popcount(u & r), so H H = b I.  The inverse
+ *   transform of Compress is applied with the exact scale 2^-log2b; p is
+ *   then exactly the XOR convolution of eq. (fwhtxorconvolution).
+ * - Errors are returned as status codes; nothing is thrown or aborted across
+ *   the ABI.  Argument checks run on the host before anything is enqueued;
+ *   on CMM_EINVAL nothing was launched.  cmm_last_error() gives a message
+ *   for the last non-OK status returned on the calling host thread.
+ *   Sizes of zero are a no-op returning CMM_OK.
+ */
+#ifndef CMM_H
+#define CMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CMM_OK = 0,
+  CMM_EINVAL = 1,       /* an argument check failed; nothing was launched   */
+  CMM_ENOMEM = 2,       /* the workspace passed in is smaller than required */
+  CMM_EHIP = 3,         /* a HIP runtime call or a kernel launch failed     */
+  CMM_EUNSUPPORTED = 4  /* valid arguments, combination not implemented     */
+} cmm_status;
+
+typedef enum { CMM_F64 = 0, CMM_F32 = 1, CMM_BF16 = 2, CMM_F16 = 3 } cmm_dtype;
+
+/* Decompress: median over the d repetitions (Algorithm 1; needs odd d) or
+ * the mean over d (each repetition is unbiased, Section 3.1). */
+typedef enum { CMM_MEDIAN = 0, CMM_MEAN = 1 } cmm_estimator;
+
+/* ------------------------------------------------------------------ hash */
+/* Section 4.2 multiply-add-shift family, drawn once per repetition as in
+ * Algorithm 1: h(x) = floor(((a x + c) mod 2^64) / 2^(64 - log2b)) for the
+ * buckets, the same with one output bit for the signs.
+ *   keys  device uint64[d][4][2]: (a, c) for h1, h2, s1, s2 of repetition t.
+ *   tab1  device uint32[d][n_rows] out: entry of row i of A, repetition t.
+ *   tab2  device uint32[d][n_cols] out: entry of column j of B.
+ * n_rows, n_cols <= 2^32 (the family's domain).  Bit-exact. */
+cmm_status cmm_hash(const uint64_t* keys, int d, int64_t n_rows, int64_t n_cols, int log2b,
+                    uint32_t* tab1, uint32_t* tab2, void* stream);
+
+/* ---------------------------------------------------------------- sketch */
+/* Algorithm 1, the count-sketch loops of Compress, for kc consecutive values
+ * of the inner index starting at k0:
+ *   side 0 (M = A, rows x cols, ld):  out[t][kk][x] = sum over i with
+ *          bucket(tab[t][i]) = x of sign(tab[t][i]) * A[i][k0 + kk]
+ *          (tab is tab1, uint32[d][rows]);
+ *   side 1 (M = B, rows x cols, ld):  out[t][kk][x] = sum over j with
+ *          bucket(tab[t][j]) = x of sign(tab[t][j]) * B[k0 + kk][j]
+ *          (tab is tab2, uint32[d][cols]).
+ * dtype CMM_F64 or CMM_F32 (M and out have the same type); out is
+ * [d][kc][2^log2b], fully overwritten.  Terms are added in ascending index
+ * order, so results are deterministic. */
+cmm_status cmm_sketch(int side, const void* M, cmm_dtype dtype, int64_t rows, int64_t cols,
+                      int64_t ld, const uint32_t* tab, int d, int log2b, int64_t k0, int64_t kc,
+                      void* out, void* stream);
+
+/* ------------------------------------------------------------------ FWHT */
+/* Section 3.2: in-place Walsh-Hadamard transform of `batch` contiguous
+ * vectors of length 2^log2b (natural order, unnormalised butterflies), then
+ * x *= scale.  dtype CMM_F64 or CMM_F32.  scale must be a power of two
+ * (1.0 for the forward transform, 2^-log2b for the inverse of Compress) so
+ * that it is exact. */
+cmm_status cmm_fwht(void* x, cmm_dtype dtype, int64_t batch, int log2b, double scale,
+                    void* stream);
+
+/* ------------------------------------------------------------ accumulate */
+/* Algorithm 1, p[t] <- p[t] + H{p_A} o H{p_B}, over kc values of k:
+ *   p_hat[t][u] += sum_kk X[t][kk][u] * Y[t][kk][u]   (kk ascending,
+ *   product rounded, then added: no fused multiply-add).
+ * X, Y: [d][kc][2^log2b] of dtype CMM_F64 or CMM_F32; p_hat: float64
+ * [d][2^log2b], accumulated into (the caller zeroes it first). */
+cmm_status cmm_accumulate(const void* X, const void* Y, cmm_dtype dtype, int d, int64_t kc,
+                          int log2b, double* p_hat, void* stream);
+
+/* --------------------------------------------------------------- extract */
+/* Algorithm 1, Decompress, for the dense n_rows x n_cols block:
+ *   C_hat[i][j] = Median_t ( s1_t(i) s2_t(j) p[t][h1_t(i) xor h2_t(j)] )
+ * (or the mean over t).  p: float64 [d][2^log2b]; tables as above.
+ * out_dtype CMM_F64 or CMM_F32; C_hat row-major with leading dimension ldc.
+ * CMM_MEDIAN requires odd d.  The median is the exact middle value. */
+cmm_status cmm_extract(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                       int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
+                       void* C_hat, cmm_dtype out_dtype, int64_t ldc, void* stream);
+
+/* ------------------------------------------------------------- end to end */
+/* One compressed product C_hat ~ A B (Algorithm 1 Compress + dense
+ * Decompress).
+ *   A: n_rows x n_inner (lda), B: n_inner x n_cols (ldb), both of in_dtype.
+ *   compute: CMM_F64 -- sketches, transforms, accumulation in float64;
+ *            CMM_F32 -- sketches and transforms in float32, products summed
+ *                       in float32 per k-group, groups added in float64;
+ *            CMM_BF16 / CMM_F16 -- precision form: sketches rounded to
+ *                       bf16 / f16, transforms on the matrix cores (MFMA) with
+ *                       float32 accumulation, cross-k accumulation and the
+ *                       inverse transform in float64.
+ *   in_dtype: CMM_F64 or CMM_F32 (CMM_F64 required when compute = CMM_F64).
+ *   keys: device uint64[d][4][2] or NULL.  If non-NULL the tables are
+ *         computed from the keys into tab1 / tab2 (outputs).  If NULL,
+ *         tab1 / tab2 are read as given (explicit tables).
+ *   p:    device float64[d][2^log2b] out (the compressed product returned
+ *         by Compress), or NULL to keep it in the workspace only.
+ *   C_hat: device out_dtype (CMM_F64 / CMM_F32) n_rows x n_cols (ldc), or
+ *         NULL to run Compress only.
+ * Requires n_rows, n_cols <= 2^32 and the workspace size reported by
+ * cmm_workspace_size for the same problem. */
+typedef struct {
+  int64_t n_rows, n_inner, n_cols;
+  const void* A; int64_t lda;
+  const void* B; int64_t ldb;
+  cmm_dtype in_dtype;
+  cmm_dtype compute;
+  int d;
+  int log2b;
+  cmm_estimator estimator;
+  const uint64_t* keys;
+  uint32_t* tab1;
+  uint32_t* tab2;
+  double* p;
+  void* C_hat; cmm_dtype out_dtype; int64_t ldc;
+} cmm_problem;
+
+cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes);
+cmm_status cmm_estimate(const cmm_problem* prob, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/* ---------------------------------------------------------- kernel timing */
+/* Tracing for measurement: while enabled, every launch of the library is
+ * bracketed by two HIP events recorded on the caller's stream, and
+ * cmm_profile_query returns the summed elapsed time and the number of
+ * launches of one kernel ("hash", "transpose", "plan", "compress",
+ * "reduce", "fwht", "extract", "sketch", "accumulate") since the last
+ * cmm_profile_enable call.  Enabling or disabling discards the records.
+ * query waits for the recorded events.  Off by default. */
+void cmm_profile_enable(int on);
+cmm_status cmm_profile_query(const char* kernel, double* total_ms, int* launches);
+
+/* ---------------------------------------------------------------- status */
+const char* cmm_status_string(cmm_status s);
+const char* cmm_last_error(void);
+int cmm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CMM_H */

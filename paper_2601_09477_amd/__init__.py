@@ -1,0 +1,262 @@
+"""MI355X (gfx950) compressed matrix multiplication in the FWHT form.
+
+A thin ctypes binding over ``libcmm.so`` (the HIP library declared in
+``include/cmm.h``).  The functions named ``cmm_*`` take torch tensors that
+live on the GPU and marshal their device pointers and the current HIP
+stream into the C ABI of the same name; every step runs in the library's
+kernels.  ``estimate`` is the end-to-end convenience wrapper (it allocates
+outputs and the workspace with torch).
+
+The library must be built (``python -m paper_2601_09477_amd.build`` or
+``__graft_entry__.build()``); importing works without it, but any call
+raises ``CmmError`` when ``libcmm.so`` is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcmm.so")
+
+CMM_OK, CMM_EINVAL, CMM_ENOMEM, CMM_EHIP, CMM_EUNSUPPORTED = range(5)
+CMM_F64, CMM_F32, CMM_BF16, CMM_F16 = range(4)
+CMM_MEDIAN, CMM_MEAN = range(2)
+
+EXPORTED = ["cmm_hash", "cmm_sketch", "cmm_fwht", "cmm_accumulate", "cmm_extract",
+            "cmm_workspace_size", "cmm_estimate", "cmm_status_string", "cmm_last_error",
+            "cmm_abi_version", "cmm_profile_enable", "cmm_profile_query"]
+
+
+class CmmError(RuntimeError):
+    """A non-OK status returned by libcmm (or the library is missing)."""
+
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn}: {_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_STATUS_NAMES = {0: "CMM_OK", 1: "CMM_EINVAL", 2: "CMM_ENOMEM", 3: "CMM_EHIP",
+                 4: "CMM_EUNSUPPORTED"}
+
+
+class Problem(ctypes.Structure):
+    """Mirror of ``cmm_problem`` in include/cmm.h."""
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_inner", ctypes.c_int64),
+                ("n_cols", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("in_dtype", ctypes.c_int), ("compute", ctypes.c_int),
+                ("d", ctypes.c_int), ("log2b", ctypes.c_int), ("estimator", ctypes.c_int),
+                ("keys", ctypes.c_void_p), ("tab1", ctypes.c_void_p), ("tab2", ctypes.c_void_p),
+                ("p", ctypes.c_void_p),
+                ("C_hat", ctypes.c_void_p), ("out_dtype", ctypes.c_int), ("ldc", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcmm.so (once) and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise CmmError("load", CMM_EUNSUPPORTED,
+                       f"{LIB_PATH} is not built; run python -m paper_2601_09477_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    sig = {
+        "cmm_hash": [vp, i32, i64, i64, i32, vp, vp, vp],
+        "cmm_sketch": [i32, vp, i32, i64, i64, i64, vp, i32, i32, i64, i64, vp, vp],
+        "cmm_fwht": [vp, i32, i64, i32, dbl, vp],
+        "cmm_accumulate": [vp, vp, i32, i32, i64, i32, vp, vp],
+        "cmm_extract": [vp, vp, vp, i32, i64, i64, i32, i32, vp, i32, i64, vp],
+        "cmm_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
+        "cmm_estimate": [ctypes.POINTER(Problem), vp, ctypes.c_size_t, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.cmm_status_string.argtypes = [ctypes.c_int]
+    L.cmm_status_string.restype = ctypes.c_char_p
+    L.cmm_last_error.argtypes = []
+    L.cmm_last_error.restype = ctypes.c_char_p
+    L.cmm_abi_version.argtypes = []
+    L.cmm_abi_version.restype = ctypes.c_int
+    L.cmm_profile_enable.argtypes = [ctypes.c_int]
+    L.cmm_profile_enable.restype = None
+    L.cmm_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int)]
+    L.cmm_profile_query.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(fn: str, status: int) -> None:
+    if status != CMM_OK:
+        raise CmmError(fn, status, lib().cmm_last_error().decode())
+
+
+# ------------------------------------------------------------ marshalling
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return CMM_F64
+    if t.dtype == torch.float32:
+        return CMM_F32
+    raise CmmError("dtype", CMM_EINVAL, f"unsupported tensor dtype {t.dtype}")
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise CmmError("marshal", CMM_EINVAL, "tensors must live on the GPU")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+# -------------------------------------------------------- C-ABI wrappers
+def cmm_hash(keys, d, n_rows, n_cols, log2b, tab1, tab2, stream=None) -> None:
+    """keys int64[d][4][2] (uint64 bits), tab1 int32[d][n_rows], tab2 int32[d][n_cols]."""
+    _check("cmm_hash", lib().cmm_hash(_ptr(keys), d, n_rows, n_cols, log2b, _ptr(tab1),
+                                      _ptr(tab2), _stream(stream)))
+
+
+def cmm_sketch(side, M, rows, cols, ld, tab, d, log2b, k0, kc, out, stream=None) -> None:
+    _check("cmm_sketch", lib().cmm_sketch(side, _ptr(M), _dtype_code(M), rows, cols, ld,
+                                          _ptr(tab), d, log2b, k0, kc, _ptr(out),
+                                          _stream(stream)))
+
+
+def cmm_fwht(x, batch, log2b, scale=1.0, stream=None) -> None:
+    _check("cmm_fwht", lib().cmm_fwht(_ptr(x), _dtype_code(x), batch, log2b, float(scale),
+                                      _stream(stream)))
+
+
+def cmm_accumulate(X, Y, d, kc, log2b, p_hat, stream=None) -> None:
+    _check("cmm_accumulate", lib().cmm_accumulate(_ptr(X), _ptr(Y), _dtype_code(X), d, kc,
+                                                  log2b, _ptr(p_hat), _stream(stream)))
+
+
+def cmm_extract(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat, ldc=None,
+                stream=None) -> None:
+    ldc = n_cols if ldc is None else ldc
+    _check("cmm_extract", lib().cmm_extract(_ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols,
+                                            log2b, estimator, _ptr(C_hat), _dtype_code(C_hat),
+                                            ldc, _stream(stream)))
+
+
+def cmm_workspace_size(prob: Problem) -> int:
+    n = ctypes.c_size_t(0)
+    _check("cmm_workspace_size", lib().cmm_workspace_size(ctypes.byref(prob), ctypes.byref(n)))
+    return n.value
+
+
+def cmm_estimate(prob: Problem, workspace, workspace_bytes: int, stream=None) -> None:
+    _check("cmm_estimate", lib().cmm_estimate(ctypes.byref(prob), _ptr(workspace),
+                                              workspace_bytes, _stream(stream)))
+
+
+def cmm_profile_enable(on: bool = True) -> None:
+    lib().cmm_profile_enable(1 if on else 0)
+
+
+def cmm_profile_query(kernel: str):
+    """(total milliseconds, launches) of one kernel since profiling was enabled."""
+    ms, n = ctypes.c_double(0.0), ctypes.c_int(0)
+    _check("cmm_profile_query", lib().cmm_profile_query(kernel.encode(), ctypes.byref(ms),
+                                                        ctypes.byref(n)))
+    return ms.value, n.value
+
+
+# ------------------------------------------------------------ high level
+_COMPUTE = {"f64": CMM_F64, "f32": CMM_F32, "bf16": CMM_BF16, "f16": CMM_F16}
+
+
+def keys_tensor(keys: np.ndarray, device="cuda"):
+    """uint64[d][4][2] hash keys -> int64 device tensor with the same bits."""
+    torch = _torch()
+    k = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64)).view(np.int64)
+    return torch.from_numpy(k.copy()).to(device)
+
+
+def make_problem(A, B, d, log2b, *, keys=None, tab1=None, tab2=None, p=None, C_hat=None,
+                 compute="f64", estimator="median") -> Problem:
+    pr = Problem()
+    pr.n_rows, pr.n_inner = A.shape
+    pr.n_cols = B.shape[1]
+    pr.A, pr.lda = _ptr(A), A.stride(0)
+    pr.B, pr.ldb = _ptr(B), B.stride(0)
+    pr.in_dtype = _dtype_code(A)
+    pr.compute = _COMPUTE[compute]
+    pr.d, pr.log2b = d, log2b
+    pr.estimator = CMM_MEDIAN if estimator == "median" else CMM_MEAN
+    pr.keys = _ptr(keys)
+    pr.tab1, pr.tab2 = _ptr(tab1), _ptr(tab2)
+    pr.p = _ptr(p)
+    if C_hat is not None:
+        pr.C_hat, pr.out_dtype, pr.ldc = _ptr(C_hat), _dtype_code(C_hat), C_hat.stride(0)
+    return pr
+
+
+class Estimate:
+    """Result of ``estimate``: C_hat, the sketch p and the hash tables."""
+
+    def __init__(self, C_hat, p, tab1, tab2):
+        self.C_hat, self.p, self.tab1, self.tab2 = C_hat, p, tab1, tab2
+
+
+def estimate(A, B, d: int, log2b: int, *, keys=None, tab1=None, tab2=None,
+             compute: str = "f64", estimator: str = "median", out_dtype=None,
+             dense: bool = True, workspace=None, stream=None) -> Estimate:
+    """Compressed product of A (n_rows x n_inner) and B (n_inner x n_cols).
+
+    Give either ``keys`` (uint64[d][4][2], numpy or an int64 device tensor)
+    or explicit tables ``tab1`` / ``tab2`` (int32 device tensors)."""
+    torch = _torch()
+    dev = A.device
+    n_rows, n_cols = A.shape[0], B.shape[1]
+    if keys is not None and not hasattr(keys, "data_ptr"):
+        keys = keys_tensor(keys, dev)
+    if keys is not None:
+        tab1 = torch.empty((d, n_rows), dtype=torch.int32, device=dev)
+        tab2 = torch.empty((d, n_cols), dtype=torch.int32, device=dev)
+    p = torch.empty((d, 1 << log2b), dtype=torch.float64, device=dev)
+    C_hat = None
+    if dense:
+        C_hat = torch.empty((n_rows, n_cols), dtype=out_dtype or A.dtype, device=dev)
+    pr = make_problem(A, B, d, log2b, keys=keys, tab1=tab1, tab2=tab2, p=p, C_hat=C_hat,
+                      compute=compute, estimator=estimator)
+    nbytes = cmm_workspace_size(pr)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    cmm_estimate(pr, workspace, nbytes, stream)
+    return Estimate(C_hat, p, tab1, tab2)
+
+
+def tables_to_numpy(tab) -> np.ndarray:
+    """int32 device table -> uint32 numpy array with the same bits."""
+    return tab.cpu().numpy().view(np.uint32)
+
+
+def effective_rate(n_rows: int, n_inner: int, n_cols: int, seconds: float) -> float:
+    """2 n_rows n_inner n_cols / seconds (DGEMM-equivalent flop rate)."""
+    return 2.0 * n_rows * n_inner * n_cols / seconds if seconds > 0 else math.inf

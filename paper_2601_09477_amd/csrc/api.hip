@@ -1,0 +1,427 @@
+// C-ABI entry points of libcmm: argument checks on the host, then launches.
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "cmm_internal.h"
+
+namespace cmm {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+cmm_status invalid(const std::string& msg) {
+  set_error(msg);
+  return CMM_EINVAL;
+}
+
+cmm_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return CMM_OK;
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return CMM_EHIP;
+}
+
+// ------------------------------------------------------------ kernel timing
+namespace {
+std::atomic<int> g_prof_on{0};
+std::mutex g_prof_mu;
+std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> g_prof;
+
+void prof_clear_locked() {
+  for (auto& kv : g_prof)
+    for (auto& ev : kv.second) {
+      hipEventDestroy(ev.first);
+      hipEventDestroy(ev.second);
+    }
+  g_prof.clear();
+}
+}  // namespace
+
+ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), stream_(s) {
+  if (!g_prof_on.load(std::memory_order_relaxed)) return;
+  if (hipEventCreate(&start_) != hipSuccess) { start_ = nullptr; return; }
+  hipEventRecord(start_, stream_);
+}
+
+ProfScope::~ProfScope() {
+  if (!start_) return;
+  hipEvent_t stop = nullptr;
+  if (hipEventCreate(&stop) != hipSuccess) { hipEventDestroy(start_); return; }
+  hipEventRecord(stop, stream_);
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof[name_].emplace_back(start_, stop);
+}
+
+namespace {
+
+constexpr int kMaxLog2b = 30;
+constexpr size_t kLdsBytes = 160 * 1024;
+constexpr int64_t kMaxHashDomain = (int64_t)1 << 32;
+
+bool is_f64_or_f32(cmm_dtype t) { return t == CMM_F64 || t == CMM_F32; }
+
+cmm_status check_log2b(int log2b, const char* fn) {
+  if (log2b < 1 || log2b > kMaxLog2b)
+    return invalid(std::string(fn) + ": log2b must be in [1, 30]");
+  return CMM_OK;
+}
+
+cmm_status check_d(int d, const char* fn) {
+  if (d < 1 || d > 65535) return invalid(std::string(fn) + ": d must be in [1, 65535]");
+  return CMM_OK;
+}
+
+// ------------------------------------------------------------ estimate plan
+// Everything cmm_estimate needs besides the caller's buffers, laid out in
+// the workspace in this order.
+struct EstimatePlan {
+  bool fused = false;
+  int lb = 0;          // log2 b_lo of the fused kernel
+  int groups = 1;      // k-ranges of the fused kernel
+  int64_t kc = 0;      // k-chunk of the composed path
+  cmm_dtype cdt = CMM_F64;
+  size_t off_at = 0, off_bc = 0, off_planA = 0, off_planB = 0, off_part = 0, off_p = 0;
+  size_t off_x = 0, off_y = 0;
+  size_t bytes = 0;
+};
+
+cmm_status validate_problem(const cmm_problem* pr, const char* fn) {
+  if (!pr) return invalid(std::string(fn) + ": null problem");
+  if (pr->n_rows < 0 || pr->n_inner < 0 || pr->n_cols < 0)
+    return invalid(std::string(fn) + ": negative dimension");
+  if (pr->n_rows > kMaxHashDomain || pr->n_cols > kMaxHashDomain)
+    return invalid(std::string(fn) + ": n_rows and n_cols must be <= 2^32 (hash domain)");
+  cmm_status s = check_log2b(pr->log2b, fn);
+  if (s != CMM_OK) return s;
+  if ((s = check_d(pr->d, fn)) != CMM_OK) return s;
+  if (pr->estimator != CMM_MEDIAN && pr->estimator != CMM_MEAN)
+    return invalid(std::string(fn) + ": unknown estimator");
+  if (pr->estimator == CMM_MEDIAN && (pr->d % 2) == 0)
+    return invalid(std::string(fn) + ": the median estimator needs an odd d");
+  if (!is_f64_or_f32(pr->in_dtype))
+    return invalid(std::string(fn) + ": in_dtype must be CMM_F64 or CMM_F32");
+  if (pr->compute == CMM_F64 && pr->in_dtype != CMM_F64)
+    return invalid(std::string(fn) + ": compute CMM_F64 needs in_dtype CMM_F64");
+  if (pr->compute != CMM_F64 && pr->compute != CMM_F32 && pr->compute != CMM_BF16 &&
+      pr->compute != CMM_F16)
+    return invalid(std::string(fn) + ": unknown compute type");
+  if (pr->lda < pr->n_inner || pr->ldb < pr->n_cols)
+    return invalid(std::string(fn) + ": leading dimension smaller than the row length");
+  if (pr->n_rows > 0 && pr->n_inner > 0 && !pr->A) return invalid(std::string(fn) + ": A is null");
+  if (pr->n_inner > 0 && pr->n_cols > 0 && !pr->B) return invalid(std::string(fn) + ": B is null");
+  if ((pr->n_rows > 0 && !pr->tab1) || (pr->n_cols > 0 && !pr->tab2))
+    return invalid(std::string(fn) + ": tab1 / tab2 must be given (outputs when keys != NULL)");
+  if (pr->C_hat) {
+    if (!is_f64_or_f32(pr->out_dtype))
+      return invalid(std::string(fn) + ": out_dtype must be CMM_F64 or CMM_F32");
+    if (pr->ldc < pr->n_cols) return invalid(std::string(fn) + ": ldc < n_cols");
+  }
+  return CMM_OK;
+}
+
+EstimatePlan make_plan(const cmm_problem* pr) {
+  EstimatePlan P;
+  P.cdt = pr->compute == CMM_F64 ? CMM_F64 : CMM_F32;
+  const size_t es = dtype_size(P.cdt);
+  const int64_t b = (int64_t)1 << pr->log2b;
+  const int d = pr->d;
+  // fused path: b_lo = 2^lb with 11 <= lb <= log2b; LDS holds the transpose
+  // buffer and one staged row of each operand.
+  const int lb_max = P.cdt == CMM_F64 ? 13 : 14;
+  int lb = pr->log2b < lb_max ? pr->log2b : lb_max;
+  while (lb >= 11 && (((size_t)1 << lb) + (size_t)pr->n_rows + (size_t)pr->n_cols) * es > kLdsBytes)
+    --lb;
+  P.fused = lb >= 11 && pr->n_rows <= 65535 && pr->n_cols <= 65535 && pr->n_rows > 0 &&
+            pr->n_cols > 0 && pr->n_inner > 0;
+  size_t off = 0;
+  if (P.fused) {
+    P.lb = lb;
+    const int64_t units = (int64_t)d << (pr->log2b - lb);
+    // aim at >= 8 work-groups per CU over the 256 CUs, whole multiple of 8
+    int64_t g = (2048 + units - 1) / units;
+    if (g > pr->n_inner) g = pr->n_inner;
+    if (g < 1) g = 1;
+    while (g > 1 && ((units * g) & 7) != 0 && g < pr->n_inner) ++g;
+    P.groups = (int)g;
+    P.off_at = off; off = align_up(off + es * (size_t)pr->n_rows * pr->n_inner, 256);
+    if (P.cdt != pr->in_dtype) {
+      P.off_bc = off; off = align_up(off + es * (size_t)pr->n_inner * pr->n_cols, 256);
+    }
+    P.off_planA = off; off = align_up(off + plan_bytes(d, pr->n_rows, lb), 256);
+    P.off_planB = off; off = align_up(off + plan_bytes(d, pr->n_cols, lb), 256);
+    P.off_part = off; off = align_up(off + sizeof(double) * (size_t)P.groups * d * b, 256);
+  } else {
+    // composed path: standalone sketch / transform / accumulate over k-chunks
+    const size_t budget = (size_t)1 << 29;   // 512 MB for the two chunk buffers
+    int64_t kc = (int64_t)(budget / (2 * es * (size_t)d * b));
+    if (kc < 1) kc = 1;
+    if (kc > pr->n_inner) kc = pr->n_inner;
+    P.kc = kc < 1 ? 1 : kc;
+    if (P.cdt != pr->in_dtype) {
+      P.off_at = off; off = align_up(off + es * (size_t)pr->n_rows * pr->n_inner, 256);
+      P.off_bc = off; off = align_up(off + es * (size_t)pr->n_inner * pr->n_cols, 256);
+    }
+    P.off_x = off; off = align_up(off + es * (size_t)d * P.kc * b, 256);
+    P.off_y = off; off = align_up(off + es * (size_t)d * P.kc * b, 256);
+    P.off_part = off; off = align_up(off + sizeof(double) * (size_t)d * b, 256);
+  }
+  P.off_p = off; off = align_up(off + sizeof(double) * (size_t)d * b, 256);
+  P.bytes = off;
+  return P;
+}
+
+cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
+  const EstimatePlan P = make_plan(pr);
+  const int d = pr->d;
+  const int64_t b = (int64_t)1 << pr->log2b;
+  cmm_status st;
+  if (pr->keys) {
+    st = launch_hash(pr->keys, d, pr->n_rows, pr->n_cols, pr->log2b, pr->tab1, pr->tab2, s);
+    if (st != CMM_OK) return st;
+  }
+  double* p = pr->p ? pr->p : reinterpret_cast<double*>(ws + P.off_p);
+  if (pr->n_inner == 0 || pr->n_rows == 0 || pr->n_cols == 0) {
+    if ((st = launch_zero(p, (size_t)d * b, s)) != CMM_OK) return st;
+  } else if (P.fused) {
+    void* At = ws + P.off_at;
+    st = launch_transpose(pr->A, pr->in_dtype, pr->n_rows, pr->n_inner, pr->lda, At, P.cdt, s);
+    if (st != CMM_OK) return st;
+    const void* Bc = pr->B;
+    int64_t ldb = pr->ldb;
+    if (P.cdt != pr->in_dtype) {
+      Bc = ws + P.off_bc;
+      ldb = pr->n_cols;
+      st = launch_convert(pr->B, pr->in_dtype, pr->n_inner, pr->n_cols, pr->ldb,
+                          const_cast<void*>(Bc), P.cdt, s);
+      if (st != CMM_OK) return st;
+    }
+    CompressArgs a;
+    a.At = At;
+    a.B = Bc;
+    a.ldb = ldb;
+    a.n_rows = pr->n_rows;
+    a.n_cols = pr->n_cols;
+    a.n_inner = pr->n_inner;
+    a.tab1 = pr->tab1;
+    a.tab2 = pr->tab2;
+    a.planA = carve_plan(ws + P.off_planA, d, pr->n_rows, P.lb);
+    a.planB = carve_plan(ws + P.off_planB, d, pr->n_cols, P.lb);
+    a.d = d;
+    a.log2b = pr->log2b;
+    a.groups = P.groups;
+    a.partial = reinterpret_cast<double*>(ws + P.off_part);
+    if ((st = launch_plan(pr->tab1, d, pr->n_rows, P.lb, a.planA, s)) != CMM_OK) return st;
+    if ((st = launch_plan(pr->tab2, d, pr->n_cols, P.lb, a.planB, s)) != CMM_OK) return st;
+    if ((st = launch_compress(a, P.cdt, P.lb, s)) != CMM_OK) return st;
+    if ((st = launch_reduce_partials(a.partial, P.groups, (size_t)d * b, p, s)) != CMM_OK) return st;
+  } else {
+    const void* A = pr->A;
+    const void* B = pr->B;
+    int64_t lda = pr->lda, ldb = pr->ldb;
+    if (P.cdt != pr->in_dtype) {
+      void* Ac = ws + P.off_at;
+      void* Bc = ws + P.off_bc;
+      st = launch_convert(pr->A, pr->in_dtype, pr->n_rows, pr->n_inner, pr->lda, Ac, P.cdt, s);
+      if (st != CMM_OK) return st;
+      st = launch_convert(pr->B, pr->in_dtype, pr->n_inner, pr->n_cols, pr->ldb, Bc, P.cdt, s);
+      if (st != CMM_OK) return st;
+      A = Ac; B = Bc; lda = pr->n_inner; ldb = pr->n_cols;
+    }
+    double* p_hat = reinterpret_cast<double*>(ws + P.off_part);
+    void* X = ws + P.off_x;
+    void* Y = ws + P.off_y;
+    if ((st = launch_zero(p_hat, (size_t)d * b, s)) != CMM_OK) return st;
+    for (int64_t k0 = 0; k0 < pr->n_inner; k0 += P.kc) {
+      const int64_t kc = (pr->n_inner - k0) < P.kc ? (pr->n_inner - k0) : P.kc;
+      if ((st = launch_sketch(0, A, P.cdt, pr->n_rows, pr->n_inner, lda, pr->tab1, d,
+                              pr->log2b, k0, kc, X, s)) != CMM_OK) return st;
+      if ((st = launch_sketch(1, B, P.cdt, pr->n_inner, pr->n_cols, ldb, pr->tab2, d,
+                              pr->log2b, k0, kc, Y, s)) != CMM_OK) return st;
+      if ((st = launch_fwht(X, P.cdt, (int64_t)d * kc, pr->log2b, 1.0, s)) != CMM_OK) return st;
+      if ((st = launch_fwht(Y, P.cdt, (int64_t)d * kc, pr->log2b, 1.0, s)) != CMM_OK) return st;
+      if ((st = launch_accumulate(X, Y, P.cdt, d, kc, pr->log2b, p_hat, s)) != CMM_OK) return st;
+    }
+    if ((st = launch_reduce_partials(p_hat, 1, (size_t)d * b, p, s)) != CMM_OK) return st;
+  }
+  if (pr->n_inner > 0 && pr->n_rows > 0 && pr->n_cols > 0) {
+    st = launch_fwht(p, CMM_F64, d, pr->log2b, std::ldexp(1.0, -pr->log2b), s);
+    if (st != CMM_OK) return st;
+  }
+  if (pr->C_hat && pr->n_rows > 0 && pr->n_cols > 0)
+    return launch_extract(p, pr->tab1, pr->tab2, d, pr->n_rows, pr->n_cols, pr->log2b,
+                          pr->estimator, pr->C_hat, pr->out_dtype, pr->ldc, s);
+  return CMM_OK;
+}
+
+}  // namespace
+}  // namespace cmm
+
+using namespace cmm;
+
+extern "C" {
+
+int cmm_abi_version(void) { return 1; }
+
+void cmm_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  prof_clear_locked();
+  g_prof_on.store(on ? 1 : 0);
+}
+
+cmm_status cmm_profile_query(const char* kernel, double* total_ms, int* launches) {
+  if (!kernel || !total_ms || !launches) return invalid("cmm_profile_query: null pointer");
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  *total_ms = 0.0;
+  *launches = 0;
+  auto it = g_prof.find(kernel);
+  if (it == g_prof.end()) return CMM_OK;
+  for (auto& ev : it->second) {
+    cmm_status s = hip_check(hipEventSynchronize(ev.second), "cmm_profile_query");
+    if (s != CMM_OK) return s;
+    float ms = 0.f;
+    if ((s = hip_check(hipEventElapsedTime(&ms, ev.first, ev.second), "cmm_profile_query")) != CMM_OK)
+      return s;
+    *total_ms += ms;
+    *launches += 1;
+  }
+  return CMM_OK;
+}
+
+const char* cmm_status_string(cmm_status s) {
+  switch (s) {
+    case CMM_OK: return "CMM_OK";
+    case CMM_EINVAL: return "CMM_EINVAL";
+    case CMM_ENOMEM: return "CMM_ENOMEM";
+    case CMM_EHIP: return "CMM_EHIP";
+    case CMM_EUNSUPPORTED: return "CMM_EUNSUPPORTED";
+  }
+  return "unknown status";
+}
+
+const char* cmm_last_error(void) { return g_last_error.c_str(); }
+
+cmm_status cmm_hash(const uint64_t* keys, int d, int64_t n_rows, int64_t n_cols, int log2b,
+                    uint32_t* tab1, uint32_t* tab2, void* stream) {
+  cmm_status s;
+  if ((s = check_d(d, "cmm_hash")) != CMM_OK) return s;
+  if ((s = check_log2b(log2b, "cmm_hash")) != CMM_OK) return s;
+  if (n_rows < 0 || n_cols < 0) return invalid("cmm_hash: negative size");
+  if (n_rows > kMaxHashDomain || n_cols > kMaxHashDomain)
+    return invalid("cmm_hash: sizes must be <= 2^32 (hash domain)");
+  if (n_rows == 0 && n_cols == 0) return CMM_OK;
+  if (!keys) return invalid("cmm_hash: keys is null");
+  if ((n_rows > 0 && !tab1) || (n_cols > 0 && !tab2)) return invalid("cmm_hash: table is null");
+  return launch_hash(keys, d, n_rows, n_cols, log2b, tab1, tab2, as_stream(stream));
+}
+
+cmm_status cmm_sketch(int side, const void* M, cmm_dtype dtype, int64_t rows, int64_t cols,
+                      int64_t ld, const uint32_t* tab, int d, int log2b, int64_t k0, int64_t kc,
+                      void* out, void* stream) {
+  cmm_status s;
+  if (side != 0 && side != 1) return invalid("cmm_sketch: side must be 0 (A) or 1 (B)");
+  if (!is_f64_or_f32(dtype)) return invalid("cmm_sketch: dtype must be CMM_F64 or CMM_F32");
+  if ((s = check_d(d, "cmm_sketch")) != CMM_OK) return s;
+  if ((s = check_log2b(log2b, "cmm_sketch")) != CMM_OK) return s;
+  if (rows < 0 || cols < 0 || k0 < 0 || kc < 0) return invalid("cmm_sketch: negative size");
+  if (ld < cols) return invalid("cmm_sketch: ld < cols");
+  const int64_t n_inner = side == 0 ? cols : rows;
+  if (k0 + kc > n_inner) return invalid("cmm_sketch: k0 + kc exceeds the inner dimension");
+  if (kc == 0) return CMM_OK;
+  if (!out || !tab || (rows > 0 && cols > 0 && !M)) return invalid("cmm_sketch: null pointer");
+  return launch_sketch(side, M, dtype, rows, cols, ld, tab, d, log2b, k0, kc, out,
+                       as_stream(stream));
+}
+
+cmm_status cmm_fwht(void* x, cmm_dtype dtype, int64_t batch, int log2b, double scale,
+                    void* stream) {
+  cmm_status s;
+  if (!is_f64_or_f32(dtype)) return invalid("cmm_fwht: dtype must be CMM_F64 or CMM_F32");
+  if ((s = check_log2b(log2b, "cmm_fwht")) != CMM_OK) return s;
+  if (batch < 0) return invalid("cmm_fwht: negative batch");
+  int ex = 0;
+  const double m = std::frexp(scale, &ex);
+  if (!(scale > 0) || m != 0.5) return invalid("cmm_fwht: scale must be a positive power of two");
+  if (batch == 0) return CMM_OK;
+  if (!x) return invalid("cmm_fwht: x is null");
+  return launch_fwht(x, dtype, batch, log2b, scale, as_stream(stream));
+}
+
+cmm_status cmm_accumulate(const void* X, const void* Y, cmm_dtype dtype, int d, int64_t kc,
+                          int log2b, double* p_hat, void* stream) {
+  cmm_status s;
+  if (!is_f64_or_f32(dtype)) return invalid("cmm_accumulate: dtype must be CMM_F64 or CMM_F32");
+  if ((s = check_d(d, "cmm_accumulate")) != CMM_OK) return s;
+  if ((s = check_log2b(log2b, "cmm_accumulate")) != CMM_OK) return s;
+  if (kc < 0) return invalid("cmm_accumulate: negative kc");
+  if (kc == 0) return CMM_OK;
+  if (!X || !Y || !p_hat) return invalid("cmm_accumulate: null pointer");
+  return launch_accumulate(X, Y, dtype, d, kc, log2b, p_hat, as_stream(stream));
+}
+
+cmm_status cmm_extract(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                       int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
+                       void* C_hat, cmm_dtype out_dtype, int64_t ldc, void* stream) {
+  cmm_status s;
+  if ((s = check_d(d, "cmm_extract")) != CMM_OK) return s;
+  if ((s = check_log2b(log2b, "cmm_extract")) != CMM_OK) return s;
+  if (estimator != CMM_MEDIAN && estimator != CMM_MEAN)
+    return invalid("cmm_extract: unknown estimator");
+  if (estimator == CMM_MEDIAN && d % 2 == 0)
+    return invalid("cmm_extract: the median estimator needs an odd d");
+  if (d > 63 && estimator == CMM_MEDIAN) {
+    set_error("cmm_extract: median over more than 63 repetitions is not implemented");
+    return CMM_EUNSUPPORTED;
+  }
+  if (!is_f64_or_f32(out_dtype)) return invalid("cmm_extract: out_dtype must be CMM_F64 or CMM_F32");
+  if (n_rows < 0 || n_cols < 0) return invalid("cmm_extract: negative size");
+  if (n_rows > kMaxHashDomain || n_cols > kMaxHashDomain)
+    return invalid("cmm_extract: sizes must be <= 2^32");
+  if (ldc < n_cols) return invalid("cmm_extract: ldc < n_cols");
+  if (n_rows == 0 || n_cols == 0) return CMM_OK;
+  if (!p || !tab1 || !tab2 || !C_hat) return invalid("cmm_extract: null pointer");
+  return launch_extract(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat, out_dtype,
+                        ldc, as_stream(stream));
+}
+
+cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes) {
+  cmm_status s = validate_problem(prob, "cmm_workspace_size");
+  if (s != CMM_OK) return s;
+  if (!bytes) return invalid("cmm_workspace_size: bytes is null");
+  if (prob->compute == CMM_BF16 || prob->compute == CMM_F16) {
+    set_error("cmm_workspace_size: the bf16/f16 precision form is not built yet");
+    return CMM_EUNSUPPORTED;
+  }
+  *bytes = make_plan(prob).bytes;
+  return CMM_OK;
+}
+
+cmm_status cmm_estimate(const cmm_problem* prob, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+  cmm_status s = validate_problem(prob, "cmm_estimate");
+  if (s != CMM_OK) return s;
+  if (prob->compute == CMM_BF16 || prob->compute == CMM_F16) {
+    set_error("cmm_estimate: the bf16/f16 precision form is not built yet");
+    return CMM_EUNSUPPORTED;
+  }
+  if (prob->d > 63 && prob->estimator == CMM_MEDIAN && prob->C_hat) {
+    set_error("cmm_estimate: median over more than 63 repetitions is not implemented");
+    return CMM_EUNSUPPORTED;
+  }
+  const EstimatePlan P = make_plan(prob);
+  if (workspace_bytes < P.bytes) {
+    set_error("cmm_estimate: workspace of " + std::to_string(workspace_bytes) +
+              " bytes, need " + std::to_string(P.bytes));
+    return CMM_ENOMEM;
+  }
+  if (!workspace && P.bytes > 0) return invalid("cmm_estimate: workspace is null");
+  return run_estimate(prob, static_cast<char*>(workspace), as_stream(stream));
+}
+
+}  // extern "C"

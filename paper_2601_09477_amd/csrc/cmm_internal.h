@@ -1,0 +1,120 @@
+// Internal declarations shared by the HIP translation units of libcmm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "cmm.h"
+
+namespace cmm {
+
+constexpr uint32_t kSignBit = 0x80000000u;
+constexpr uint32_t kBucketMask = 0x7FFFFFFFu;
+
+// Thread-local message for cmm_last_error().
+void set_error(const std::string& msg);
+
+// Returns CMM_EINVAL after recording msg.
+cmm_status invalid(const std::string& msg);
+
+// Maps a HIP error to CMM_EHIP (recording where it happened) or CMM_OK.
+cmm_status hip_check(hipError_t e, const char* what);
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline size_t dtype_size(cmm_dtype t) {
+  switch (t) {
+    case CMM_F64: return 8;
+    case CMM_F32: return 4;
+    case CMM_BF16: return 2;
+    case CMM_F16: return 2;
+  }
+  return 0;
+}
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------ kernel timing
+// While timing is enabled (cmm_profile_enable), launchers bracket their
+// kernels with HIP events recorded on the launch stream; cmm_profile_query
+// sums the elapsed times per kernel name.  Disabled, a scope costs one
+// relaxed atomic load.
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t s);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t stream_;
+  hipEvent_t start_ = nullptr;
+};
+
+// ---------------------------------------------------------------- launchers
+// Every launcher only enqueues work; arguments were validated by the caller.
+cmm_status launch_hash(const uint64_t* keys, int d, int64_t n_rows, int64_t n_cols, int log2b,
+                       uint32_t* tab1, uint32_t* tab2, hipStream_t s);
+
+cmm_status launch_sketch(int side, const void* M, cmm_dtype dt, int64_t rows, int64_t cols,
+                         int64_t ld, const uint32_t* tab, int d, int log2b, int64_t k0,
+                         int64_t kc, void* out, hipStream_t s);
+
+cmm_status launch_fwht(void* x, cmm_dtype dt, int64_t batch, int log2b, double scale,
+                       hipStream_t s);
+
+cmm_status launch_accumulate(const void* X, const void* Y, cmm_dtype dt, int d, int64_t kc,
+                             int log2b, double* p_hat, hipStream_t s);
+
+cmm_status launch_extract(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                          int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator est,
+                          void* C_hat, cmm_dtype out_dt, int64_t ldc, hipStream_t s);
+
+// Fill n doubles with zero (a kernel, not hipMemsetAsync, so that the
+// sequence stays valid under stream capture).
+cmm_status launch_zero(double* x, size_t n, hipStream_t s);
+
+// Sum g partial float64 vectors of length len (stored back to back) into
+// out, in ascending partial order.
+cmm_status launch_reduce_partials(const double* parts, int g, size_t len, double* out,
+                                  hipStream_t s);
+
+// ------------------------------------------------------ fused compress
+// Per-call plan of the lo-bucket membership of one operand (see k_compress).
+struct PlanView {
+  int32_t* first;     // [d][b_lo]  lowest index in each lo-bucket, or -1
+  uint32_t* extras;   // [d][n]     index | first << 16, grouped by rank
+  uint32_t* meta;     // [d][n]     hi-bits xor | sign xor << 31
+  int32_t* roff;      // [d][n + 2] start of each rank in extras
+  int32_t* maxrank;   // [d]
+  int32_t* rank;      // [d][n]     scratch
+};
+
+struct CompressArgs {
+  const void* At;          // A^T: n_inner x n_rows, dense
+  const void* B;           // n_inner x n_cols, leading dimension ldb
+  int64_t ldb;
+  int64_t n_rows, n_cols, n_inner;
+  const uint32_t* tab1;    // [d][n_rows]
+  const uint32_t* tab2;    // [d][n_cols]
+  PlanView planA, planB;
+  int d, log2b, groups;
+  double* partial;         // [groups][d][2^log2b]
+};
+
+size_t plan_bytes(int d, int64_t n, int lb);
+PlanView carve_plan(char* p, int d, int64_t n, int lb);
+cmm_status launch_plan(const uint32_t* tab, int d, int64_t n, int lb, const PlanView& pv,
+                       hipStream_t s);
+cmm_status launch_compress(const CompressArgs& a, cmm_dtype dt, int lb, hipStream_t s);
+
+// out[c][r] = in[r][c] (dense out, leading dimension rows), with conversion.
+cmm_status launch_transpose(const void* in, cmm_dtype in_dt, int64_t rows, int64_t cols,
+                            int64_t ld, void* out, cmm_dtype out_dt, hipStream_t s);
+// out[r][c] = in[r][c] (dense out), with conversion.
+cmm_status launch_convert(const void* in, cmm_dtype in_dt, int64_t rows, int64_t cols,
+                          int64_t ld, void* out, cmm_dtype out_dt, hipStream_t s);
+
+}  // namespace cmm

@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, it
+exports every function the header declares, and argument checks return
+CMM_EINVAL before anything touches the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2601_09477_amd as cmm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "cmm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmm_[a-z_]+)\s*\(", src)))
+
+
+def _lib_or_skip():
+    if not os.path.exists(cmm.LIB_PATH):
+        pytest.skip("libcmm.so not built")
+    return cmm.lib()
+
+
+def test_header_declares_the_boundary():
+    fns = _header_functions()
+    for name in ["cmm_hash", "cmm_sketch", "cmm_fwht", "cmm_accumulate", "cmm_extract",
+                 "cmm_estimate", "cmm_workspace_size"]:
+        assert name in fns
+    assert set(fns) == set(cmm.EXPORTED)
+
+
+def test_library_exports_every_header_symbol():
+    L = _lib_or_skip()
+    for name in _header_functions():
+        assert hasattr(L, name), name
+    assert L.cmm_abi_version() == 1
+    assert L.cmm_status_string(1) == b"CMM_EINVAL"
+
+
+def test_problem_struct_layout_matches_header():
+    # offsets of the C struct on x86-64 (int64 / pointer = 8, enum / int = 4)
+    P = cmm.Problem
+    assert P.A.offset == 24 and P.lda.offset == 32 and P.B.offset == 40
+    assert P.in_dtype.offset == 56 and P.estimator.offset == 72 and P.keys.offset == 80
+    assert P.C_hat.offset == 112 and P.out_dtype.offset == 120 and P.ldc.offset == 128
+    assert ctypes.sizeof(P) == 136
+
+
+@pytest.mark.parametrize("call", [
+    lambda L: L.cmm_hash(None, 0, 4, 4, 8, None, None, None),          # d = 0
+    lambda L: L.cmm_hash(None, 3, 4, 4, 31, None, None, None),         # log2b too large
+    lambda L: L.cmm_hash(None, 3, 4, 4, 8, None, None, None),          # null keys
+    lambda L: L.cmm_hash(1, 3, 1 << 33, 4, 8, 1, 1, None),              # beyond hash domain
+    lambda L: L.cmm_sketch(2, 1, 0, 4, 4, 4, 1, 1, 8, 0, 1, 1, None),   # bad side
+    lambda L: L.cmm_sketch(0, 1, 2, 4, 4, 4, 1, 1, 8, 0, 1, 1, None),   # bf16 not a sketch type
+    lambda L: L.cmm_sketch(0, 1, 0, 4, 4, 3, 1, 1, 8, 0, 1, 1, None),   # ld < cols
+    lambda L: L.cmm_sketch(0, 1, 0, 4, 4, 4, 1, 1, 8, 3, 2, 1, None),   # k0 + kc > inner
+    lambda L: L.cmm_fwht(1, 0, 4, 8, 3.0, None),                        # scale not a power of 2
+    lambda L: L.cmm_fwht(1, 0, 4, 0, 1.0, None),                        # log2b = 0
+    lambda L: L.cmm_fwht(None, 0, 4, 8, 1.0, None),                     # null x
+    lambda L: L.cmm_accumulate(None, 1, 0, 3, 2, 8, 1, None),           # null X
+    lambda L: L.cmm_extract(1, 1, 1, 4, 8, 8, 8, 0, 1, 0, 8, None),     # median with even d
+    lambda L: L.cmm_extract(1, 1, 1, 3, 8, 8, 8, 0, 1, 0, 7, None),     # ldc < n_cols
+    lambda L: L.cmm_extract(1, 1, 1, 3, 8, 8, 8, 5, 1, 0, 8, None),     # unknown estimator
+])
+def test_invalid_arguments_rejected_on_host(call):
+    L = _lib_or_skip()
+    assert call(L) == cmm.CMM_EINVAL
+    assert len(L.cmm_last_error()) > 0
+
+
+def _problem(**kw):
+    pr = cmm.Problem()
+    pr.n_rows, pr.n_inner, pr.n_cols = 8, 8, 8
+    pr.A, pr.lda, pr.B, pr.ldb = 1, 8, 1, 8
+    pr.in_dtype, pr.compute, pr.d, pr.log2b = cmm.CMM_F64, cmm.CMM_F64, 3, 10
+    pr.estimator, pr.tab1, pr.tab2 = cmm.CMM_MEDIAN, 1, 1
+    for k, v in kw.items():
+        setattr(pr, k, v)
+    return pr
+
+
+@pytest.mark.parametrize("kw", [
+    dict(d=4), dict(log2b=0), dict(lda=7), dict(in_dtype=cmm.CMM_F32),
+    dict(compute=9), dict(A=None), dict(tab1=None), dict(C_hat=1, ldc=7),
+    dict(n_rows=(1 << 32) + 1),
+])
+def test_problem_validation(kw):
+    L = _lib_or_skip()
+    n = ctypes.c_size_t(0)
+    assert L.cmm_workspace_size(ctypes.byref(_problem(**kw)), ctypes.byref(n)) == cmm.CMM_EINVAL
+    assert L.cmm_estimate(ctypes.byref(_problem(**kw)), None, 0, None) == cmm.CMM_EINVAL
+
+
+def test_workspace_size_and_short_workspace():
+    L = _lib_or_skip()
+    n = ctypes.c_size_t(0)
+    pr = _problem(n_rows=256, n_inner=256, n_cols=256, lda=256, ldb=256, log2b=12, d=5)
+    assert L.cmm_workspace_size(ctypes.byref(pr), ctypes.byref(n)) == cmm.CMM_OK
+    assert n.value > 5 * 4096 * 8
+    # a workspace one byte short is refused before any launch
+    assert L.cmm_estimate(ctypes.byref(pr), 1, n.value - 1, None) == cmm.CMM_ENOMEM
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(cmm, "_lib", None)
+    monkeypatch.setattr(cmm, "LIB_PATH", "/nonexistent/libcmm.so")
+    with pytest.raises(cmm.CmmError):
+        cmm.lib()
