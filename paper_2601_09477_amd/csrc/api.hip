@@ -61,6 +61,8 @@ ProfScope::~ProfScope() {
 
 namespace {
 
+int g_compress_variant = 0;   // selected by cmm_set_option("compress_variant")
+
 constexpr int kMaxLog2b = 30;
 constexpr size_t kLdsBytes = 160 * 1024;
 constexpr int64_t kMaxHashDomain = (int64_t)1 << 32;
@@ -136,9 +138,15 @@ EstimatePlan make_plan(const cmm_problem* pr) {
   // buffer and one staged row of each operand.
   const int lb_max = P.cdt == CMM_F64 ? 13 : 14;
   int lb = pr->log2b < lb_max ? pr->log2b : lb_max;
-  while (lb >= 11 && (((size_t)1 << lb) + (size_t)pr->n_rows + (size_t)pr->n_cols) * es > kLdsBytes)
-    --lb;
-  P.fused = lb >= 11 && pr->n_rows <= 65535 && pr->n_cols <= 65535 && pr->n_rows > 0 &&
+  auto fits = [&](int l) {
+    const size_t v = 16 / es;
+    const size_t rows = ((size_t)1 << l) + ((size_t)1 << (l - 7)) +
+                        ((size_t)pr->n_rows + v) / v * v + ((size_t)pr->n_cols + v) / v * v;
+    return rows * es <= kLdsBytes && plan_lds_bytes(pr->n_rows, l) <= kLdsBytes &&
+           plan_lds_bytes(pr->n_cols, l) <= kLdsBytes;
+  };
+  while (lb >= 11 && !fits(lb)) --lb;
+  P.fused = lb >= 11 && pr->n_rows <= 65534 && pr->n_cols <= 65534 && pr->n_rows > 0 &&
             pr->n_cols > 0 && pr->n_inner > 0;
   size_t off = 0;
   if (P.fused) {
@@ -217,6 +225,9 @@ cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
     a.log2b = pr->log2b;
     a.groups = P.groups;
     a.partial = reinterpret_cast<double*>(ws + P.off_part);
+    a.ex_cap = 0;
+    a.dma = 0;
+    a.variant = g_compress_variant;
     if ((st = launch_plan(pr->tab1, d, pr->n_rows, P.lb, a.planA, s)) != CMM_OK) return st;
     if ((st = launch_plan(pr->tab2, d, pr->n_cols, P.lb, a.planB, s)) != CMM_OK) return st;
     if ((st = launch_compress(a, P.cdt, P.lb, s)) != CMM_OK) return st;

@@ -85,11 +85,11 @@ cmm_status launch_reduce_partials(const double* parts, int g, size_t len, double
 // Per-call plan of the lo-bucket membership of one operand (see k_compress).
 struct PlanView {
   int32_t* first;     // [d][b_lo]  lowest index in each lo-bucket, or -1
-  uint32_t* extras;   // [d][n]     index | first << 16, grouped by rank
-  uint32_t* meta;     // [d][n]     hi-bits xor | sign xor << 31
-  int32_t* roff;      // [d][n + 2] start of each rank in extras
+  uint2* pairs;       // [d][n]     (index | first << 16, hi-bits xor | sign xor << 31)
+                      //            of every non-first index, grouped by rank
+  int32_t* roff;      // [d][n + 2] start of each rank in pairs
   int32_t* maxrank;   // [d]
-  int32_t* rank;      // [d][n]     scratch
+  int32_t* cursor;    // [d][n]     scratch: per-rank placement cursors
 };
 
 struct CompressArgs {
@@ -102,9 +102,13 @@ struct CompressArgs {
   PlanView planA, planB;
   int d, log2b, groups;
   double* partial;         // [groups][d][2^log2b]
+  int64_t ex_cap;          // set by the launcher: LDS entries for the extras
+  int dma;                 // set by the launcher: asynchronous row copies
+  int variant;             // 0: default kernel for (dtype, b_lo); 1: 32 elements per thread
 };
 
 size_t plan_bytes(int d, int64_t n, int lb);
+size_t plan_lds_bytes(int64_t n, int lb);
 PlanView carve_plan(char* p, int d, int64_t n, int lb);
 cmm_status launch_plan(const uint32_t* tab, int d, int64_t n, int lb, const PlanView& pv,
                        hipStream_t s);

@@ -43,76 +43,80 @@ namespace cmm {
 //   maxrank[t].
 namespace {
 
-constexpr int kPlanWave = 64;
+constexpr int kPlanThreads = 1024;
+constexpr int32_t kNone = 0x7FFFFFFF;
 
-__global__ __launch_bounds__(kPlanWave) void plan_kernel(const uint32_t* __restrict__ tab,
-                                                         int64_t n, int lb, PlanView pv) {
+// One work-group per repetition.  LDS: cur[b_lo], nxt[b_lo] (int32) and
+// rank[n] (int32).  Rank rounds: round 0 takes the lowest index of every
+// lo-bucket (atomicMin, order independent); round r takes the lowest index
+// among those not yet ranked.  Hence rank(i) = number of lower indices in
+// the same lo-bucket, computed deterministically.
+__global__ __launch_bounds__(kPlanThreads) void plan_kernel(const uint32_t* __restrict__ tab,
+                                                            int64_t n, int lb, PlanView pv) {
   const int t = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int64_t blo = (int64_t)1 << lb;
+  const int tid = threadIdx.x;
+  const int blo = 1 << lb;
   const uint32_t lomask = (uint32_t)blo - 1u;
   const uint32_t* tb = tab + (size_t)t * n;
   int32_t* first = pv.first + (size_t)t * blo;
-  int32_t* rank = pv.rank + (size_t)t * n;
   int32_t* roff = pv.roff + (size_t)t * (n + 2);
-  // cnt[r]: indices seen so far in lo-bucket r (LDS holds max(b_lo, n + 2)
-  // counters so that it can be reused as the per-rank cursor below).
-  extern __shared__ int32_t cnt[];
-  for (int64_t r = lane; r < blo; r += kPlanWave) { cnt[r] = 0; first[r] = -1; }
-  for (int64_t r = lane; r < n + 2; r += kPlanWave) roff[r] = 0;
+  extern __shared__ int32_t sh[];
+  int32_t* cur = sh;                // [b_lo]
+  int32_t* nxt = sh + blo;          // [b_lo]
+  int32_t* rank = sh + 2 * blo;     // [n]
+  int32_t* flags = rank + n;        // [2]: more, maxrank
+  int32_t& s_more = flags[0];
+  int32_t& s_maxr = flags[1];
+  int32_t* cursor = pv.cursor + (size_t)t * n;   // global per-rank cursors
+  for (int r = tid; r < blo; r += kPlanThreads) cur[r] = kNone;
+  for (int64_t i = tid; i < n; i += kPlanThreads) rank[i] = -1;
+  for (int64_t r = tid; r < n + 2; r += kPlanThreads) roff[r] = 0;
+  if (tid == 0) s_maxr = 0;
   __syncthreads();
-  int maxr = 0;
-  for (int64_t g0 = 0; g0 < n; g0 += kPlanWave) {
-    const int64_t i = g0 + lane;
-    const uint32_t key = i < n ? (tb[i] & lomask) : 0xFFFFFFFFu;
-    int below = 0, above = 0;
-    for (int j = 0; j < kPlanWave; ++j) {
-      const uint32_t kj = (uint32_t)__builtin_amdgcn_readlane((int)key, j);
-      below += (j < lane && kj == key) ? 1 : 0;
-      above += (j > lane && kj == key) ? 1 : 0;
-    }
-    int rk = 0;
-    if (i < n) {
-      rk = cnt[key] + below;
-      rank[i] = rk;
-      if (rk == 0) first[key] = (int32_t)i;
-      maxr = rk > maxr ? rk : maxr;
-    }
-    __syncthreads();   // all reads of cnt for this group precede the updates
-    if (i < n && above == 0) cnt[key] = rk + 1;
+  for (int64_t i = tid; i < n; i += kPlanThreads) atomicMin(&cur[tb[i] & lomask], (int32_t)i);
+  __syncthreads();
+  for (int r = tid; r < blo; r += kPlanThreads) first[r] = cur[r] == kNone ? -1 : cur[r];
+  for (int64_t i = tid; i < n; i += kPlanThreads)
+    if (cur[tb[i] & lomask] == (int32_t)i) rank[i] = 0;
+  for (int round = 1;; ++round) {
+    for (int r = tid; r < blo; r += kPlanThreads) nxt[r] = kNone;
+    if (tid == 0) s_more = 0;
     __syncthreads();
-  }
-  for (int off = 32; off >= 1; off >>= 1) {
-    const int o = __shfl_xor(maxr, off);
-    maxr = o > maxr ? o : maxr;
-  }
-  if (lane == 0) pv.maxrank[t] = maxr;
-  // histogram of ranks >= 1 into roff[rank + 1], then prefix sum
-  for (int64_t i = lane; i < n; i += kPlanWave) {
-    const int rk = rank[i];
-    if (rk >= 1) atomicAdd(&roff[rk + 1], 1);
+    for (int64_t i = tid; i < n; i += kPlanThreads)
+      if (rank[i] < 0) atomicMin(&nxt[tb[i] & lomask], (int32_t)i);
+    __syncthreads();
+    for (int64_t i = tid; i < n; i += kPlanThreads)
+      if (rank[i] < 0 && nxt[tb[i] & lomask] == (int32_t)i) { rank[i] = round; s_more = 1; }
+    __syncthreads();
+    if (!s_more) { if (tid == 0) s_maxr = round - 1; break; }
+    __syncthreads();   // everyone read s_more before it is reset
   }
   __syncthreads();
-  if (lane == 0) {
+  const int maxr = s_maxr;
+  if (tid == 0) pv.maxrank[t] = maxr;
+  // counts of each rank >= 1 (global roff as the histogram), prefix sums
+  for (int64_t i = tid; i < n; i += kPlanThreads)
+    if (rank[i] >= 1) atomicAdd(&roff[rank[i] + 1], 1);
+  __syncthreads();
+  if (tid == 0) {
     int32_t acc = 0;
-    for (int r = 0; r <= maxr + 1 && r < n + 2; ++r) { acc += roff[r]; roff[r] = acc; }
+    for (int r = 0; r <= maxr + 1; ++r) { acc += roff[r]; roff[r] = acc; }
   }
   __syncthreads();
-  // roff[r] now = number of entries with rank < r (r >= 1).  Place the
-  // entries of each rank through a per-rank cursor; the order inside a rank
-  // is irrelevant because the targets of one rank are distinct buckets.
-  for (int r = lane; r <= maxr + 1; r += kPlanWave) cnt[r] = 0;
+  // placement through per-rank cursors (ranks 1 .. maxr <= n - 1); the order
+  // inside one rank is irrelevant because its targets are distinct buckets
+  for (int r = tid; r <= maxr && r < n; r += kPlanThreads) cursor[r] = 0;
   __syncthreads();
-  for (int64_t i = lane; i < n; i += kPlanWave) {
+  for (int64_t i = tid; i < n; i += kPlanThreads) {
     const int rk = rank[i];
     if (rk >= 1) {
       const uint32_t e = tb[i];
-      const int32_t f = first[e & lomask];
+      const int32_t f = cur[e & lomask];          // round-0 winner = first index
       const uint32_t ef = tb[f];
-      const int pos = roff[rk] + atomicAdd(&cnt[rk], 1);
-      pv.extras[(size_t)t * n + pos] = (uint32_t)i | ((uint32_t)f << 16);
+      const int pos = roff[rk] + atomicAdd(&cursor[rk], 1);
       const uint32_t hx = ((e & kBucketMask) >> lb) ^ ((ef & kBucketMask) >> lb);
-      pv.meta[(size_t)t * n + pos] = hx | ((e ^ ef) & kSignBit);
+      pv.pairs[(size_t)t * n + pos] = make_uint2((uint32_t)i | ((uint32_t)f << 16),
+                                                 hx | ((e ^ ef) & kSignBit));
     }
   }
 }
@@ -249,8 +253,12 @@ __device__ __forceinline__ uint32_t l2_lane(int l, int w, bool after) {
   for (int k = 0; k < LB - 11; ++k) r |= (uint32_t)((w >> k) & 1) << L2Map<LB>::wave(k);
   return r;
 }
-// XOR swizzle of the transpose buffer: low 4 bits ^= bits 7..10.
-__device__ __forceinline__ uint32_t swz(uint32_t x) { return x ^ ((x >> 7) & 15u); }
+// Padded transpose buffer: one spare element after every 128.  Writes (L1',
+// lanes 0..15 stepping u_lo bit 7) then hit 16 distinct bank pairs, reads
+// (L2, lanes 0..15 stepping bits 0..3) are contiguous; and the padding is
+// additive in the register part of the index, so every access is a base
+// address plus an immediate offset.
+__device__ __forceinline__ uint32_t swz(uint32_t x) { return x + (x >> 7); }
 
 }  // namespace
 
@@ -263,29 +271,57 @@ struct Cfg {
   static constexpr int NT = (1 << LB) / E;
 };
 
-// Stage row `k` of the operand (n values) into LDS.
+// Copy a row of n values into LDS.  With `dma` the copy is issued as
+// asynchronous 16-byte global->LDS loads (global_load_lds_dwordx4): each
+// wavefront moves 64 consecutive 16-byte chunks per instruction, lane L to
+// LDS offset 16 L; completion is awaited with s_waitcnt vmcnt(0) before the
+// next barrier.  Without `dma` it is a plain load/store loop.
 template <typename T, int NT>
 __device__ __forceinline__ void stage_row(T* __restrict__ dst, const T* __restrict__ src,
-                                          int64_t n) {
-  for (int64_t i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
+                                          int64_t n, bool dma) {
+  if (dma) {
+    constexpr int V = 16 / sizeof(T);
+    const int64_t chunks = n / V;
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = threadIdx.x & ~63;
+    for (int64_t c0 = wbase; c0 < chunks; c0 += NT) {
+      if (c0 + lane < chunks)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(src + (c0 + lane) * V),
+            (__attribute__((address_space(3))) void*)(dst + c0 * V), 16, 0, 0);
+    }
+  } else {
+    for (int64_t i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
+  }
 }
 
-// Apply the rank rounds of extras onto the staged row (folded signs).
+// Elements of a staged row, rounded up so the next row stays 16-byte
+// aligned, plus one zero pad element.
+template <typename T>
+__host__ __device__ constexpr int64_t row_pitch(int64_t n) {
+  return (n + 1 + (16 / (int64_t)sizeof(T)) - 1) / (16 / (int64_t)sizeof(T)) * (16 / (int64_t)sizeof(T));
+}
+
+// x with its sign bit flipped when bit 31 of m is set.
+__device__ __forceinline__ double flip_sign(double x, uint32_t m) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x) ^ ((uint64_t)m << 32);
+  return __longlong_as_double((long long)u);
+}
+__device__ __forceinline__ float flip_sign(float x, uint32_t m) {
+  return __uint_as_float(__float_as_uint(x) ^ m);
+}
+
+__device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// One rank round of the non-first rows of one operand: row[target] += +-row[index].
 template <typename T, int NT>
-__device__ __forceinline__ void fixups(T* __restrict__ row, const uint32_t* __restrict__ ex,
-                                       const uint32_t* __restrict__ meta,
-                                       const int32_t* __restrict__ roff, int maxr,
-                                       uint32_t uhi) {
-  for (int r = 1; r <= maxr; ++r) {
-    const int beg = roff[r], end = roff[r + 1];
-    for (int q = beg + (int)threadIdx.x; q < end; q += NT) {
-      const uint32_t x = ex[q], m = meta[q];
-      const uint32_t idx = x & 0xFFFFu, tgt = x >> 16;
-      const uint32_t neg = (m >> 31) ^ (__popc(uhi & (m & kBucketMask)) & 1u);
-      const T v = row[idx];
-      row[tgt] = row[tgt] + (neg ? -v : v);
-    }
-    __syncthreads();
+__device__ __forceinline__ void fix_round(T* __restrict__ row, const uint2* __restrict__ ex,
+                                          int beg, int end, uint32_t uhi) {
+  for (int q = beg + (int)threadIdx.x; q < end; q += NT) {
+    const uint2 x = ex[q];
+    const uint32_t neg = (x.y >> 31) ^ (__popc(uhi & (x.y & kBucketMask)) & 1u);
+    const T v = row[x.x & 0xFFFFu];
+    row[x.x >> 16] = row[x.x >> 16] + (neg ? -v : v);
   }
 }
 
@@ -295,20 +331,20 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a
   constexpr int NT = Cfg<T, LB>::NT;
   constexpr int BLO = 1 << LB;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* xbuf = reinterpret_cast<T*>(smem);                 // BLO
-  T* rowA = xbuf + BLO;                                 // n_rows
-  T* rowB = rowA + a.n_rows;                            // n_cols
+  T* xbuf = reinterpret_cast<T*>(smem);                          // BLO
+  T* rowA = xbuf + BLO + BLO / 128;                              // n_rows (16-byte aligned)
+  T* rowB = rowA + row_pitch<T>(a.n_rows);                       // n_cols (+ pad)
+  uint2* exl = reinterpret_cast<uint2*>(rowB + row_pitch<T>(a.n_cols));
+  if (threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
 
   const int b_hi_bits = a.log2b - LB;
   const int64_t nunits = (int64_t)a.d << b_hi_bits;
   // XCD-aware order: work-groups are dealt to the 8 XCDs round robin, so
-  // give consecutive groups of the same XCD the same k-range.
+  // the groups one XCD runs share a k-range (their input rows hit its L2).
   const int64_t wg = blockIdx.x;
   const int64_t total = nunits * a.groups;
-  const int64_t xcd = wg & 7, slot = wg >> 3;
-  const int64_t per_xcd = (total + 7) >> 3;
-  int64_t lin = xcd * per_xcd + slot;                   // a permutation when total % 8 == 0
-  if ((total & 7) != 0) lin = wg;
+  int64_t lin = wg;
+  if ((total & 7) == 0) lin = (wg & 7) * (total >> 3) + (wg >> 3);
   const int g = (int)(lin / nunits);
   const int64_t unit = lin - (int64_t)g * nunits;
   const int t = (int)(unit >> b_hi_bits);
@@ -318,10 +354,11 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a
   const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // L1: this thread's 32 consecutive buckets start at base1.
   const uint32_t base1 = ((uint32_t)((lane >> 4) & 1) << 5) | ((uint32_t)((lane >> 5) & 1) << 6) |
                          ((uint32_t)(lane & 15) << 7) | ((uint32_t)w << 11);
-  // First rows of the thread's buckets (0xFFFF = empty) and folded signs.
+  // First rows of the thread's 32 consecutive buckets and their folded
+  // signs.  Empty buckets point at a zero pad element after the staged row
+  // (index n), so the gather below is branch free.
   uint32_t fa[E / 2], fb[E / 2];
   uint32_t nega = 0, negb = 0;
   {
@@ -332,34 +369,39 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int32_t r1 = f1[e], r2 = f2[e];
-      uint32_t s1 = 0, s2 = 0;
-      if (r1 >= 0) {
-        const uint32_t en = t1[r1];
-        s1 = (en >> 31) ^ (__popc(uhi & ((en & kBucketMask) >> LB)) & 1u);
-      }
-      if (r2 >= 0) {
-        const uint32_t en = t2[r2];
-        s2 = (en >> 31) ^ (__popc(uhi & ((en & kBucketMask) >> LB)) & 1u);
-      }
+      const uint32_t en1 = t1[r1 >= 0 ? r1 : 0], en2 = t2[r2 >= 0 ? r2 : 0];
+      const uint32_t s1 = r1 >= 0 ? (en1 >> 31) ^ (__popc(uhi & ((en1 & kBucketMask) >> LB)) & 1u) : 0u;
+      const uint32_t s2 = r2 >= 0 ? (en2 >> 31) ^ (__popc(uhi & ((en2 & kBucketMask) >> LB)) & 1u) : 0u;
       nega |= s1 << e;
       negb |= s2 << e;
-      const uint32_t ra = r1 >= 0 ? (uint32_t)r1 : 0xFFFFu;
-      const uint32_t rb = r2 >= 0 ? (uint32_t)r2 : 0xFFFFu;
+      const uint32_t ra = r1 >= 0 ? (uint32_t)r1 : (uint32_t)a.n_rows;
+      const uint32_t rb = r2 >= 0 ? (uint32_t)r2 : (uint32_t)a.n_cols;
       if (e & 1) { fa[e >> 1] |= ra << 16; fb[e >> 1] |= rb << 16; }
       else { fa[e >> 1] = ra; fb[e >> 1] = rb; }
     }
   }
-  const uint32_t* exA = a.planA.extras + (size_t)t * a.n_rows;
-  const uint32_t* mtA = a.planA.meta + (size_t)t * a.n_rows;
+  // Non-first rows (constant over k): copied once into LDS when they fit.
   const int32_t* roA = a.planA.roff + (size_t)t * (a.n_rows + 2);
-  const int maxrA = a.planA.maxrank[t];
-  const uint32_t* exB = a.planB.extras + (size_t)t * a.n_cols;
-  const uint32_t* mtB = a.planB.meta + (size_t)t * a.n_cols;
   const int32_t* roB = a.planB.roff + (size_t)t * (a.n_cols + 2);
-  const int maxrB = a.planB.maxrank[t];
+  const int maxrA = a.planA.maxrank[t], maxrB = a.planB.maxrank[t];
+  const int cntA = roA[maxrA + 1], cntB = roB[maxrB + 1];
+  const bool ex_lds = (int64_t)(cntA + cntB) <= a.ex_cap;
+  const uint2* exA;
+  const uint2* exB;
+  const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
+  const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
+  if (ex_lds) {
+    for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gA[q];
+    for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gB[q];
+    exA = exl;
+    exB = exl + cntA;
+  } else {
+    exA = gA;
+    exB = gB;
+  }
 
-  const uint32_t w1 = l1p_lane(lane, w);
-  const uint32_t r2lane = l2_lane<LB>(lane, w, false);
+  const uint32_t w1 = swz(l1p_lane(lane, w));          // + l1p_reg(e) (additive)
+  const uint32_t r2lane = swz(l2_lane<LB>(lane, w, false));   // + swz(l2_reg(e))
 
   T acc[E];
 #pragma unroll
@@ -367,30 +409,20 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a
 
   const T* At = reinterpret_cast<const T*>(a.At);
   const T* Bm = reinterpret_cast<const T*>(a.B);
+  const bool dma = a.dma != 0;
+  if (k0 < k1) {
+    stage_row<T, NT>(rowA, At + k0 * a.n_rows, a.n_rows, dma);
+    stage_row<T, NT>(rowB, Bm + k0 * a.ldb, a.n_cols, dma);
+  }
+  const int maxr = maxrA > maxrB ? maxrA : maxrB;
 
   for (int64_t k = k0; k < k1; ++k) {
-    stage_row<T, NT>(rowA, At + k * a.n_rows, a.n_rows);
-    stage_row<T, NT>(rowB, Bm + k * a.ldb, a.n_cols);
+    if (dma) wait_dma();
     __syncthreads();
     // rank rounds of both operands share the barriers
-    const int maxr = maxrA > maxrB ? maxrA : maxrB;
     for (int r = 1; r <= maxr; ++r) {
-      if (r <= maxrA) {
-        for (int q = roA[r] + (int)threadIdx.x; q < roA[r + 1]; q += NT) {
-          const uint32_t x = exA[q], m = mtA[q];
-          const uint32_t neg = (m >> 31) ^ (__popc(uhi & (m & kBucketMask)) & 1u);
-          const T v = rowA[x & 0xFFFFu];
-          rowA[x >> 16] = rowA[x >> 16] + (neg ? -v : v);
-        }
-      }
-      if (r <= maxrB) {
-        for (int q = roB[r] + (int)threadIdx.x; q < roB[r + 1]; q += NT) {
-          const uint32_t x = exB[q], m = mtB[q];
-          const uint32_t neg = (m >> 31) ^ (__popc(uhi & (m & kBucketMask)) & 1u);
-          const T v = rowB[x & 0xFFFFu];
-          rowB[x >> 16] = rowB[x >> 16] + (neg ? -v : v);
-        }
-      }
+      if (r <= maxrA) fix_round<T, NT>(rowA, exA, roA[r], roA[r + 1], uhi);
+      if (r <= maxrB) fix_round<T, NT>(rowB, exB, roB[r], roB[r + 1], uhi);
       __syncthreads();
     }
     T X[E], Y[E];
@@ -398,31 +430,32 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a
     for (int e = 0; e < E; ++e) {
       const uint32_t ra = (e & 1) ? (fa[e >> 1] >> 16) : (fa[e >> 1] & 0xFFFFu);
       const uint32_t rb = (e & 1) ? (fb[e >> 1] >> 16) : (fb[e >> 1] & 0xFFFFu);
-      T va = ra != 0xFFFFu ? rowA[ra] : T(0);
-      T vb = rb != 0xFFFFu ? rowB[rb] : T(0);
-      X[e] = ((nega >> e) & 1u) ? -va : va;
-      Y[e] = ((negb >> e) & 1u) ? -vb : vb;
+      X[e] = flip_sign(rowA[ra], (nega << (31 - e)) & 0x80000000u);
+      Y[e] = flip_sign(rowB[rb], (negb << (31 - e)) & 0x80000000u);
+    }
+    __syncthreads();   // every gather is done: the row buffers can be refilled
+    if (k + 1 < k1) {
+      stage_row<T, NT>(rowA, At + (k + 1) * a.n_rows, a.n_rows, dma);
+      stage_row<T, NT>(rowB, Bm + (k + 1) * a.ldb, a.n_cols, dma);
     }
     pass1(X);
     pass1(Y);
-    // transpose X through LDS
 #pragma unroll
-    for (int e = 0; e < E; ++e) xbuf[swz(w1 | l1p_reg(e))] = X[e];
+    for (int e = 0; e < E; ++e) xbuf[w1 + l1p_reg(e)] = X[e];
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) X[e] = xbuf[swz(r2lane | l2_reg<LB>(e, false))];
+    for (int e = 0; e < E; ++e) X[e] = xbuf[r2lane + swz(l2_reg<LB>(e, false))];
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) xbuf[swz(w1 | l1p_reg(e))] = Y[e];
+    for (int e = 0; e < E; ++e) xbuf[w1 + l1p_reg(e)] = Y[e];
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) Y[e] = xbuf[swz(r2lane | l2_reg<LB>(e, false))];
+    for (int e = 0; e < E; ++e) Y[e] = xbuf[r2lane + swz(l2_reg<LB>(e, false))];
     pass2<LB>(X);
     pass2<LB>(Y);
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = fma(X[e], Y[e], acc[e]);
-    // rowA/rowB and xbuf are rewritten next iteration only after this barrier
-    __syncthreads();
+    // xbuf is rewritten next iteration only after the rank-round barriers
   }
   // write the slice of the partial p_hat
   const int64_t b = (int64_t)1 << a.log2b;
@@ -432,18 +465,216 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a
   for (int e = 0; e < E; ++e) dst[r2after | l2_reg<LB>(e, true)] = (double)acc[e];
 }
 
+// ------------------------------------------------ 16 elements per thread
+// The float64 variant for b_lo = 2^13 with 512 threads (two wavefronts per
+// SIMD): 4 register bits, 6 lane bits, 3 wave bits.
+//   L1 (gather, pass 1): reg -> u_lo bits 0..3, lane bits 4,5 -> 4,5,
+//       lane bits 0..3 -> 6..9, waves -> 10..12.  Pass 1: stages 0..3 in
+//       registers, stages 4 and 5 after permlane16/32 swaps with reg bits 0/1.
+//   L2 (pass 2): reg -> 6..9, lane bits 4,5 -> 10,11 (permlane swaps),
+//       lane bit 3 -> 12 (a DPP row_ror:8 butterfly, i.e. partner lane
+//       xor 8), lane bits 0..2 -> 0..2, waves -> 3..5.
+// Transpose buffer padding g(x) = x + (x >> 6) + 8 * bit12(x) makes both
+// the L1' writes and the L2 reads free of bank conflicts and is additive in
+// the register part of the index.
+
+__device__ __forceinline__ uint32_t pad16(uint32_t x) { return x + (x >> 6) + ((x >> 9) & 8u); }
+
+// Butterfly across lane bit 3: lanes with bit 3 clear keep a + b, lanes
+// with it set b' = a - b, where the partner value comes from lane xor 8
+// (row_ror:8 within 16-lane rows).
+__device__ __forceinline__ double dpp_xor8(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x128, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x128, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ float dpp_xor8(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
+}
+
+template <int J, typename T>
+__device__ __forceinline__ void stage_reg16(T (&v)[16]) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e)
+    if ((e & (1 << J)) == 0) bfly(v[e], v[e | (1 << J)]);
+}
+template <int J, int S, typename T>
+__device__ __forceinline__ void swap_reg16(T (&v)[16]) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e)
+    if ((e & (1 << J)) == 0) {
+      if (S == 16) xswap16(v[e], v[e | (1 << J)]);
+      else xswap32(v[e], v[e | (1 << J)]);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void pass1_16(T (&v)[16]) {
+  stage_reg16<0>(v); stage_reg16<1>(v); stage_reg16<2>(v); stage_reg16<3>(v);
+  swap_reg16<0, 16>(v); stage_reg16<0>(v);
+  swap_reg16<1, 32>(v); stage_reg16<1>(v);
+}
+template <typename T>
+__device__ __forceinline__ void pass2_16(T (&v)[16], T sgn8) {
+  stage_reg16<0>(v); stage_reg16<1>(v); stage_reg16<2>(v); stage_reg16<3>(v);
+  swap_reg16<0, 16>(v); stage_reg16<0>(v);
+  swap_reg16<1, 32>(v); stage_reg16<1>(v);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = fma(v[e], sgn8, dpp_xor8(v[e]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
+  constexpr int LB = 13;
+  constexpr int E = 16;
+  constexpr int NT = 512;
+  constexpr int BLO = 1 << LB;
+  constexpr int XLEN = BLO + BLO / 64 + 16;   // padded transpose buffer
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* xbuf = reinterpret_cast<T*>(smem);
+  T* rowA = xbuf + XLEN;
+  T* rowB = rowA + row_pitch<T>(a.n_rows);
+  uint2* exl = reinterpret_cast<uint2*>(rowB + row_pitch<T>(a.n_cols));
+  if (threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
+
+  const int b_hi_bits = a.log2b - LB;
+  const int64_t nunits = (int64_t)a.d << b_hi_bits;
+  const int64_t wg = blockIdx.x;
+  const int64_t total = nunits * a.groups;
+  int64_t lin = wg;
+  if ((total & 7) == 0) lin = (wg & 7) * (total >> 3) + (wg >> 3);
+  const int g = (int)(lin / nunits);
+  const int64_t unit = lin - (int64_t)g * nunits;
+  const int t = (int)(unit >> b_hi_bits);
+  const uint32_t uhi = (uint32_t)(unit & (((int64_t)1 << b_hi_bits) - 1));
+  const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
+  const int64_t k0 = (int64_t)g * k_per;
+  const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
+
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t l4 = (lane >> 4) & 1, l5 = (lane >> 5) & 1, l3 = (lane >> 3) & 1;
+  const uint32_t base1 = (l4 << 4) | (l5 << 5) | ((lane & 15) << 6) | (w << 10);
+  uint32_t fa[E / 2], fb[E / 2];
+  uint32_t nega = 0, negb = 0;
+  {
+    const int32_t* f1 = a.planA.first + (size_t)t * BLO + base1;
+    const int32_t* f2 = a.planB.first + (size_t)t * BLO + base1;
+    const uint32_t* t1 = a.tab1 + (size_t)t * a.n_rows;
+    const uint32_t* t2 = a.tab2 + (size_t)t * a.n_cols;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int32_t r1 = f1[e], r2 = f2[e];
+      const uint32_t en1 = t1[r1 >= 0 ? r1 : 0], en2 = t2[r2 >= 0 ? r2 : 0];
+      const uint32_t s1 = r1 >= 0 ? (en1 >> 31) ^ (__popc(uhi & ((en1 & kBucketMask) >> LB)) & 1u) : 0u;
+      const uint32_t s2 = r2 >= 0 ? (en2 >> 31) ^ (__popc(uhi & ((en2 & kBucketMask) >> LB)) & 1u) : 0u;
+      nega |= s1 << e;
+      negb |= s2 << e;
+      const uint32_t ra = r1 >= 0 ? (uint32_t)r1 : (uint32_t)a.n_rows;
+      const uint32_t rb = r2 >= 0 ? (uint32_t)r2 : (uint32_t)a.n_cols;
+      if (e & 1) { fa[e >> 1] |= ra << 16; fb[e >> 1] |= rb << 16; }
+      else { fa[e >> 1] = ra; fb[e >> 1] = rb; }
+    }
+  }
+  const int32_t* roA = a.planA.roff + (size_t)t * (a.n_rows + 2);
+  const int32_t* roB = a.planB.roff + (size_t)t * (a.n_cols + 2);
+  const int maxrA = a.planA.maxrank[t], maxrB = a.planB.maxrank[t];
+  const int cntA = roA[maxrA + 1], cntB = roB[maxrB + 1];
+  const bool ex_lds = (int64_t)(cntA + cntB) <= a.ex_cap;
+  const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
+  const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
+  const uint2* exA = gA;
+  const uint2* exB = gB;
+  if (ex_lds) {
+    for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gA[q];
+    for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gB[q];
+    exA = exl;
+    exB = exl + cntA;
+  }
+  // transpose addresses: thread part (padded) + register part
+  const uint32_t wr_t = pad16(l4 | (l5 << 1) | ((lane & 15) << 6) | (w << 10));
+  const uint32_t rd_t = pad16((lane & 7) | (w << 3) | (l4 << 10) | (l5 << 11) | (l3 << 12));
+  // register parts: L1' reg bit0 -> 4, bit1 -> 5, bits 2,3 -> 2,3;  L2 reg bits -> 6..9
+  auto wr_e = [](int e) -> uint32_t {
+    return ((uint32_t)(e & 1) << 4) | ((uint32_t)((e >> 1) & 1) << 5) | (uint32_t)(e & 12);
+  };
+  auto rd_e = [](int e) -> uint32_t { return pad16((uint32_t)e << 6); };
+  const T sgn8 = l3 ? T(-1) : T(1);
+
+  T acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = T(0);
+
+  const T* At = reinterpret_cast<const T*>(a.At);
+  const T* Bm = reinterpret_cast<const T*>(a.B);
+  const bool dma = a.dma != 0;
+  if (k0 < k1) {
+    stage_row<T, NT>(rowA, At + k0 * a.n_rows, a.n_rows, dma);
+    stage_row<T, NT>(rowB, Bm + k0 * a.ldb, a.n_cols, dma);
+  }
+  const int maxr = maxrA > maxrB ? maxrA : maxrB;
+  for (int64_t k = k0; k < k1; ++k) {
+    if (dma) wait_dma();
+    __syncthreads();
+    for (int r = 1; r <= maxr; ++r) {
+      if (r <= maxrA) fix_round<T, NT>(rowA, exA, roA[r], roA[r + 1], uhi);
+      if (r <= maxrB) fix_round<T, NT>(rowB, exB, roB[r], roB[r + 1], uhi);
+      __syncthreads();
+    }
+    T X[E], Y[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t ra = (e & 1) ? (fa[e >> 1] >> 16) : (fa[e >> 1] & 0xFFFFu);
+      const uint32_t rb = (e & 1) ? (fb[e >> 1] >> 16) : (fb[e >> 1] & 0xFFFFu);
+      X[e] = flip_sign(rowA[ra], (nega << (31 - e)) & 0x80000000u);
+      Y[e] = flip_sign(rowB[rb], (negb << (31 - e)) & 0x80000000u);
+    }
+    __syncthreads();
+    if (k + 1 < k1) {
+      stage_row<T, NT>(rowA, At + (k + 1) * a.n_rows, a.n_rows, dma);
+      stage_row<T, NT>(rowB, Bm + (k + 1) * a.ldb, a.n_cols, dma);
+    }
+    pass1_16(X);
+    pass1_16(Y);
+#pragma unroll
+    for (int e = 0; e < E; ++e) xbuf[wr_t + wr_e(e)] = X[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) X[e] = xbuf[rd_t + rd_e(e)];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xbuf[wr_t + wr_e(e)] = Y[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) Y[e] = xbuf[rd_t + rd_e(e)];
+    pass2_16(X, sgn8);
+    pass2_16(Y, sgn8);
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = fma(X[e], Y[e], acc[e]);
+  }
+  // final layout L2': reg bit0 -> 10, bit1 -> 11, bits 2,3 -> 8,9;
+  // lane bit4 -> 6, bit5 -> 7, bit3 -> 12, bits 0..2 -> 0..2; waves -> 3..5
+  const int64_t b = (int64_t)1 << a.log2b;
+  double* dst = a.partial + ((size_t)g * a.d + t) * b + ((int64_t)uhi << LB);
+  const uint32_t fin_t = (lane & 7) | (w << 3) | (l4 << 6) | (l5 << 7) | (l3 << 12);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint32_t fe = ((uint32_t)(e & 1) << 10) | ((uint32_t)((e >> 1) & 1) << 11) |
+                        ((uint32_t)((e >> 2) & 3) << 8);
+    dst[fin_t | fe] = (double)acc[e];
+  }
+}
+
 }  // namespace
 
 // Host-side helpers used by the estimate driver.
 size_t plan_bytes(int d, int64_t n, int lb) {
   const size_t blo = (size_t)1 << lb;
   size_t s = 0;
-  s += align_up(sizeof(int32_t) * d * blo, 256);          // first
-  s += align_up(sizeof(uint32_t) * d * (size_t)n, 256);   // extras
-  s += align_up(sizeof(uint32_t) * d * (size_t)n, 256);   // meta
-  s += align_up(sizeof(int32_t) * d * (size_t)(n + 2), 256);  // roff
-  s += align_up(sizeof(int32_t) * d, 256);                // maxrank
-  s += align_up(sizeof(int32_t) * d * (size_t)n, 256);    // rank
+  s += align_up(sizeof(int32_t) * d * blo, 256);               // first
+  s += align_up(sizeof(uint2) * d * (size_t)n, 256);           // pairs
+  s += align_up(sizeof(int32_t) * d * (size_t)(n + 2), 256);   // roff
+  s += align_up(sizeof(int32_t) * d, 256);                     // maxrank
+  s += align_up(sizeof(int32_t) * d * (size_t)n, 256);         // cursor
   return s;
 }
 
@@ -451,35 +682,51 @@ PlanView carve_plan(char* p, int d, int64_t n, int lb) {
   const size_t blo = (size_t)1 << lb;
   PlanView v;
   v.first = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d * blo, 256);
-  v.extras = reinterpret_cast<uint32_t*>(p); p += align_up(sizeof(uint32_t) * d * (size_t)n, 256);
-  v.meta = reinterpret_cast<uint32_t*>(p); p += align_up(sizeof(uint32_t) * d * (size_t)n, 256);
+  v.pairs = reinterpret_cast<uint2*>(p); p += align_up(sizeof(uint2) * d * (size_t)n, 256);
   v.roff = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d * (size_t)(n + 2), 256);
   v.maxrank = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d, 256);
-  v.rank = reinterpret_cast<int32_t*>(p);
+  v.cursor = reinterpret_cast<int32_t*>(p);
   return v;
+}
+
+size_t plan_lds_bytes(int64_t n, int lb) {
+  return sizeof(int32_t) * (2 * ((size_t)1 << lb) + (size_t)n + 2);
 }
 
 cmm_status launch_plan(const uint32_t* tab, int d, int64_t n, int lb, const PlanView& pv,
                        hipStream_t s) {
   ProfScope prof_("plan", s);
-  const size_t lds = sizeof(int32_t) * (((size_t)1 << lb) > (size_t)(n + 2) ? ((size_t)1 << lb)
-                                                                           : (size_t)(n + 2));
+  const size_t lds = plan_lds_bytes(n, lb);
   if (lds > 160 * 1024) {
-    set_error("plan: too many indices for the LDS counters");
+    set_error("plan: too many indices for the LDS rank arrays");
     return CMM_EUNSUPPORTED;
   }
   hipError_t e = hipFuncSetAttribute((const void*)plan_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_check(e, "plan: set LDS size");
-  hipLaunchKernelGGL(plan_kernel, dim3(d), dim3(kPlanWave), lds, s, tab, n, lb, pv);
+  hipLaunchKernelGGL(plan_kernel, dim3(d), dim3(kPlanThreads), lds, s, tab, n, lb, pv);
   return hip_check(hipGetLastError(), "plan kernel launch");
 }
 
 template <typename T, int LB>
-static cmm_status launch_compress_t(const CompressArgs& a, hipStream_t s) {
+static cmm_status launch_compress_t(const CompressArgs& a0, hipStream_t s) {
   ProfScope prof_("compress", s);
+  CompressArgs a = a0;
   const int64_t blocks = ((int64_t)a.d << (a.log2b - LB)) * a.groups;
-  const size_t lds = sizeof(T) * (((size_t)1 << LB) + (size_t)a.n_rows + (size_t)a.n_cols);
+  const size_t base = sizeof(T) * (((size_t)1 << LB) + ((size_t)1 << (LB - 7)) +
+                                   (size_t)row_pitch<T>(a.n_rows) + (size_t)row_pitch<T>(a.n_cols));
+  const size_t kMax = 160 * 1024;
+  if (base > kMax) { set_error("compress: rows do not fit in LDS"); return CMM_EUNSUPPORTED; }
+  // LDS left for the non-first-row lists (8 bytes per entry)
+  int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
+  const int64_t want = a.n_rows + a.n_cols;
+  if (cap > want) cap = want;
+  a.ex_cap = cap;
+  const size_t lds = base + sizeof(uint2) * (size_t)cap;
+  // 16-byte asynchronous row copies need 16-byte aligned rows
+  constexpr int V = 16 / sizeof(T);
+  a.dma = (a.n_rows % V == 0) && (a.n_cols % V == 0) && (a.ldb % V == 0) &&
+          ((uintptr_t)a.At % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
   auto kern = compress_kernel<T, LB>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
@@ -488,12 +735,41 @@ static cmm_status launch_compress_t(const CompressArgs& a, hipStream_t s) {
   return hip_check(hipGetLastError(), "compress kernel launch");
 }
 
+template <typename T>
+static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
+  ProfScope prof_("compress", s);
+  CompressArgs a = a0;
+  constexpr int LB = 13;
+  const int64_t blocks = ((int64_t)a.d << (a.log2b - LB)) * a.groups;
+  const size_t xlen = ((size_t)1 << LB) + ((size_t)1 << (LB - 6)) + 16;
+  const size_t base = sizeof(T) * (xlen + (size_t)row_pitch<T>(a.n_rows) +
+                                   (size_t)row_pitch<T>(a.n_cols));
+  const size_t kMax = 160 * 1024;
+  if (base > kMax) { set_error("compress: rows do not fit in LDS"); return CMM_EUNSUPPORTED; }
+  int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
+  const int64_t want = a.n_rows + a.n_cols;
+  if (cap > want) cap = want;
+  a.ex_cap = cap;
+  const size_t lds = base + sizeof(uint2) * (size_t)cap;
+  constexpr int V = 16 / sizeof(T);
+  a.dma = (a.n_rows % V == 0) && (a.n_cols % V == 0) && (a.ldb % V == 0) &&
+          ((uintptr_t)a.At % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
+  auto kern = compress16_kernel<T>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return hip_check(e, "compress: set LDS size");
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(512), lds, s, a);
+  return hip_check(hipGetLastError(), "compress kernel launch");
+}
+
 cmm_status launch_compress(const CompressArgs& a, cmm_dtype dt, int lb, hipStream_t s) {
   if (dt == CMM_F64) {
     switch (lb) {
       case 11: return launch_compress_t<double, 11>(a, s);
       case 12: return launch_compress_t<double, 12>(a, s);
-      case 13: return launch_compress_t<double, 13>(a, s);
+      case 13:
+        if (a.variant == 1) return launch_compress_t<double, 13>(a, s);
+        return launch_compress16<double>(a, s);
     }
   } else {
     switch (lb) {
