@@ -86,10 +86,10 @@ cmm_status launch_reduce_partials(const double* parts, int g, size_t len, double
 struct PlanView {
   int32_t* first;     // [d][b_lo]  lowest index in each lo-bucket, or -1
   uint2* pairs;       // [d][n]     (index | first << 16, hi-bits xor | sign xor << 31)
-                      //            of every non-first index, grouped by rank
-  int32_t* roff;      // [d][n + 2] start of each rank in pairs
-  int32_t* maxrank;   // [d]
-  int32_t* cursor;    // [d][n]     scratch: per-rank placement cursors
+                      //            of every non-first index, bucket by bucket,
+                      //            each bucket's chain in ascending index order
+  int32_t* cstart;    // [d][n + 2] start of each chain in pairs (+ end sentinel)
+  int32_t* nchains;   // [d]        number of buckets with two or more indices
 };
 
 struct CompressArgs {

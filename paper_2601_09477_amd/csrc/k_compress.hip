@@ -50,7 +50,30 @@ constexpr int32_t kNone = 0x7FFFFFFF;
 // rank[n] (int32).  Rank rounds: round 0 takes the lowest index of every
 // lo-bucket (atomicMin, order independent); round r takes the lowest index
 // among those not yet ranked.  Hence rank(i) = number of lower indices in
-// the same lo-bucket, computed deterministically.
+// the same lo-bucket, computed deterministically.  The non-first indices
+// are then laid out bucket by bucket (a "chain" per bucket with two or
+// more indices), each chain in rank order.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* tmp, int32_t* total) {
+  // 1024 threads: inclusive scan within wavefronts, then over wave sums
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) tmp[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t acc = 0;
+    for (int q = 0; q < kPlanThreads / 64; ++q) { const int32_t s = tmp[q]; tmp[q] = acc; acc += s; }
+    *total = acc;
+  }
+  __syncthreads();
+  const int32_t r = x - v + tmp[wv];
+  __syncthreads();
+  return r;
+}
+
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const uint32_t* __restrict__ tab,
                                                             int64_t n, int lb, PlanView pv) {
   const int t = blockIdx.x;
@@ -59,19 +82,18 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const uint32_t* __re
   const uint32_t lomask = (uint32_t)blo - 1u;
   const uint32_t* tb = tab + (size_t)t * n;
   int32_t* first = pv.first + (size_t)t * blo;
-  int32_t* roff = pv.roff + (size_t)t * (n + 2);
+  int32_t* cstart = pv.cstart + (size_t)t * (n + 2);
+  uint2* pairs = pv.pairs + (size_t)t * n;
   extern __shared__ int32_t sh[];
-  int32_t* cur = sh;                // [b_lo]
-  int32_t* nxt = sh + blo;          // [b_lo]
+  int32_t* cur = sh;                // [b_lo]  first index per bucket
+  int32_t* nxt = sh + blo;          // [b_lo]  scratch, then counts, then chain offsets
   int32_t* rank = sh + 2 * blo;     // [n]
-  int32_t* flags = rank + n;        // [2]: more, maxrank
-  int32_t& s_more = flags[0];
-  int32_t& s_maxr = flags[1];
-  int32_t* cursor = pv.cursor + (size_t)t * n;   // global per-rank cursors
+  int32_t* misc = rank + n;         // [2 + 16]: more, total, wave sums
+  int32_t& s_more = misc[0];
+  int32_t* s_total = misc + 1;
+  int32_t* wsum = misc + 2;
   for (int r = tid; r < blo; r += kPlanThreads) cur[r] = kNone;
   for (int64_t i = tid; i < n; i += kPlanThreads) rank[i] = -1;
-  for (int64_t r = tid; r < n + 2; r += kPlanThreads) roff[r] = 0;
-  if (tid == 0) s_maxr = 0;
   __syncthreads();
   for (int64_t i = tid; i < n; i += kPlanThreads) atomicMin(&cur[tb[i] & lomask], (int32_t)i);
   __syncthreads();
@@ -88,35 +110,54 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const uint32_t* __re
     for (int64_t i = tid; i < n; i += kPlanThreads)
       if (rank[i] < 0 && nxt[tb[i] & lomask] == (int32_t)i) { rank[i] = round; s_more = 1; }
     __syncthreads();
-    if (!s_more) { if (tid == 0) s_maxr = round - 1; break; }
+    const int more = s_more;
     __syncthreads();   // everyone read s_more before it is reset
+    if (!more) break;
   }
+  // rows per bucket
+  for (int r = tid; r < blo; r += kPlanThreads) nxt[r] = 0;
   __syncthreads();
-  const int maxr = s_maxr;
-  if (tid == 0) pv.maxrank[t] = maxr;
-  // counts of each rank >= 1 (global roff as the histogram), prefix sums
-  for (int64_t i = tid; i < n; i += kPlanThreads)
-    if (rank[i] >= 1) atomicAdd(&roff[rank[i] + 1], 1);
+  for (int64_t i = tid; i < n; i += kPlanThreads) atomicAdd(&nxt[tb[i] & lomask], 1);
   __syncthreads();
+  // each thread owns a run of consecutive buckets: chain lengths and count
+  const int per = blo / kPlanThreads > 0 ? blo / kPlanThreads : 1;
+  const int r0 = tid * per;
+  int32_t len_sum = 0, chains = 0;
+  for (int r = r0; r < r0 + per && r < blo; ++r) {
+    const int32_t c = nxt[r];
+    if (c >= 2) { len_sum += c - 1; chains += 1; }
+  }
+  const int32_t off0 = block_exclusive_scan(len_sum, wsum, s_total);
+  const int32_t total_extras = *s_total;
+  const int32_t ch0 = block_exclusive_scan(chains, wsum, s_total);
+  const int32_t total_chains = *s_total;
+  // chain starts and per-bucket offsets (nxt[r] becomes the bucket's offset)
+  {
+    int32_t off = off0, ch = ch0;
+    for (int r = r0; r < r0 + per && r < blo; ++r) {
+      const int32_t c = nxt[r];
+      if (c >= 2) {
+        cstart[ch] = off;
+        nxt[r] = off;
+        off += c - 1;
+        ch += 1;
+      }
+    }
+  }
   if (tid == 0) {
-    int32_t acc = 0;
-    for (int r = 0; r <= maxr + 1; ++r) { acc += roff[r]; roff[r] = acc; }
+    cstart[total_chains] = total_extras;
+    pv.nchains[t] = total_chains;
   }
-  __syncthreads();
-  // placement through per-rank cursors (ranks 1 .. maxr <= n - 1); the order
-  // inside one rank is irrelevant because its targets are distinct buckets
-  for (int r = tid; r <= maxr && r < n; r += kPlanThreads) cursor[r] = 0;
   __syncthreads();
   for (int64_t i = tid; i < n; i += kPlanThreads) {
     const int rk = rank[i];
     if (rk >= 1) {
       const uint32_t e = tb[i];
-      const int32_t f = cur[e & lomask];          // round-0 winner = first index
+      const int32_t f = cur[e & lomask];
       const uint32_t ef = tb[f];
-      const int pos = roff[rk] + atomicAdd(&cursor[rk], 1);
       const uint32_t hx = ((e & kBucketMask) >> lb) ^ ((ef & kBucketMask) >> lb);
-      pv.pairs[(size_t)t * n + pos] = make_uint2((uint32_t)i | ((uint32_t)f << 16),
-                                                 hx | ((e ^ ef) & kSignBit));
+      pairs[nxt[e & lomask] + rk - 1] =
+          make_uint2((uint32_t)i | ((uint32_t)f << 16), hx | ((e ^ ef) & kSignBit));
     }
   }
 }
@@ -313,15 +354,49 @@ __device__ __forceinline__ float flip_sign(float x, uint32_t m) {
 
 __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// One rank round of the non-first rows of one operand: row[target] += +-row[index].
+// The non-first rows of one operand, bucket by bucket: a thread takes one
+// bucket's chain and adds its rows onto the bucket's first row in rank
+// (ascending index) order, row[first] += +-row[index], so every bucket
+// receives its rows left to right without atomics.  Entries are fetched
+// four at a time (independent loads) and two chains are in flight per
+// thread, so a chain costs a few LDS round trips instead of two per row.
+template <typename T>
+__device__ __forceinline__ T chain_sum(const T* __restrict__ row, const uint2* __restrict__ ex,
+                                       int beg, int end, uint32_t uhi, T accv) {
+  for (int q0 = beg; q0 < end; q0 += 4) {
+    uint2 x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = (q0 + j < end) ? ex[q0 + j] : make_uint2(0u, 0u);
+    T v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = (q0 + j < end) ? row[x[j].x & 0xFFFFu] : T(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (q0 + j < end) {
+        const uint32_t neg = (x[j].y >> 31) ^ (__popc(uhi & (x[j].y & kBucketMask)) & 1u);
+        accv = accv + (neg ? -v[j] : v[j]);
+      }
+    }
+  }
+  return accv;
+}
+
 template <typename T, int NT>
-__device__ __forceinline__ void fix_round(T* __restrict__ row, const uint2* __restrict__ ex,
-                                          int beg, int end, uint32_t uhi) {
-  for (int q = beg + (int)threadIdx.x; q < end; q += NT) {
-    const uint2 x = ex[q];
-    const uint32_t neg = (x.y >> 31) ^ (__popc(uhi & (x.y & kBucketMask)) & 1u);
-    const T v = row[x.x & 0xFFFFu];
-    row[x.x >> 16] = row[x.x >> 16] + (neg ? -v : v);
+__device__ __forceinline__ void fix_chains(T* __restrict__ row, const uint2* __restrict__ ex,
+                                           const int32_t* __restrict__ cs, int nch,
+                                           uint32_t uhi) {
+  for (int c = threadIdx.x; c < nch; c += 2 * NT) {
+    const int c2 = c + NT;
+    const int b1 = cs[c], e1 = cs[c + 1];
+    const int b2 = c2 < nch ? cs[c2] : 0, e2 = c2 < nch ? cs[c2 + 1] : 0;
+    const uint32_t t1 = ex[b1].x >> 16;
+    const uint32_t t2 = c2 < nch ? ex[b2].x >> 16 : 0u;
+    const T a1 = row[t1];
+    const T a2 = c2 < nch ? row[t2] : T(0);
+    const T s1 = chain_sum(row, ex, b1, e1, uhi, a1);
+    const T s2 = chain_sum(row, ex, b2, e2, uhi, a2);
+    row[t1] = s1;
+    if (c2 < nch) row[t2] = s2;
   }
 }
 
@@ -381,20 +456,28 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a
     }
   }
   // Non-first rows (constant over k): copied once into LDS when they fit.
-  const int32_t* roA = a.planA.roff + (size_t)t * (a.n_rows + 2);
-  const int32_t* roB = a.planB.roff + (size_t)t * (a.n_cols + 2);
-  const int maxrA = a.planA.maxrank[t], maxrB = a.planB.maxrank[t];
-  const int cntA = roA[maxrA + 1], cntB = roB[maxrB + 1];
-  const bool ex_lds = (int64_t)(cntA + cntB) <= a.ex_cap;
+  const int32_t* gcA = a.planA.cstart + (size_t)t * (a.n_rows + 2);
+  const int32_t* gcB = a.planB.cstart + (size_t)t * (a.n_cols + 2);
+  const int nchA = a.planA.nchains[t], nchB = a.planB.nchains[t];
+  const int cntA = gcA[nchA], cntB = gcB[nchB];
+  // entries (8 bytes) plus chain starts (4 bytes each, two per 8-byte slot)
+  const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
   const uint2* exA;
   const uint2* exB;
   const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
   const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
+  const int32_t* csA = gcA;
+  const int32_t* csB = gcB;
   if (ex_lds) {
     for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gA[q];
     for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gB[q];
+    int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
+    for (int q = threadIdx.x; q <= nchA; q += NT) csl[q] = gcA[q];
+    for (int q = threadIdx.x; q <= nchB; q += NT) csl[nchA + 1 + q] = gcB[q];
     exA = exl;
     exB = exl + cntA;
+    csA = csl;
+    csB = csl + nchA + 1;
   } else {
     exA = gA;
     exB = gB;
@@ -414,15 +497,15 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a
     stage_row<T, NT>(rowA, At + k0 * a.n_rows, a.n_rows, dma);
     stage_row<T, NT>(rowB, Bm + k0 * a.ldb, a.n_cols, dma);
   }
-  const int maxr = maxrA > maxrB ? maxrA : maxrB;
+
 
   for (int64_t k = k0; k < k1; ++k) {
     if (dma) wait_dma();
     __syncthreads();
     // rank rounds of both operands share the barriers
-    for (int r = 1; r <= maxr; ++r) {
-      if (r <= maxrA) fix_round<T, NT>(rowA, exA, roA[r], roA[r + 1], uhi);
-      if (r <= maxrB) fix_round<T, NT>(rowB, exB, roB[r], roB[r + 1], uhi);
+    if (nchA + nchB > 0) {
+      fix_chains<T, NT>(rowA, exA, csA, nchA, uhi);
+      fix_chains<T, NT>(rowB, exB, csB, nchB, uhi);
       __syncthreads();
     }
     T X[E], Y[E];
@@ -554,7 +637,9 @@ __global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t l4 = (lane >> 4) & 1, l5 = (lane >> 5) & 1, l3 = (lane >> 3) & 1;
   const uint32_t base1 = (l4 << 4) | (l5 << 5) | ((lane & 15) << 6) | (w << 10);
-  uint32_t fa[E / 2], fb[E / 2];
+  // byte offsets (from the LDS base) of the gather sources of the thread's
+  // 16 buckets, and their folded signs
+  uint32_t offA[E], offB[E];
   uint32_t nega = 0, negb = 0;
   {
     const int32_t* f1 = a.planA.first + (size_t)t * BLO + base1;
@@ -571,24 +656,35 @@ __global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
       negb |= s2 << e;
       const uint32_t ra = r1 >= 0 ? (uint32_t)r1 : (uint32_t)a.n_rows;
       const uint32_t rb = r2 >= 0 ? (uint32_t)r2 : (uint32_t)a.n_cols;
-      if (e & 1) { fa[e >> 1] |= ra << 16; fb[e >> 1] |= rb << 16; }
-      else { fa[e >> 1] = ra; fb[e >> 1] = rb; }
+      offA[e] = (uint32_t)((const unsigned char*)(rowA + ra) - smem);
+      offB[e] = (uint32_t)((const unsigned char*)(rowB + rb) - smem);
     }
   }
-  const int32_t* roA = a.planA.roff + (size_t)t * (a.n_rows + 2);
-  const int32_t* roB = a.planB.roff + (size_t)t * (a.n_cols + 2);
-  const int maxrA = a.planA.maxrank[t], maxrB = a.planB.maxrank[t];
-  const int cntA = roA[maxrA + 1], cntB = roB[maxrB + 1];
-  const bool ex_lds = (int64_t)(cntA + cntB) <= a.ex_cap;
+  const int32_t* gcA = a.planA.cstart + (size_t)t * (a.n_rows + 2);
+  const int32_t* gcB = a.planB.cstart + (size_t)t * (a.n_cols + 2);
+  const int nchA = a.planA.nchains[t], nchB = a.planB.nchains[t];
+  const int cntA = gcA[nchA], cntB = gcB[nchB];
+  // entries (8 bytes) plus chain starts (4 bytes each, two per 8-byte slot)
+  const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
+  const uint2* exA;
+  const uint2* exB;
   const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
   const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
-  const uint2* exA = gA;
-  const uint2* exB = gB;
+  const int32_t* csA = gcA;
+  const int32_t* csB = gcB;
   if (ex_lds) {
     for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gA[q];
     for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gB[q];
+    int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
+    for (int q = threadIdx.x; q <= nchA; q += NT) csl[q] = gcA[q];
+    for (int q = threadIdx.x; q <= nchB; q += NT) csl[nchA + 1 + q] = gcB[q];
     exA = exl;
     exB = exl + cntA;
+    csA = csl;
+    csB = csl + nchA + 1;
+  } else {
+    exA = gA;
+    exB = gB;
   }
   // transpose addresses: thread part (padded) + register part
   const uint32_t wr_t = pad16(l4 | (l5 << 1) | ((lane & 15) << 6) | (w << 10));
@@ -607,49 +703,61 @@ __global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
   const T* At = reinterpret_cast<const T*>(a.At);
   const T* Bm = reinterpret_cast<const T*>(a.B);
   const bool dma = a.dma != 0;
-  if (k0 < k1) {
-    stage_row<T, NT>(rowA, At + k0 * a.n_rows, a.n_rows, dma);
-    stage_row<T, NT>(rowB, Bm + k0 * a.ldb, a.n_cols, dma);
-  }
-  const int maxr = maxrA > maxrB ? maxrA : maxrB;
-  for (int64_t k = k0; k < k1; ++k) {
-    if (dma) wait_dma();
-    __syncthreads();
-    for (int r = 1; r <= maxr; ++r) {
-      if (r <= maxrA) fix_round<T, NT>(rowA, exA, roA[r], roA[r + 1], uhi);
-      if (r <= maxrB) fix_round<T, NT>(rowB, exB, roB[r], roB[r + 1], uhi);
-      __syncthreads();
-    }
-    T X[E], Y[E];
+  T X[E], Y[E];
+  // Rows of k are staged, fixed up and gathered into X, Y before the
+  // iteration that transforms them; the gather of k + 1 closes iteration k.
+  auto load_k = [&](int64_t kk) {
+    stage_row<T, NT>(rowA, At + kk * a.n_rows, a.n_rows, dma);
+    stage_row<T, NT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
+  };
+  auto fixups = [&]() {
+    fix_chains<T, NT>(rowA, exA, csA, nchA, uhi);
+    fix_chains<T, NT>(rowB, exB, csB, nchB, uhi);
+  };
+  auto gather = [&]() {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const uint32_t ra = (e & 1) ? (fa[e >> 1] >> 16) : (fa[e >> 1] & 0xFFFFu);
-      const uint32_t rb = (e & 1) ? (fb[e >> 1] >> 16) : (fb[e >> 1] & 0xFFFFu);
-      X[e] = flip_sign(rowA[ra], (nega << (31 - e)) & 0x80000000u);
-      Y[e] = flip_sign(rowB[rb], (negb << (31 - e)) & 0x80000000u);
+      X[e] = flip_sign(*reinterpret_cast<const T*>(smem + offA[e]), (nega << (31 - e)) & 0x80000000u);
+      Y[e] = flip_sign(*reinterpret_cast<const T*>(smem + offB[e]), (negb << (31 - e)) & 0x80000000u);
     }
+  };
+  if (k0 < k1) {
+    load_k(k0);
+    if (dma) wait_dma();
     __syncthreads();
-    if (k + 1 < k1) {
-      stage_row<T, NT>(rowA, At + (k + 1) * a.n_rows, a.n_rows, dma);
-      stage_row<T, NT>(rowB, Bm + (k + 1) * a.ldb, a.n_cols, dma);
-    }
+    fixups();
+    __syncthreads();
+    gather();
+  }
+  for (int64_t k = k0; k < k1; ++k) {
+    const bool more = k + 1 < k1;
+    __syncthreads();   // every gather of k is done: the row buffers can be refilled
+    if (more) load_k(k + 1);
     pass1_16(X);
-    pass1_16(Y);
 #pragma unroll
     for (int e = 0; e < E; ++e) xbuf[wr_t + wr_e(e)] = X[e];
     __syncthreads();
+    // the transposed reads of X overlap pass 1 of Y
 #pragma unroll
     for (int e = 0; e < E; ++e) X[e] = xbuf[rd_t + rd_e(e)];
+    pass1_16(Y);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) xbuf[wr_t + wr_e(e)] = Y[e];
-    __syncthreads();
+    if (more && dma) wait_dma();
+    __syncthreads();   // Y transposed and the rows of k + 1 have landed
 #pragma unroll
     for (int e = 0; e < E; ++e) Y[e] = xbuf[rd_t + rd_e(e)];
+    // the collision fix-ups of k + 1 run while other waves do pass 2 of k
+    if (more) fixups();
     pass2_16(X, sgn8);
     pass2_16(Y, sgn8);
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = fma(X[e], Y[e], acc[e]);
+    if (more) {
+      __syncthreads();
+      gather();
+    }
   }
   // final layout L2': reg bit0 -> 10, bit1 -> 11, bits 2,3 -> 8,9;
   // lane bit4 -> 6, bit5 -> 7, bit3 -> 12, bits 0..2 -> 0..2; waves -> 3..5
@@ -672,9 +780,8 @@ size_t plan_bytes(int d, int64_t n, int lb) {
   size_t s = 0;
   s += align_up(sizeof(int32_t) * d * blo, 256);               // first
   s += align_up(sizeof(uint2) * d * (size_t)n, 256);           // pairs
-  s += align_up(sizeof(int32_t) * d * (size_t)(n + 2), 256);   // roff
-  s += align_up(sizeof(int32_t) * d, 256);                     // maxrank
-  s += align_up(sizeof(int32_t) * d * (size_t)n, 256);         // cursor
+  s += align_up(sizeof(int32_t) * d * (size_t)(n + 2), 256);   // cstart
+  s += align_up(sizeof(int32_t) * d, 256);                     // nchains
   return s;
 }
 
@@ -683,14 +790,13 @@ PlanView carve_plan(char* p, int d, int64_t n, int lb) {
   PlanView v;
   v.first = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d * blo, 256);
   v.pairs = reinterpret_cast<uint2*>(p); p += align_up(sizeof(uint2) * d * (size_t)n, 256);
-  v.roff = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d * (size_t)(n + 2), 256);
-  v.maxrank = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d, 256);
-  v.cursor = reinterpret_cast<int32_t*>(p);
+  v.cstart = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d * (size_t)(n + 2), 256);
+  v.nchains = reinterpret_cast<int32_t*>(p);
   return v;
 }
 
 size_t plan_lds_bytes(int64_t n, int lb) {
-  return sizeof(int32_t) * (2 * ((size_t)1 << lb) + (size_t)n + 2);
+  return sizeof(int32_t) * (2 * ((size_t)1 << lb) + (size_t)n + 2 + kPlanThreads / 64);
 }
 
 cmm_status launch_plan(const uint32_t* tab, int d, int64_t n, int lb, const PlanView& pv,
