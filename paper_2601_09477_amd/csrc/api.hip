@@ -85,6 +85,7 @@ cmm_status check_d(int d, const char* fn) {
 // the workspace in this order.
 struct EstimatePlan {
   bool fused = false;
+  bool mfma = false;   // precision form (bf16 / fp16 on the matrix cores)
   int lb = 0;          // log2 b_lo of the fused kernel
   int groups = 1;      // k-ranges of the fused kernel
   int64_t kc = 0;      // k-chunk of the composed path
@@ -120,6 +121,18 @@ cmm_status validate_problem(const cmm_problem* pr, const char* fn) {
   if (pr->n_inner > 0 && pr->n_cols > 0 && !pr->B) return invalid(std::string(fn) + ": B is null");
   if ((pr->n_rows > 0 && !pr->tab1) || (pr->n_cols > 0 && !pr->tab2))
     return invalid(std::string(fn) + ": tab1 / tab2 must be given (outputs when keys != NULL)");
+  if (pr->compute == CMM_BF16 || pr->compute == CMM_F16) {
+    if (pr->log2b < 14) {
+      set_error(std::string(fn) + ": the bf16/f16 precision form needs log2b >= 14");
+      return CMM_EUNSUPPORTED;
+    }
+    if (pr->n_rows > 65534 || pr->n_cols > 65534 ||
+        (2 * 16384 + (pr->n_rows + 8) / 8 * 8 + (pr->n_cols + 8) / 8 * 8) * 2 > 160 * 1024 ||
+        plan_lds_bytes(pr->n_rows, 14) > 160 * 1024 || plan_lds_bytes(pr->n_cols, 14) > 160 * 1024) {
+      set_error(std::string(fn) + ": the bf16/f16 precision form needs n_rows + n_cols <= 32752");
+      return CMM_EUNSUPPORTED;
+    }
+  }
   if (pr->C_hat) {
     if (!is_f64_or_f32(pr->out_dtype))
       return invalid(std::string(fn) + ": out_dtype must be CMM_F64 or CMM_F32");
@@ -134,15 +147,38 @@ EstimatePlan make_plan(const cmm_problem* pr) {
   const size_t es = dtype_size(P.cdt);
   const int64_t b = (int64_t)1 << pr->log2b;
   const int d = pr->d;
+  if (pr->compute == CMM_BF16 || pr->compute == CMM_F16) {
+    // precision form: b_lo = 2^14, low-precision operand copies in the workspace
+    P.mfma = true;
+    P.fused = true;
+    P.lb = 14;
+    const int64_t units = (int64_t)d << (pr->log2b - 14);
+    int64_t g = (2048 + units - 1) / units;
+    if (g > pr->n_inner) g = pr->n_inner;
+    if (g < 1) g = 1;
+    while (g > 1 && ((units * g) & 7) != 0 && g < pr->n_inner) ++g;
+    P.groups = (int)g;
+    size_t off = 0;
+    P.off_at = off; off = align_up(off + 2 * (size_t)pr->n_rows * pr->n_inner, 256);
+    P.off_bc = off; off = align_up(off + 2 * (size_t)pr->n_inner * pr->n_cols, 256);
+    P.off_planA = off; off = align_up(off + plan_bytes(d, pr->n_rows, 14), 256);
+    P.off_planB = off; off = align_up(off + plan_bytes(d, pr->n_cols, 14), 256);
+    P.off_part = off; off = align_up(off + sizeof(double) * (size_t)P.groups * d * b, 256);
+    P.off_p = off; off = align_up(off + sizeof(double) * (size_t)d * b, 256);
+    P.bytes = off;
+    return P;
+  }
   // fused path: b_lo = 2^lb with 11 <= lb <= log2b; LDS holds the transpose
   // buffer and one staged row of each operand.
   const int lb_max = P.cdt == CMM_F64 ? 13 : 14;
   int lb = pr->log2b < lb_max ? pr->log2b : lb_max;
   auto fits = [&](int l) {
     const size_t v = 16 / es;
-    const size_t rows = ((size_t)1 << l) + ((size_t)1 << (l - 7)) +
-                        ((size_t)pr->n_rows + v) / v * v + ((size_t)pr->n_cols + v) / v * v;
-    return rows * es <= kLdsBytes && plan_lds_bytes(pr->n_rows, l) <= kLdsBytes &&
+    const size_t ra = ((size_t)pr->n_rows + v) / v * v, rb = ((size_t)pr->n_cols + v) / v * v;
+    // the float64 b_lo = 2^13 kernel can also time-share one row buffer
+    const size_t rows = (P.cdt == CMM_F64 && l == 13) ? (ra > rb ? ra : rb) : ra + rb;
+    const size_t xb = ((size_t)1 << l) + ((size_t)1 << (l - 6)) + 16;
+    return (xb + rows) * es <= kLdsBytes && plan_lds_bytes(pr->n_rows, l) <= kLdsBytes &&
            plan_lds_bytes(pr->n_cols, l) <= kLdsBytes;
   };
   while (lb >= 11 && !fits(lb)) --lb;
@@ -197,6 +233,37 @@ cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
   double* p = pr->p ? pr->p : reinterpret_cast<double*>(ws + P.off_p);
   if (pr->n_inner == 0 || pr->n_rows == 0 || pr->n_cols == 0) {
     if ((st = launch_zero(p, (size_t)d * b, s)) != CMM_OK) return st;
+  } else if (P.mfma) {
+    void* At = ws + P.off_at;
+    void* Bc = ws + P.off_bc;
+    st = launch_lp_copy(pr->A, pr->in_dtype, pr->n_rows, pr->n_inner, pr->lda, At, pr->compute,
+                        true, s);
+    if (st != CMM_OK) return st;
+    st = launch_lp_copy(pr->B, pr->in_dtype, pr->n_inner, pr->n_cols, pr->ldb, Bc, pr->compute,
+                        false, s);
+    if (st != CMM_OK) return st;
+    CompressArgs a;
+    a.At = At;
+    a.B = Bc;
+    a.ldb = pr->n_cols;
+    a.n_rows = pr->n_rows;
+    a.n_cols = pr->n_cols;
+    a.n_inner = pr->n_inner;
+    a.tab1 = pr->tab1;
+    a.tab2 = pr->tab2;
+    a.planA = carve_plan(ws + P.off_planA, d, pr->n_rows, P.lb);
+    a.planB = carve_plan(ws + P.off_planB, d, pr->n_cols, P.lb);
+    a.d = d;
+    a.log2b = pr->log2b;
+    a.groups = P.groups;
+    a.partial = reinterpret_cast<double*>(ws + P.off_part);
+    a.ex_cap = 0;
+    a.dma = 0;
+    a.variant = 0;
+    if ((st = launch_plan(pr->tab1, d, pr->n_rows, P.lb, a.planA, s)) != CMM_OK) return st;
+    if ((st = launch_plan(pr->tab2, d, pr->n_cols, P.lb, a.planB, s)) != CMM_OK) return st;
+    if ((st = launch_compress_mfma(a, pr->compute, s)) != CMM_OK) return st;
+    if ((st = launch_reduce_partials(a.partial, P.groups, (size_t)d * b, p, s)) != CMM_OK) return st;
   } else if (P.fused) {
     void* At = ws + P.off_at;
     st = launch_transpose(pr->A, pr->in_dtype, pr->n_rows, pr->n_inner, pr->lda, At, P.cdt, s);
@@ -405,10 +472,6 @@ cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes) {
   cmm_status s = validate_problem(prob, "cmm_workspace_size");
   if (s != CMM_OK) return s;
   if (!bytes) return invalid("cmm_workspace_size: bytes is null");
-  if (prob->compute == CMM_BF16 || prob->compute == CMM_F16) {
-    set_error("cmm_workspace_size: the bf16/f16 precision form is not built yet");
-    return CMM_EUNSUPPORTED;
-  }
   *bytes = make_plan(prob).bytes;
   return CMM_OK;
 }
@@ -417,10 +480,6 @@ cmm_status cmm_estimate(const cmm_problem* prob, void* workspace, size_t workspa
                         void* stream) {
   cmm_status s = validate_problem(prob, "cmm_estimate");
   if (s != CMM_OK) return s;
-  if (prob->compute == CMM_BF16 || prob->compute == CMM_F16) {
-    set_error("cmm_estimate: the bf16/f16 precision form is not built yet");
-    return CMM_EUNSUPPORTED;
-  }
   if (prob->d > 63 && prob->estimator == CMM_MEDIAN && prob->C_hat) {
     set_error("cmm_estimate: median over more than 63 repetitions is not implemented");
     return CMM_EUNSUPPORTED;

@@ -114,6 +114,12 @@ cmm_status launch_plan(const uint32_t* tab, int d, int64_t n, int lb, const Plan
                        hipStream_t s);
 cmm_status launch_compress(const CompressArgs& a, cmm_dtype dt, int lb, hipStream_t s);
 
+// Precision form: MFMA compress (b_lo = 2^14) on bf16 / fp16 rows.
+cmm_status launch_compress_mfma(const CompressArgs& a, cmm_dtype lp, hipStream_t s);
+// bf16 / fp16 copy of a float64 / float32 matrix, transposed or not.
+cmm_status launch_lp_copy(const void* in, cmm_dtype in_dt, int64_t rows, int64_t cols, int64_t ld,
+                          void* out, cmm_dtype lp, bool transpose, hipStream_t s);
+
 // out[c][r] = in[r][c] (dense out, leading dimension rows), with conversion.
 cmm_status launch_transpose(const void* in, cmm_dtype in_dt, int64_t rows, int64_t cols,
                             int64_t ld, void* out, cmm_dtype out_dt, hipStream_t s);

@@ -87,8 +87,8 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const uint32_t* __re
   extern __shared__ int32_t sh[];
   int32_t* cur = sh;                // [b_lo]  first index per bucket
   int32_t* nxt = sh + blo;          // [b_lo]  scratch, then counts, then chain offsets
-  int32_t* rank = sh + 2 * blo;     // [n]
-  int32_t* misc = rank + n;         // [2 + 16]: more, total, wave sums
+  int16_t* rank = reinterpret_cast<int16_t*>(sh + 2 * blo);   // [n] (ranks < 2^15)
+  int32_t* misc = sh + 2 * blo + (n + 1) / 2;                   // [2 + 16]: more, total, wave sums
   int32_t& s_more = misc[0];
   int32_t* s_total = misc + 1;
   int32_t* wsum = misc + 2;
@@ -100,6 +100,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const uint32_t* __re
   for (int r = tid; r < blo; r += kPlanThreads) first[r] = cur[r] == kNone ? -1 : cur[r];
   for (int64_t i = tid; i < n; i += kPlanThreads)
     if (cur[tb[i] & lomask] == (int32_t)i) rank[i] = 0;
+  __syncthreads();
   for (int round = 1;; ++round) {
     for (int r = tid; r < blo; r += kPlanThreads) nxt[r] = kNone;
     if (tid == 0) s_more = 0;
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const uint32_t* __re
       if (rank[i] < 0) atomicMin(&nxt[tb[i] & lomask], (int32_t)i);
     __syncthreads();
     for (int64_t i = tid; i < n; i += kPlanThreads)
-      if (rank[i] < 0 && nxt[tb[i] & lomask] == (int32_t)i) { rank[i] = round; s_more = 1; }
+      if (rank[i] < 0 && nxt[tb[i] & lomask] == (int32_t)i) { rank[i] = (int16_t)round; s_more = 1; }
     __syncthreads();
     const int more = s_more;
     __syncthreads();   // everyone read s_more before it is reset
@@ -606,7 +607,9 @@ __device__ __forceinline__ void pass2_16(T (&v)[16], T sgn8) {
   for (int e = 0; e < 16; ++e) v[e] = fma(v[e], sgn8, dpp_xor8(v[e]));
 }
 
-template <typename T>
+// SINGLE: one row buffer shared by the two operands (A staged, fixed up and
+// gathered before B), for rows too long to stage both at once.
+template <typename T, bool SINGLE>
 __global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
   constexpr int LB = 13;
   constexpr int E = 16;
@@ -616,9 +619,13 @@ __global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* xbuf = reinterpret_cast<T*>(smem);
   T* rowA = xbuf + XLEN;
-  T* rowB = rowA + row_pitch<T>(a.n_rows);
-  uint2* exl = reinterpret_cast<uint2*>(rowB + row_pitch<T>(a.n_cols));
-  if (threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
+  const int64_t pitch1 = SINGLE ? (row_pitch<T>(a.n_rows) > row_pitch<T>(a.n_cols)
+                                       ? row_pitch<T>(a.n_rows) : row_pitch<T>(a.n_cols))
+                                : row_pitch<T>(a.n_rows);
+  T* rowB = SINGLE ? rowA : rowA + pitch1;
+  uint2* exl = reinterpret_cast<uint2*>(rowB + (SINGLE ? 0 : row_pitch<T>(a.n_cols)) +
+                                        (SINGLE ? pitch1 : 0));
+  if (!SINGLE && threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
 
   const int b_hi_bits = a.log2b - LB;
   const int64_t nunits = (int64_t)a.d << b_hi_bits;
@@ -708,31 +715,50 @@ __global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
   // iteration that transforms them; the gather of k + 1 closes iteration k.
   auto load_k = [&](int64_t kk) {
     stage_row<T, NT>(rowA, At + kk * a.n_rows, a.n_rows, dma);
-    stage_row<T, NT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
+    if (!SINGLE) stage_row<T, NT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
   };
   auto fixups = [&]() {
     fix_chains<T, NT>(rowA, exA, csA, nchA, uhi);
-    fix_chains<T, NT>(rowB, exB, csB, nchB, uhi);
+    if (!SINGLE) fix_chains<T, NT>(rowB, exB, csB, nchB, uhi);
   };
   auto gather = [&]() {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       X[e] = flip_sign(*reinterpret_cast<const T*>(smem + offA[e]), (nega << (31 - e)) & 0x80000000u);
-      Y[e] = flip_sign(*reinterpret_cast<const T*>(smem + offB[e]), (negb << (31 - e)) & 0x80000000u);
+      if (!SINGLE)
+        Y[e] = flip_sign(*reinterpret_cast<const T*>(smem + offB[e]), (negb << (31 - e)) & 0x80000000u);
     }
   };
+  // SINGLE: B of step kk through the shared buffer (after X is gathered)
+  auto single_b = [&](int64_t kk) {
+    __syncthreads();   // X gathered: the buffer can take B
+    if (threadIdx.x == 0) rowB[a.n_cols] = T(0);
+    stage_row<T, NT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
+    if (dma) wait_dma();
+    __syncthreads();
+    fix_chains<T, NT>(rowB, exB, csB, nchB, uhi);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      Y[e] = flip_sign(*reinterpret_cast<const T*>(smem + offB[e]), (negb << (31 - e)) & 0x80000000u);
+  };
   if (k0 < k1) {
+    if (SINGLE && threadIdx.x == 0) rowA[a.n_rows] = T(0);
     load_k(k0);
     if (dma) wait_dma();
     __syncthreads();
     fixups();
     __syncthreads();
     gather();
+    if (SINGLE) single_b(k0);
   }
   for (int64_t k = k0; k < k1; ++k) {
     const bool more = k + 1 < k1;
     __syncthreads();   // every gather of k is done: the row buffers can be refilled
-    if (more) load_k(k + 1);
+    if (more) {
+      if (SINGLE && threadIdx.x == 0) rowA[a.n_rows] = T(0);
+      load_k(k + 1);
+    }
     pass1_16(X);
 #pragma unroll
     for (int e = 0; e < E; ++e) xbuf[wr_t + wr_e(e)] = X[e];
@@ -757,6 +783,7 @@ __global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
     if (more) {
       __syncthreads();
       gather();
+      if (SINGLE) single_b(k + 1);
     }
   }
   // final layout L2': reg bit0 -> 10, bit1 -> 11, bits 2,3 -> 8,9;
@@ -796,7 +823,7 @@ PlanView carve_plan(char* p, int d, int64_t n, int lb) {
 }
 
 size_t plan_lds_bytes(int64_t n, int lb) {
-  return sizeof(int32_t) * (2 * ((size_t)1 << lb) + (size_t)n + 2 + kPlanThreads / 64);
+  return sizeof(int32_t) * (2 * ((size_t)1 << lb) + ((size_t)n + 1) / 2 + 2 + kPlanThreads / 64);
 }
 
 cmm_status launch_plan(const uint32_t* tab, int d, int64_t n, int lb, const PlanView& pv,
@@ -848,9 +875,16 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   constexpr int LB = 13;
   const int64_t blocks = ((int64_t)a.d << (a.log2b - LB)) * a.groups;
   const size_t xlen = ((size_t)1 << LB) + ((size_t)1 << (LB - 6)) + 16;
-  const size_t base = sizeof(T) * (xlen + (size_t)row_pitch<T>(a.n_rows) +
-                                   (size_t)row_pitch<T>(a.n_cols));
+  size_t base = sizeof(T) * (xlen + (size_t)row_pitch<T>(a.n_rows) +
+                             (size_t)row_pitch<T>(a.n_cols));
   const size_t kMax = 160 * 1024;
+  bool single = false;
+  if (base > kMax) {
+    const size_t p1 = (size_t)(row_pitch<T>(a.n_rows) > row_pitch<T>(a.n_cols)
+                                   ? row_pitch<T>(a.n_rows) : row_pitch<T>(a.n_cols));
+    base = sizeof(T) * (xlen + p1);
+    single = true;
+  }
   if (base > kMax) { set_error("compress: rows do not fit in LDS"); return CMM_EUNSUPPORTED; }
   int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
   const int64_t want = a.n_rows + a.n_cols;
@@ -860,7 +894,7 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   constexpr int V = 16 / sizeof(T);
   a.dma = (a.n_rows % V == 0) && (a.n_cols % V == 0) && (a.ldb % V == 0) &&
           ((uintptr_t)a.At % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
-  auto kern = compress16_kernel<T>;
+  auto kern = single ? compress16_kernel<T, true> : compress16_kernel<T, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return hip_check(e, "compress: set LDS size");

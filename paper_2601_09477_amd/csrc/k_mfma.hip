@@ -1,0 +1,403 @@
+// Precision form of the fused Compress: sketches rounded to bf16 / fp16,
+// the Walsh-Hadamard transform on the matrix cores (MFMA) with float32
+// accumulation, the sum over k flushed into float64 every kFlush steps.
+//
+// Transform.  b_lo = 2^14 per work-group (512 threads, 8 wavefronts, each
+// holding 8 tiles of 16 x 16).  For a tile Z with row index a and column
+// index b (4 bits each),
+//   pass 1:  D1 = Z  . H16   (Z as the A operand)  transforms b;
+//   pass 2:  D2 = H16 . D1   (D1 as the B operand) transforms a.
+// The D layout of v_mfma_f32_16x16x16 (lane l holds rows 4(l/16)+v of column
+// l%16) is exactly its B layout, so pass 2 consumes pass 1's output after a
+// float32 -> bf16/fp16 conversion in place: 8 index bits per tile with no
+// data movement.  One LDS transpose (bf16, 8-byte reads) regroups the bits
+// and a second chained pair (H16, then H4 x I4 on the two top bits) does
+// the remaining six.  H16 and H4 are exact in bf16 / fp16; only the data
+// operand rounds.
+//
+// u_lo index bits:
+//   gather / pass 1 (A layout): v -> 0,1  g=l/16 -> 2,3  m=l%16 -> 4..7
+//                               tile c -> 8..10  wave w -> 11..13
+//   after pass 2:               n=l%16 -> 0..3  (4g+v) -> 4..7  c, w as above
+//   pass 3 (A layout):          m=l%16 -> {0,1,12,13}  (4g+v) -> 8..11
+//                               tile c -> 2..4  wave w -> 5..7
+//   after pass 4 (final):       v -> 0,1  g -> 12,13  n=l%16 -> 8..11
+//                               c -> 2..4  w -> 5..7
+// The sketch (fold, gather, collision chains) is the one of the float64
+// kernel, on rows staged in the low precision.
+#include "cmm_internal.h"
+
+namespace cmm {
+namespace {
+
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+typedef __attribute__((ext_vector_type(4))) _Float16 f16x4;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+template <typename IN> struct Mf;
+template <> struct Mf<__bf16> {
+  typedef bf16x4 vec;
+  static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mf<_Float16> {
+  typedef f16x4 vec;
+  static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int kLB = 14;
+constexpr int kNT = 512;
+constexpr int kTiles = 8;
+constexpr int kFlush = 16;   // k steps summed in float32 before the float64 flush
+
+template <typename IN>
+__device__ __forceinline__ IN neg_if(IN x, uint32_t neg) {
+  return neg ? -x : x;
+}
+
+// transpose-buffer address (in elements) of index u: bits 8,9 lowest so a
+// pass-3 lane reads its 4 values with one 8-byte load; bits 12,13 are XORed
+// into bits 4,5 so the 16 lanes of a read phase use distinct bank pairs.
+__device__ __forceinline__ uint32_t taddr(uint32_t u) {
+  const uint32_t a = ((u >> 8) & 3u) | ((u & 0xFFu) << 2) | ((u >> 10) << 10);
+  return a ^ (((a >> 12) & 3u) << 4);
+}
+
+template <typename IN>
+__device__ __forceinline__ float to_f(IN x) { return (float)x; }
+
+// Collision chains on a low-precision staged row: the sum is formed in
+// float32 in ascending index order and rounded once.
+template <typename IN, int NT>
+__device__ __forceinline__ void fix_chains_lp(IN* __restrict__ row, const uint2* __restrict__ ex,
+                                              const int32_t* __restrict__ cs, int nch,
+                                              uint32_t uhi) {
+  for (int c = threadIdx.x; c < nch; c += NT) {
+    const int beg = cs[c], end = cs[c + 1];
+    const uint32_t tgt = ex[beg].x >> 16;
+    float acc = to_f(row[tgt]);
+    for (int q0 = beg; q0 < end; q0 += 4) {
+      uint2 x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = (q0 + j < end) ? ex[q0 + j] : make_uint2(0u, 0u);
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = (q0 + j < end) ? to_f(row[x[j].x & 0xFFFFu]) : 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (q0 + j < end) {
+          const uint32_t neg = (x[j].y >> 31) ^ (__popc(uhi & (x[j].y & kBucketMask)) & 1u);
+          acc = acc + (neg ? -v[j] : v[j]);
+        }
+    }
+    row[tgt] = (IN)acc;
+  }
+}
+
+// Copy a row of n low-precision values into LDS (16-byte asynchronous
+// global->LDS loads when possible, else a plain loop).
+template <typename IN, int NT>
+__device__ __forceinline__ void stage_row_lp(IN* __restrict__ dst, const IN* __restrict__ src,
+                                             int64_t n, bool dma) {
+  if (dma) {
+    const int64_t chunks = n / 8;
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = threadIdx.x & ~63;
+    for (int64_t c0 = wbase; c0 < chunks; c0 += NT) {
+      if (c0 + lane < chunks)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(src + (c0 + lane) * 8),
+            (__attribute__((address_space(3))) void*)(dst + c0 * 8), 16, 0, 0);
+    }
+  } else {
+    for (int64_t i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
+  }
+}
+
+template <typename IN>
+__global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
+  typedef typename Mf<IN>::vec vec;
+  constexpr int BLO = 1 << kLB;
+  constexpr int NS = kTiles * 4;   // gather slots per thread and operand
+  extern __shared__ __align__(16) unsigned char smem[];
+  IN* tbufX = reinterpret_cast<IN*>(smem);               // BLO
+  IN* tbufY = tbufX + BLO;                               // BLO
+  IN* rowA = tbufY + BLO;
+  const int64_t pitchA = (a.n_rows + 1 + 7) / 8 * 8;     // 16-byte aligned rows + zero pad
+  const int64_t pitchB = (a.n_cols + 1 + 7) / 8 * 8;
+  IN* rowB = rowA + pitchA;
+  uint2* exl = reinterpret_cast<uint2*>(rowB + pitchB);
+  if (threadIdx.x == 0) { rowA[a.n_rows] = (IN)0.f; rowB[a.n_cols] = (IN)0.f; }
+
+  const int b_hi_bits = a.log2b - kLB;
+  const int64_t nunits = (int64_t)a.d << b_hi_bits;
+  const int64_t wg = blockIdx.x;
+  const int64_t total = nunits * a.groups;
+  int64_t lin = wg;
+  if ((total & 7) == 0) lin = (wg & 7) * (total >> 3) + (wg >> 3);
+  const int g = (int)(lin / nunits);
+  const int64_t unit = lin - (int64_t)g * nunits;
+  const int t = (int)(unit >> b_hi_bits);
+  const uint32_t uhi = (uint32_t)(unit & (((int64_t)1 << b_hi_bits) - 1));
+  const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
+  const int64_t k0 = (int64_t)g * k_per;
+  const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
+
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t lg = lane >> 4, lm = lane & 15;
+  // gather slots e = 4 c + v -> bucket v | lg << 2 | lm << 4 | c << 8 | w << 11;
+  // two 16-bit row indices per word, and the folded sign bits
+  uint32_t idxA[NS / 2], idxB[NS / 2];
+  uint32_t negA = 0, negB = 0;
+  {
+    const int32_t* f1 = a.planA.first + (size_t)t * BLO;
+    const int32_t* f2 = a.planB.first + (size_t)t * BLO;
+    const uint32_t* t1 = a.tab1 + (size_t)t * a.n_rows;
+    const uint32_t* t2 = a.tab2 + (size_t)t * a.n_cols;
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      const uint32_t c = (uint32_t)e >> 2, v = (uint32_t)e & 3u;
+      const uint32_t r = v | (lg << 2) | (lm << 4) | (c << 8) | (w << 11);
+      const int32_t r1 = f1[r], r2 = f2[r];
+      const uint32_t en1 = t1[r1 >= 0 ? r1 : 0], en2 = t2[r2 >= 0 ? r2 : 0];
+      const uint32_t s1 = r1 >= 0 ? (en1 >> 31) ^ (__popc(uhi & ((en1 & kBucketMask) >> kLB)) & 1u) : 0u;
+      const uint32_t s2 = r2 >= 0 ? (en2 >> 31) ^ (__popc(uhi & ((en2 & kBucketMask) >> kLB)) & 1u) : 0u;
+      negA |= s1 << e;
+      negB |= s2 << e;
+      const uint32_t ia = r1 >= 0 ? (uint32_t)r1 : (uint32_t)a.n_rows;
+      const uint32_t ib = r2 >= 0 ? (uint32_t)r2 : (uint32_t)a.n_cols;
+      if (e & 1) { idxA[e >> 1] |= ia << 16; idxB[e >> 1] |= ib << 16; }
+      else { idxA[e >> 1] = ia; idxB[e >> 1] = ib; }
+    }
+  }
+  const int32_t* gcA = a.planA.cstart + (size_t)t * (a.n_rows + 2);
+  const int32_t* gcB = a.planB.cstart + (size_t)t * (a.n_cols + 2);
+  const int nchA = a.planA.nchains[t], nchB = a.planB.nchains[t];
+  const int cntA = gcA[nchA], cntB = gcB[nchB];
+  const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
+  const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
+  const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
+  const uint2* exA = gA;
+  const uint2* exB = gB;
+  const int32_t* csA = gcA;
+  const int32_t* csB = gcB;
+  if (ex_lds) {
+    for (int q = threadIdx.x; q < cntA; q += kNT) exl[q] = gA[q];
+    for (int q = threadIdx.x; q < cntB; q += kNT) exl[cntA + q] = gB[q];
+    int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
+    for (int q = threadIdx.x; q <= nchA; q += kNT) csl[q] = gcA[q];
+    for (int q = threadIdx.x; q <= nchB; q += kNT) csl[nchA + 1 + q] = gcB[q];
+    exA = exl;
+    exB = exl + cntA;
+    csA = csl;
+    csB = csl + nchA + 1;
+  }
+
+  // H16 as the B operand (passes 1, 3) and as the A operand (pass 2): lane
+  // holds H[4 lg + v][lm] = H[lm][4 lg + v].  Pass 4: M4 = H4 x I4 on the
+  // two top bits, as the A operand: M4[lm][4 lg + v] = H4[lm >> 2][lg] [lm & 3 == v].
+  vec h16, m4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const uint32_t k = 4u * lg + (uint32_t)v;
+    h16[v] = (IN)((__popc(k & lm) & 1u) ? -1.f : 1.f);
+    const float h4 = (__popc((lm >> 2) & lg) & 1u) ? -1.f : 1.f;
+    m4[v] = (IN)(((lm & 3u) == (uint32_t)v) ? h4 : 0.f);
+  }
+  // pass-2 output index base (+ (4 lg + v) << 4 + c << 8) and pass-3 read
+  // index base (+ c << 2, the four v at bits 8, 9 are one 8-byte load)
+  const uint32_t w2 = lm | (w << 11);
+  const uint32_t r3 = (lm & 3u) | ((lm >> 2) << 12) | (lg << 10) | (w << 5);
+
+  const IN* At = reinterpret_cast<const IN*>(a.At);
+  const IN* Bm = reinterpret_cast<const IN*>(a.B);
+  const bool dma = a.dma != 0;
+  auto load_k = [&](int64_t kk) {
+    stage_row_lp<IN, kNT>(rowA, At + kk * a.n_rows, a.n_rows, dma);
+    stage_row_lp<IN, kNT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
+  };
+  // passes 1-2 of one operand from its staged row; result written (rounded)
+  // to the transpose buffer
+  auto front = [&](const IN* row, const uint32_t (&idx)[NS / 2], uint32_t neg, IN* tb) {
+#pragma unroll
+    for (int c = 0; c < kTiles; ++c) {
+      vec av;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int e = c * 4 + v;
+        const uint32_t o = (idx[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu;
+        av[v] = neg_if(row[o], (neg >> e) & 1u);
+      }
+      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+      const f32x4 d1 = Mf<IN>::mma(av, h16, z);
+      vec bv;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = (IN)d1[v];
+      const f32x4 d2 = Mf<IN>::mma(h16, bv, z);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        tb[taddr(w2 | ((4u * lg + (uint32_t)v) << 4) | ((uint32_t)c << 8))] = (IN)d2[v];
+    }
+  };
+  // passes 3-4 from the transpose buffer into the final float32 layout
+  auto back = [&](const IN* tb, float (&out)[NS]) {
+#pragma unroll
+    for (int c = 0; c < kTiles; ++c) {
+      const vec av = *reinterpret_cast<const vec*>(tb + taddr(r3 | ((uint32_t)c << 2)));
+      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+      const f32x4 d3 = Mf<IN>::mma(av, h16, z);
+      vec bv;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = (IN)d3[v];
+      const f32x4 d4 = Mf<IN>::mma(m4, bv, z);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[c * 4 + v] = d4[v];
+    }
+  };
+
+  // partial p_hat slice of this work-group: final index of (thread, c, v)
+  const int64_t b = (int64_t)1 << a.log2b;
+  double* dst = a.partial + ((size_t)g * a.d + t) * b + ((int64_t)uhi << kLB);
+  const uint32_t fin = (lg << 12) | (lm << 8) | (w << 5);   // + v + c << 2
+  float acc[NS];
+#pragma unroll
+  for (int e = 0; e < NS; ++e) acc[e] = 0.f;
+  int pending = 0;
+  bool first_flush = true;
+  auto flush = [&]() {
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      double* q = dst + (fin | (uint32_t)(e & 3) | ((uint32_t)(e >> 2) << 2));
+      *q = (first_flush ? 0.0 : *q) + (double)acc[e];
+      acc[e] = 0.f;
+    }
+    first_flush = false;
+    pending = 0;
+  };
+
+  if (k0 < k1) load_k(k0);
+  for (int64_t k = k0; k < k1; ++k) {
+    if (dma) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();   // rows of k staged; the transpose buffers are free
+    if (nchA + nchB > 0) {
+      fix_chains_lp<IN, kNT>(rowA, exA, csA, nchA, uhi);
+      fix_chains_lp<IN, kNT>(rowB, exB, csB, nchB, uhi);
+      __syncthreads();
+    }
+    front(rowA, idxA, negA, tbufX);
+    front(rowB, idxB, negB, tbufY);
+    __syncthreads();   // gathers done (rows free), transpose buffers written
+    if (k + 1 < k1) load_k(k + 1);
+    float X[NS], Y[NS];
+    back(tbufX, X);
+    back(tbufY, Y);
+#pragma unroll
+    for (int e = 0; e < NS; ++e) acc[e] = fmaf(X[e], Y[e], acc[e]);
+    if (++pending == kFlush) flush();
+  }
+  if (pending > 0 || first_flush) flush();
+}
+
+}  // namespace
+
+template <typename IN>
+static cmm_status launch_mfma_t(const CompressArgs& a0, hipStream_t s) {
+  ProfScope prof_("compress", s);
+  CompressArgs a = a0;
+  const int64_t blocks = ((int64_t)a.d << (a.log2b - kLB)) * a.groups;
+  const size_t pitch = ((size_t)a.n_rows + 1 + 7) / 8 * 8 + ((size_t)a.n_cols + 1 + 7) / 8 * 8;
+  const size_t base = sizeof(IN) * (2 * ((size_t)1 << kLB) + pitch);
+  const size_t kMax = 160 * 1024;
+  if (base > kMax) { set_error("compress (mfma): rows do not fit in LDS"); return CMM_EUNSUPPORTED; }
+  int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
+  const int64_t want = a.n_rows + a.n_cols;
+  if (cap > want) cap = want;
+  a.ex_cap = cap;
+  const size_t lds = base + sizeof(uint2) * (size_t)cap;
+  a.dma = (a.n_rows % 8 == 0) && (a.n_cols % 8 == 0) && (a.ldb % 8 == 0) &&
+          ((uintptr_t)a.At % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
+  auto kern = compress_mfma_kernel<IN>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return hip_check(e, "compress (mfma): set LDS size");
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNT), lds, s, a);
+  return hip_check(hipGetLastError(), "compress (mfma) kernel launch");
+}
+
+cmm_status launch_compress_mfma(const CompressArgs& a, cmm_dtype lp, hipStream_t s) {
+  if (a.log2b < kLB) {
+    set_error("compress (mfma): needs log2b >= 14");
+    return CMM_EUNSUPPORTED;
+  }
+  if (lp == CMM_BF16) return launch_mfma_t<__bf16>(a, s);
+  return launch_mfma_t<_Float16>(a, s);
+}
+
+// Low-precision copies of the operands: out[c][r] = in[r][c] (transpose)
+// or out[r][c] = in[r][c], rounded to nearest even.
+namespace {
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void lp_transpose_kernel(const TI* __restrict__ in, int64_t rows,
+                                                           int64_t cols, int64_t ld,
+                                                           TO* __restrict__ out) {
+  __shared__ float tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int y = ty; y < 64; y += 4) {
+    const int64_t r = r0 + y, c = c0 + tx;
+    if (r < rows && c < cols) tile[y][tx] = (float)in[r * ld + c];
+  }
+  __syncthreads();
+  for (int y = ty; y < 64; y += 4) {
+    const int64_t c = c0 + y, r = r0 + tx;
+    if (r < rows && c < cols) out[c * rows + r] = (TO)tile[tx][y];
+  }
+}
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void lp_convert_kernel(const TI* __restrict__ in, int64_t rows,
+                                                         int64_t cols, int64_t ld,
+                                                         TO* __restrict__ out) {
+  const int64_t n = rows * cols;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    const int64_t r = q / cols, c = q - r * cols;
+    out[q] = (TO)(float)in[r * ld + c];
+  }
+}
+template <typename TO>
+cmm_status lp_copy_t(const void* in, cmm_dtype in_dt, int64_t rows, int64_t cols, int64_t ld,
+                     void* out, bool transpose, hipStream_t s) {
+  if (transpose) {
+    dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
+    if (in_dt == CMM_F64)
+      hipLaunchKernelGGL((lp_transpose_kernel<double, TO>), grid, dim3(256), 0, s,
+                         (const double*)in, rows, cols, ld, (TO*)out);
+    else
+      hipLaunchKernelGGL((lp_transpose_kernel<float, TO>), grid, dim3(256), 0, s,
+                         (const float*)in, rows, cols, ld, (TO*)out);
+  } else {
+    int64_t gsz = (rows * cols + 255) / 256;
+    if (gsz > 65536) gsz = 65536;
+    if (gsz < 1) gsz = 1;
+    if (in_dt == CMM_F64)
+      hipLaunchKernelGGL((lp_convert_kernel<double, TO>), dim3((unsigned)gsz), dim3(256), 0, s,
+                         (const double*)in, rows, cols, ld, (TO*)out);
+    else
+      hipLaunchKernelGGL((lp_convert_kernel<float, TO>), dim3((unsigned)gsz), dim3(256), 0, s,
+                         (const float*)in, rows, cols, ld, (TO*)out);
+  }
+  return hip_check(hipGetLastError(), "low-precision copy launch");
+}
+}  // namespace
+
+cmm_status launch_lp_copy(const void* in, cmm_dtype in_dt, int64_t rows, int64_t cols, int64_t ld,
+                          void* out, cmm_dtype lp, bool transpose, hipStream_t s) {
+  ProfScope prof_("transpose", s);
+  if (lp == CMM_BF16) return lp_copy_t<__bf16>(in, in_dt, rows, cols, ld, out, transpose, s);
+  return lp_copy_t<_Float16>(in, in_dt, rows, cols, ld, out, transpose, s);
+}
+
+}  // namespace cmm
