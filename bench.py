@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 # (the 78.6 TFLOP/s FP64 vector peak counts an FMA as two flops).
 PEAK_F64_ADD = 256 * 4 * 16 * 2.4e9
 PEAK_HBM = 8.0e12
+PEAK_MFMA_16 = 2.5e15   # dense bf16 / fp16 matrix-core peak
 
 
 def compress_ops(n: int, d: int, log2b: int) -> float:
@@ -65,12 +66,96 @@ def cpu_baseline(w, budget_s: float = 20.0) -> dict:
                       f"{blas_threads} BLAS threads, the rest one thread"}
 
 
+def run_estimate(w, compute: str, steps: int, warmup: int, out_dtype=None):
+    """Time `steps` full estimates of workload w (inputs resident on the GPU).
+    Returns (ms_per_step, per-kernel ms per step, C_hat on the GPU, p)."""
+    import torch
+
+    import paper_2601_09477_amd as cmm
+    n_rows, n_cols = w.A.shape[0], w.B.shape[1]
+    d, log2b = w.d, w.log2b
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    B = torch.from_numpy(w.B).to(dev)
+    keys = cmm.keys_tensor(w.keys, dev)
+    tab1 = torch.empty((d, n_rows), dtype=torch.int32, device=dev)
+    tab2 = torch.empty((d, n_cols), dtype=torch.int32, device=dev)
+    p = torch.empty((d, 1 << log2b), dtype=torch.float64, device=dev)
+    C_hat = torch.empty((n_rows, n_cols), dtype=out_dtype or torch.float64, device=dev)
+    pr = cmm.make_problem(A, B, d, log2b, keys=keys, tab1=tab1, tab2=tab2, p=p, C_hat=C_hat,
+                          compute=compute, estimator=w.estimator)
+    nbytes = cmm.cmm_workspace_size(pr)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        cmm.cmm_estimate(pr, ws, nbytes, stream)
+    torch.cuda.synchronize()
+    cmm.cmm_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cmm.cmm_estimate(pr, ws, nbytes, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern = {k: cmm.cmm_profile_query(k) for k in
+            ("hash", "transpose", "plan", "compress", "reduce", "fwht", "extract")}
+    cmm.cmm_profile_enable(False)
+    del ws
+    return elapsed / steps * 1e3, kern, C_hat, p
+
+
+def precision_form(steps: int, warmup: int) -> dict:
+    """The precision form at n = 8192, b = 2^18, d = 9 (planted +-1, two
+    planted columns per row): bf16 and fp16 on MFMA against plain float64 on
+    the same GPU (speed, error of p, heavy-hitter recall)."""
+    import torch
+
+    from workloads import planted_8192
+    from workloads.metrics import planted_recall
+    w = planted_8192(0)
+    out = {"workload": "planted +-1, n=8192, b=2^18, d=9, 16384 planted pairs (two per row)"}
+    ref_p = None
+    ref_ms = None
+    for compute in ("f64", "bf16", "f16"):
+        ms, kern, C_hat, p = run_estimate(w, compute, steps, warmup)
+        rec = planted_recall(C_hat.cpu().numpy(), w.rows, w.cols, w.tau)
+        ms_c, n_c = kern["compress"]
+        avg_c = ms_c / max(1, n_c) * 1e-3
+        entry = {"ms_per_step": ms, "value": 2.0 * w.n ** 3 / (ms * 1e-3) / 1e12,
+                 "compress_ms": avg_c * 1e3,
+                 "recall": {"recalled": rec["recalled"], "planted": rec["planted"],
+                            "background_ge_tau": rec["background_ge_tau"]}}
+        if compute == "f64":
+            ref_p, ref_ms = p, ms
+            entry["compress_roofline"] = {
+                "bound": "alu", "achieved": compress_ops(w.n, w.d, w.log2b) / avg_c / 1e12,
+                "peak": PEAK_F64_ADD / 1e12, "unit": "TFLOP/s",
+                "frac": compress_ops(w.n, w.d, w.log2b) / avg_c / PEAK_F64_ADD}
+        else:
+            dp = (p - ref_p).abs()
+            entry["error_vs_f64"] = {"max_abs_dp_over_max_abs_p": float(dp.max() / ref_p.abs().max()),
+                                     "rms_dp_over_rms_p": float(dp.pow(2).mean().sqrt() /
+                                                                ref_p.pow(2).mean().sqrt())}
+            entry["speedup_vs_f64"] = ref_ms / ms
+            # executed matrix-core work: 4 passes x 16 MACs x 2 flops per element
+            mfma_flops = 2.0 * w.d * w.n * (1 << w.log2b) * 4 * 16 * 2
+            entry["compress_roofline"] = {
+                "bound": "mfma", "achieved": mfma_flops / avg_c / 1e12, "peak": PEAK_MFMA_16 / 1e12,
+                "unit": "TFLOP/s", "frac": mfma_flops / avg_c / PEAK_MFMA_16,
+                "algorithmic_add_rate_TFLOPs": compress_ops(w.n, w.d, w.log2b) / avg_c / 1e12}
+        out[compute] = entry
+        del C_hat, p
+        torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision-form leg")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -78,45 +163,12 @@ def main() -> int:
               f"(the path shards over GPUs only by design, see DESIGN.md)", file=sys.stderr)
         return 2
 
-    import torch
-
-    import paper_2601_09477_amd as cmm
     from workloads import planted_4096
     from workloads.metrics import planted_recall
 
     w = planted_4096(args.seed)
     n, d, log2b = w.n, w.d, w.log2b
-    dev = torch.device("cuda:0")
-    A = torch.from_numpy(w.A).to(dev)
-    B = torch.from_numpy(w.B).to(dev)
-    keys = cmm.keys_tensor(w.keys, dev)
-    tab1 = torch.empty((d, n), dtype=torch.int32, device=dev)
-    tab2 = torch.empty((d, n), dtype=torch.int32, device=dev)
-    p = torch.empty((d, 1 << log2b), dtype=torch.float64, device=dev)
-    C_hat = torch.empty((n, n), dtype=torch.float64, device=dev)
-    pr = cmm.make_problem(A, B, d, log2b, keys=keys, tab1=tab1, tab2=tab2, p=p, C_hat=C_hat)
-    nbytes = cmm.cmm_workspace_size(pr)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-
-    def step():
-        cmm.cmm_estimate(pr, ws, nbytes, stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    cmm.cmm_profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kern = {k: cmm.cmm_profile_query(k) for k in
-            ("hash", "transpose", "plan", "compress", "reduce", "fwht", "extract")}
-    cmm.cmm_profile_enable(False)
-    ms_per_step = elapsed / args.steps * 1e3
-
+    ms_per_step, kern, C_hat, _ = run_estimate(w, "f64", args.steps, args.warmup)
     rec = planted_recall(C_hat.cpu().numpy(), w.rows, w.cols, w.tau)
     ms_comp, n_comp = kern["compress"]
     avg_comp = ms_comp / max(1, n_comp) * 1e-3
@@ -141,6 +193,9 @@ def main() -> int:
                      "work_per_launch": ops, "avg_launch_ms": avg_comp * 1e3,
                      "traffic": None},
     }
+    del C_hat
+    if not args.no_forms:
+        out["mfma_form"] = precision_form(max(3, args.steps // 4), 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

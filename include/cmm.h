@@ -120,7 +120,8 @@ cmm_status cmm_extract(const double* p, const uint32_t* tab1, const uint32_t* ta
  *            CMM_BF16 / CMM_F16 -- precision form: sketches rounded to
  *                       bf16 / f16, transforms on the matrix cores (MFMA) with
  *                       float32 accumulation, cross-k accumulation and the
- *                       inverse transform in float64.
+ *                       inverse transform in float64.  Needs log2b >= 14 and
+ *                       n_rows, n_cols <= 16383 (else CMM_EUNSUPPORTED).
  *   in_dtype: CMM_F64 or CMM_F32 (CMM_F64 required when compute = CMM_F64).
  *   keys: device uint64[d][4][2] or NULL.  If non-NULL the tables are
  *         computed from the keys into tab1 / tab2 (outputs).  If NULL,

@@ -58,12 +58,16 @@ __device__ __forceinline__ IN neg_if(IN x, uint32_t neg) {
   return neg ? -x : x;
 }
 
-// transpose-buffer address (in elements) of index u: bits 8,9 lowest so a
-// pass-3 lane reads its 4 values with one 8-byte load; bits 12,13 are XORed
-// into bits 4,5 so the 16 lanes of a read phase use distinct bank pairs.
-__device__ __forceinline__ uint32_t taddr(uint32_t u) {
-  const uint32_t a = ((u >> 8) & 3u) | ((u & 0xFFu) << 2) | ((u >> 10) << 10);
-  return a ^ (((a >> 12) & 3u) << 4);
+// Transpose-buffer address (in elements) of index u, a bit permutation:
+//   a0,a1 <- u8,u9   (a pass-3 lane's four values: one 8-byte load)
+//   a2,a3 <- u0,u1   a4,a5 <- u12,u13   (the 16 lanes of a pass-3 read
+//                                        phase hit 16 distinct bank pairs)
+//   a6..a11 <- u2..u7   a12 <- u10   a13 <- u11
+// The bits a thread varies (tile c, value v) land on bits no thread bit
+// uses, so every access is a per-thread base plus an immediate offset.
+__host__ __device__ constexpr uint32_t taddr(uint32_t u) {
+  return ((u >> 8) & 3u) | ((u & 3u) << 2) | (((u >> 12) & 3u) << 4) | (((u >> 2) & 63u) << 6) |
+         (((u >> 10) & 1u) << 12) | (((u >> 11) & 1u) << 13);
 }
 
 template <typename IN>
@@ -117,19 +121,37 @@ __device__ __forceinline__ void stage_row_lp(IN* __restrict__ dst, const IN* __r
   }
 }
 
+// Pack two float32 into the low precision (round to nearest even).
+__device__ __forceinline__ uint32_t pack2(float x, float y, __bf16*) {
+  typedef __attribute__((ext_vector_type(2))) float f2;
+  typedef __attribute__((ext_vector_type(2))) __bf16 b2;
+  const b2 r = __builtin_convertvector((f2){x, y}, b2);
+  return __builtin_bit_cast(uint32_t, r);
+}
+__device__ __forceinline__ uint32_t pack2(float x, float y, _Float16*) {
+  typedef __attribute__((ext_vector_type(2))) float f2;
+  typedef __attribute__((ext_vector_type(2))) _Float16 h2;
+  const h2 r = __builtin_convertvector((f2){x, y}, h2);
+  return __builtin_bit_cast(uint32_t, r);
+}
+
 template <typename IN>
 __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   typedef typename Mf<IN>::vec vec;
+  typedef __attribute__((ext_vector_type(2))) uint32_t u2;
   constexpr int BLO = 1 << kLB;
   constexpr int NS = kTiles * 4;   // gather slots per thread and operand
   extern __shared__ __align__(16) unsigned char smem[];
-  IN* tbufX = reinterpret_cast<IN*>(smem);               // BLO
-  IN* tbufY = tbufX + BLO;                               // BLO
-  IN* rowA = tbufY + BLO;
+  // rows first (small LDS offsets), then the two transpose buffers
   const int64_t pitchA = (a.n_rows + 1 + 7) / 8 * 8;     // 16-byte aligned rows + zero pad
   const int64_t pitchB = (a.n_cols + 1 + 7) / 8 * 8;
+  IN* rowA = reinterpret_cast<IN*>(smem);
   IN* rowB = rowA + pitchA;
-  uint2* exl = reinterpret_cast<uint2*>(rowB + pitchB);
+  IN* tbufX = rowB + pitchB;                             // BLO
+  IN* tbufY = tbufX + BLO;                               // BLO
+  uint2* exl = reinterpret_cast<uint2*>(tbufY + BLO);
+  const uint16_t* rowA16 = reinterpret_cast<const uint16_t*>(rowA);
+  const uint16_t* rowB16 = reinterpret_cast<const uint16_t*>(rowB);
   if (threadIdx.x == 0) { rowA[a.n_rows] = (IN)0.f; rowB[a.n_cols] = (IN)0.f; }
 
   const int b_hi_bits = a.log2b - kLB;
@@ -148,10 +170,10 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
 
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t lg = lane >> 4, lm = lane & 15;
-  // gather slots e = 4 c + v -> bucket v | lg << 2 | lm << 4 | c << 8 | w << 11;
-  // two 16-bit row indices per word, and the folded sign bits
-  uint32_t idxA[NS / 2], idxB[NS / 2];
-  uint32_t negA = 0, negB = 0;
+  // gather slots e = 4 c + v -> bucket v | lg << 2 | lm << 4 | c << 8 | w << 11.
+  // Two 16-bit words per register: byte offset of the row element in bits
+  // 0..14 (empty bucket -> the zero pad at index n), folded sign in bit 15.
+  uint32_t idxA[NS / 2], idxB[NS / 2];     // first rows of the buckets
   {
     const int32_t* f1 = a.planA.first + (size_t)t * BLO;
     const int32_t* f2 = a.planB.first + (size_t)t * BLO;
@@ -165,10 +187,8 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
       const uint32_t en1 = t1[r1 >= 0 ? r1 : 0], en2 = t2[r2 >= 0 ? r2 : 0];
       const uint32_t s1 = r1 >= 0 ? (en1 >> 31) ^ (__popc(uhi & ((en1 & kBucketMask) >> kLB)) & 1u) : 0u;
       const uint32_t s2 = r2 >= 0 ? (en2 >> 31) ^ (__popc(uhi & ((en2 & kBucketMask) >> kLB)) & 1u) : 0u;
-      negA |= s1 << e;
-      negB |= s2 << e;
-      const uint32_t ia = r1 >= 0 ? (uint32_t)r1 : (uint32_t)a.n_rows;
-      const uint32_t ib = r2 >= 0 ? (uint32_t)r2 : (uint32_t)a.n_cols;
+      const uint32_t ia = 2u * (r1 >= 0 ? (uint32_t)r1 : (uint32_t)a.n_rows) | (s1 << 15);
+      const uint32_t ib = 2u * (r2 >= 0 ? (uint32_t)r2 : (uint32_t)a.n_cols) | (s2 << 15);
       if (e & 1) { idxA[e >> 1] |= ia << 16; idxB[e >> 1] |= ib << 16; }
       else { idxA[e >> 1] = ia; idxB[e >> 1] = ib; }
     }
@@ -208,9 +228,10 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
     m4[v] = (IN)(((lm & 3u) == (uint32_t)v) ? h4 : 0.f);
   }
   // pass-2 output index base (+ (4 lg + v) << 4 + c << 8) and pass-3 read
-  // index base (+ c << 2, the four v at bits 8, 9 are one 8-byte load)
-  const uint32_t w2 = lm | (w << 11);
-  const uint32_t r3 = (lm & 3u) | ((lm >> 2) << 12) | (lg << 10) | (w << 5);
+  // index base (+ c << 2; the four v at bits 8, 9 are one 8-byte load)
+  const uint32_t wbase = taddr(lm | ((4u * lg) << 4) | (w << 11));   // + taddr of (v, c)
+  const uint32_t rbase = taddr((lm & 3u) | ((lm >> 2) << 12) | (lg << 10) | (w << 5));   // + taddr(c << 2)
+  IN* const dummy = nullptr;
 
   const IN* At = reinterpret_cast<const IN*>(a.At);
   const IN* Bm = reinterpret_cast<const IN*>(a.B);
@@ -219,60 +240,96 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
     stage_row_lp<IN, kNT>(rowA, At + kk * a.n_rows, a.n_rows, dma);
     stage_row_lp<IN, kNT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
   };
-  // passes 1-2 of one operand from its staged row; result written (rounded)
-  // to the transpose buffer
-  auto front = [&](const IN* row, const uint32_t (&idx)[NS / 2], uint32_t neg, IN* tb) {
+  // passes 1-2 of one operand from its staged row, each phase over all
+  // tiles (independent MFMAs); result written (rounded) to the transpose buffer
+  auto gather_tiles = [&](const unsigned char* rb, const uint32_t (&idx)[NS / 2],
+                          vec (&av)[kTiles]) {
+    uint32_t raw[NS];
+#pragma unroll
+    for (int e = 0; e < NS; ++e)
+      raw[e] = *reinterpret_cast<const uint16_t*>(rb + ((idx[e >> 1] >> ((e & 1) * 16)) & 0x7FFFu));
 #pragma unroll
     for (int c = 0; c < kTiles; ++c) {
-      vec av;
+      u2 pk;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int e = c * 4 + v;
-        const uint32_t o = (idx[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu;
-        av[v] = neg_if(row[o], (neg >> e) & 1u);
+      for (int h = 0; h < 2; ++h) {
+        const int e = c * 4 + 2 * h;
+        const uint32_t word = raw[e] | (raw[e + 1] << 16);
+        pk[h] = word ^ (idx[e >> 1] & 0x80008000u);   // folded signs
       }
-      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-      const f32x4 d1 = Mf<IN>::mma(av, h16, z);
-      vec bv;
+      av[c] = __builtin_bit_cast(vec, pk);
+    }
+  };
+  // passes 1-2 of one operand from its staged row; each phase runs over all
+  // tiles (independent MFMAs); the result is written, rounded, to the
+  // transpose buffer
+  auto front = [&](const uint16_t* row16, const uint32_t (&idx)[NS / 2], IN* tb) {
+    const unsigned char* rb = reinterpret_cast<const unsigned char*>(row16);
+    vec av[kTiles];
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    f32x4 d[kTiles];
+    gather_tiles(rb, idx, av);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = (IN)d1[v];
-      const f32x4 d2 = Mf<IN>::mma(h16, bv, z);
+    for (int c = 0; c < kTiles; ++c) d[c] = Mf<IN>::mma(av[c], h16, z);
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        tb[taddr(w2 | ((4u * lg + (uint32_t)v) << 4) | ((uint32_t)c << 8))] = (IN)d2[v];
+    for (int c = 0; c < kTiles; ++c) {
+      u2 pk;
+      pk[0] = pack2(d[c][0], d[c][1], dummy);
+      pk[1] = pack2(d[c][2], d[c][3], dummy);
+      av[c] = __builtin_bit_cast(vec, pk);
+    }
+#pragma unroll
+    for (int c = 0; c < kTiles; ++c) d[c] = Mf<IN>::mma(h16, av[c], z);
+    uint16_t* tb16 = reinterpret_cast<uint16_t*>(tb) + wbase;
+#pragma unroll
+    for (int c = 0; c < kTiles; ++c) {
+      const uint32_t p01 = pack2(d[c][0], d[c][1], dummy);
+      const uint32_t p23 = pack2(d[c][2], d[c][3], dummy);
+      tb16[taddr((0u << 4) | ((uint32_t)c << 8))] = (uint16_t)p01;
+      tb16[taddr((1u << 4) | ((uint32_t)c << 8))] = (uint16_t)(p01 >> 16);
+      tb16[taddr((2u << 4) | ((uint32_t)c << 8))] = (uint16_t)p23;
+      tb16[taddr((3u << 4) | ((uint32_t)c << 8))] = (uint16_t)(p23 >> 16);
     }
   };
   // passes 3-4 from the transpose buffer into the final float32 layout
-  auto back = [&](const IN* tb, float (&out)[NS]) {
+  auto back = [&](const IN* tb, f32x4 (&out)[kTiles]) {
+    vec av[kTiles];
+#pragma unroll
+    for (int c = 0; c < kTiles; ++c)
+      av[c] = *reinterpret_cast<const vec*>(tb + rbase + taddr((uint32_t)c << 2));
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    f32x4 d[kTiles];
+#pragma unroll
+    for (int c = 0; c < kTiles; ++c) d[c] = Mf<IN>::mma(av[c], h16, z);
 #pragma unroll
     for (int c = 0; c < kTiles; ++c) {
-      const vec av = *reinterpret_cast<const vec*>(tb + taddr(r3 | ((uint32_t)c << 2)));
-      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-      const f32x4 d3 = Mf<IN>::mma(av, h16, z);
-      vec bv;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = (IN)d3[v];
-      const f32x4 d4 = Mf<IN>::mma(m4, bv, z);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) out[c * 4 + v] = d4[v];
+      u2 pk;
+      pk[0] = pack2(d[c][0], d[c][1], dummy);
+      pk[1] = pack2(d[c][2], d[c][3], dummy);
+      av[c] = __builtin_bit_cast(vec, pk);
     }
+#pragma unroll
+    for (int c = 0; c < kTiles; ++c) out[c] = Mf<IN>::mma(m4, av[c], z);
   };
 
   // partial p_hat slice of this work-group: final index of (thread, c, v)
   const int64_t b = (int64_t)1 << a.log2b;
   double* dst = a.partial + ((size_t)g * a.d + t) * b + ((int64_t)uhi << kLB);
   const uint32_t fin = (lg << 12) | (lm << 8) | (w << 5);   // + v + c << 2
-  float acc[NS];
+  f32x4 acc[kTiles];
 #pragma unroll
-  for (int e = 0; e < NS; ++e) acc[e] = 0.f;
+  for (int c = 0; c < kTiles; ++c) acc[c] = (f32x4){0.f, 0.f, 0.f, 0.f};
   int pending = 0;
   bool first_flush = true;
   auto flush = [&]() {
 #pragma unroll
-    for (int e = 0; e < NS; ++e) {
-      double* q = dst + (fin | (uint32_t)(e & 3) | ((uint32_t)(e >> 2) << 2));
-      *q = (first_flush ? 0.0 : *q) + (double)acc[e];
-      acc[e] = 0.f;
+    for (int c = 0; c < kTiles; ++c) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double* q = dst + (fin | (uint32_t)v | ((uint32_t)c << 2));
+        *q = (first_flush ? 0.0 : *q) + (double)acc[c][v];
+      }
+      acc[c] = (f32x4){0.f, 0.f, 0.f, 0.f};
     }
     first_flush = false;
     pending = 0;
@@ -287,15 +344,23 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
       fix_chains_lp<IN, kNT>(rowB, exB, csB, nchB, uhi);
       __syncthreads();
     }
-    front(rowA, idxA, negA, tbufX);
-    front(rowB, idxB, negB, tbufY);
+    front(rowA16, idxA, tbufX);
+    front(rowB16, idxB, tbufY);
     __syncthreads();   // gathers done (rows free), transpose buffers written
     if (k + 1 < k1) load_k(k + 1);
-    float X[NS], Y[NS];
+    f32x4 X[kTiles], Y[kTiles];
     back(tbufX, X);
     back(tbufY, Y);
 #pragma unroll
-    for (int e = 0; e < NS; ++e) acc[e] = fmaf(X[e], Y[e], acc[e]);
+    for (int c = 0; c < kTiles; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[c][v] = fmaf(X[c][v], Y[c][v], acc[c][v]);
+    // keep the per-slot offsets in their packed form (no hoisted copies)
+#pragma unroll
+    for (int q = 0; q < NS / 2; ++q) {
+      asm volatile("" : "+v"(idxA[q]));
+      asm volatile("" : "+v"(idxB[q]));
+    }
     if (++pending == kFlush) flush();
   }
   if (pending > 0 || first_flush) flush();
@@ -308,6 +373,10 @@ static cmm_status launch_mfma_t(const CompressArgs& a0, hipStream_t s) {
   ProfScope prof_("compress", s);
   CompressArgs a = a0;
   const int64_t blocks = ((int64_t)a.d << (a.log2b - kLB)) * a.groups;
+  if (a.n_rows > 16383 || a.n_cols > 16383) {   // byte offset of the zero pad in 15 bits
+    set_error("compress (mfma): needs n_rows, n_cols <= 16383");
+    return CMM_EUNSUPPORTED;
+  }
   const size_t pitch = ((size_t)a.n_rows + 1 + 7) / 8 * 8 + ((size_t)a.n_cols + 1 + 7) / 8 * 8;
   const size_t base = sizeof(IN) * (2 * ((size_t)1 << kLB) + pitch);
   const size_t kMax = 160 * 1024;

@@ -95,6 +95,18 @@ def test_problem_validation(kw):
     assert L.cmm_estimate(ctypes.byref(_problem(**kw)), None, 0, None) == cmm.CMM_EINVAL
 
 
+@pytest.mark.parametrize("kw", [
+    dict(compute=cmm.CMM_BF16, log2b=13),                                   # b_lo = 2^14 needs b >= 2^14
+    dict(compute=cmm.CMM_F16, log2b=16, n_rows=16384, lda=8),               # zero-pad offset in 15 bits
+    dict(compute=cmm.CMM_BF16, log2b=16, n_cols=16384, ldb=16384),
+])
+def test_precision_form_limits(kw):
+    L = _lib_or_skip()
+    n = ctypes.c_size_t(0)
+    assert L.cmm_workspace_size(ctypes.byref(_problem(**kw)), ctypes.byref(n)) == cmm.CMM_EUNSUPPORTED
+    assert b"precision form" in L.cmm_last_error()
+
+
 def test_workspace_size_and_short_workspace():
     L = _lib_or_skip()
     n = ctypes.c_size_t(0)
