@@ -152,12 +152,38 @@ cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes);
 cmm_status cmm_estimate(const cmm_problem* prob, void* workspace, size_t workspace_bytes,
                         void* stream);
 
+/* ------------------------------------------------------ differentiation */
+/* Gradient of L = sum_ij W[i][j] C_hat[i][j] for the mean-over-d estimator
+ * C_hat = (1/d) sum_t L_t(A B) of the same problem (Section 3.1: each
+ * repetition is an unbiased linear estimate; L_t(C)[i][j] is
+ * s1(i) s2(j) times the bucket sum of C at h1(i) xor h2(j), which Algorithm 1
+ * computes through the transforms of Section 3.2):
+ *   dA = dL/dA  (n_rows x n_inner, leading dimension ldda)
+ *   dB = dL/dB  (n_inner x n_cols, leading dimension lddb)
+ * by the adjoint of every step of the forward pass (bucket sums of W, the
+ * transforms, the pointwise products, the transposed count sketch), with the
+ * same tables as the forward call.
+ *   prob: as for cmm_estimate, with estimator = CMM_MEAN and compute CMM_F64 or
+ *         CMM_F32 (else CMM_EUNSUPPORTED); keys NULL to read tab1 / tab2, or the
+ *         forward's keys (the tables are then recomputed, identically);
+ *         p, C_hat are ignored.  Needs log2b >= 11 and n_rows, n_cols <= 65534.
+ *   W: n_rows x n_cols (ldw) of in_dtype; dA, dB of in_dtype, overwritten.
+ * The workspace size comes from cmm_backward_workspace_size.  With compute =
+ * CMM_F32 the transforms run in float32 and the sums over repetitions and
+ * slices in float64; the bucket sums of W are float64 (their order of
+ * addition within a block is not fixed). */
+cmm_status cmm_backward_workspace_size(const cmm_problem* prob, size_t* bytes);
+cmm_status cmm_estimate_backward(const cmm_problem* prob, const void* W, int64_t ldw, void* dA,
+                                 int64_t ldda, void* dB, int64_t lddb, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+
 /* ---------------------------------------------------------- kernel timing */
 /* Tracing for measurement: while enabled, every launch of the library is
  * bracketed by two HIP events recorded on the caller's stream, and
  * cmm_profile_query returns the summed elapsed time and the number of
  * launches of one kernel ("hash", "transpose", "plan", "compress",
- * "reduce", "fwht", "extract", "sketch", "accumulate") since the last
+ * "reduce", "fwht", "extract", "sketch", "accumulate", "wscatter",
+ * "adjoint", "adjoint_reduce") since the last
  * cmm_profile_enable call.  Enabling or disabling discards the records.
  * query waits for the recorded events.  Off by default. */
 void cmm_profile_enable(int on);

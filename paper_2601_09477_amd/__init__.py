@@ -28,7 +28,8 @@ CMM_F64, CMM_F32, CMM_BF16, CMM_F16 = range(4)
 CMM_MEDIAN, CMM_MEAN = range(2)
 
 EXPORTED = ["cmm_hash", "cmm_sketch", "cmm_fwht", "cmm_accumulate", "cmm_extract",
-            "cmm_workspace_size", "cmm_estimate", "cmm_status_string", "cmm_last_error",
+            "cmm_workspace_size", "cmm_estimate", "cmm_backward_workspace_size",
+            "cmm_estimate_backward", "cmm_status_string", "cmm_last_error",
             "cmm_abi_version", "cmm_profile_enable", "cmm_profile_query"]
 
 
@@ -78,6 +79,9 @@ def lib() -> ctypes.CDLL:
         "cmm_extract": [vp, vp, vp, i32, i64, i64, i32, i32, vp, i32, i64, vp],
         "cmm_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
         "cmm_estimate": [ctypes.POINTER(Problem), vp, ctypes.c_size_t, vp],
+        "cmm_backward_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
+        "cmm_estimate_backward": [ctypes.POINTER(Problem), vp, i64, vp, i64, vp, i64, vp,
+                                  ctypes.c_size_t, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -175,6 +179,22 @@ def cmm_estimate(prob: Problem, workspace, workspace_bytes: int, stream=None) ->
                                               workspace_bytes, _stream(stream)))
 
 
+def cmm_backward_workspace_size(prob: Problem) -> int:
+    n = ctypes.c_size_t(0)
+    _check("cmm_backward_workspace_size",
+           lib().cmm_backward_workspace_size(ctypes.byref(prob), ctypes.byref(n)))
+    return n.value
+
+
+def cmm_estimate_backward(prob: Problem, W, dA, dB, workspace, workspace_bytes: int,
+                          stream=None) -> None:
+    """dA, dB of L = sum(W o C_hat) for the mean-over-d estimate of ``prob``."""
+    _check("cmm_estimate_backward",
+           lib().cmm_estimate_backward(ctypes.byref(prob), _ptr(W), W.stride(0), _ptr(dA),
+                                       dA.stride(0), _ptr(dB), dB.stride(0), _ptr(workspace),
+                                       workspace_bytes, _stream(stream)))
+
+
 def cmm_profile_enable(on: bool = True) -> None:
     lib().cmm_profile_enable(1 if on else 0)
 
@@ -214,6 +234,8 @@ def make_problem(A, B, d, log2b, *, keys=None, tab1=None, tab2=None, p=None, C_h
     pr.p = _ptr(p)
     if C_hat is not None:
         pr.C_hat, pr.out_dtype, pr.ldc = _ptr(C_hat), _dtype_code(C_hat), C_hat.stride(0)
+    # the struct holds raw device pointers: keep the tensors alive with it
+    pr._tensors = (A, B, keys, tab1, tab2, p, C_hat)
     return pr
 
 

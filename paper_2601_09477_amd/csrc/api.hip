@@ -338,6 +338,180 @@ cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
   return CMM_OK;
 }
 
+
+// ------------------------------------------------------- backward plan
+// The adjoint of the mean-over-d estimator (see k_adjoint): W scatter into
+// q partials, their sum q, r = 2^-log2b H q, then per k-chunk the fused
+// adjoint kernel's per-(t, u_hi) partials and their reduction into dA, dB.
+struct BackwardPlan {
+  cmm_dtype cdt = CMM_F64;
+  int lb = 0;
+  int groups = 1;
+  int64_t kc = 0;        // k-chunk of the adjoint partials
+  ScatterShape sh{};
+  size_t off_at = 0, off_bc = 0, off_planA = 0, off_planB = 0, off_qpart = 0, off_r = 0,
+         off_pa = 0, off_pb = 0;
+  size_t bytes = 0;
+  bool ok = false;       // a b_lo fits the LDS
+};
+
+cmm_status validate_backward(const cmm_problem* pr, const char* fn) {
+  cmm_status s = validate_problem(pr, fn);
+  if (s != CMM_OK) return s;
+  if (pr->estimator != CMM_MEAN) {
+    set_error(std::string(fn) + ": the differentiation form is the mean-over-d estimator "
+              "(estimator must be CMM_MEAN)");
+    return CMM_EUNSUPPORTED;
+  }
+  if (pr->compute != CMM_F64 && pr->compute != CMM_F32) {
+    set_error(std::string(fn) + ": the adjoint computes in CMM_F64 or CMM_F32");
+    return CMM_EUNSUPPORTED;
+  }
+  if (pr->log2b < 11) {
+    set_error(std::string(fn) + ": the adjoint needs log2b >= 11");
+    return CMM_EUNSUPPORTED;
+  }
+  if (pr->n_rows > 65534 || pr->n_cols > 65534) {
+    set_error(std::string(fn) + ": the adjoint needs n_rows, n_cols <= 65534");
+    return CMM_EUNSUPPORTED;
+  }
+  return CMM_OK;
+}
+
+BackwardPlan make_backward_plan(const cmm_problem* pr) {
+  BackwardPlan P;
+  P.cdt = pr->compute == CMM_F64 ? CMM_F64 : CMM_F32;
+  const size_t es = dtype_size(P.cdt);
+  const int d = pr->d;
+  const int64_t b = (int64_t)1 << pr->log2b;
+  // b_lo = 2^13 for both types (the float32 2^14 variant runs out of registers)
+  const int lb_max = 13;
+  int lb = pr->log2b < lb_max ? pr->log2b : lb_max;
+  while (lb >= 11 && (adjoint_lds_bytes(P.cdt, lb, pr->n_rows, pr->n_cols) > kLdsBytes ||
+                      plan_lds_bytes(pr->n_rows, lb) > kLdsBytes ||
+                      plan_lds_bytes(pr->n_cols, lb) > kLdsBytes))
+    --lb;
+  P.ok = lb >= 11;
+  P.lb = P.ok ? lb : 11;
+  const int64_t units = (int64_t)d << (pr->log2b - P.lb);
+  // adjoint partials: at most 512 MB per chunk
+  const size_t per_k = es * (size_t)units * (size_t)(pr->n_rows + pr->n_cols);
+  int64_t kc = per_k > 0 ? (int64_t)(((size_t)1 << 29) / per_k) : pr->n_inner;
+  if (kc > pr->n_inner) kc = pr->n_inner;
+  if (kc > 65535) kc = 65535;
+  if (kc < 1) kc = 1;
+  P.kc = kc;
+  int64_t g = (2048 + units - 1) / units;
+  if (g > kc) g = kc;
+  if (g < 1) g = 1;
+  while (g > 1 && ((units * g) & 7) != 0 && g < kc) ++g;
+  P.groups = (int)g;
+  // W scatter: float64 windows of 2^13 buckets, about 512 work-groups
+  P.sh.wb = pr->log2b < 13 ? pr->log2b : 13;
+  const int64_t nwin = (int64_t)1 << (pr->log2b - P.sh.wb);
+  int64_t blocks = 512 / ((int64_t)d * nwin);
+  if (blocks < 1) blocks = 1;
+  if (blocks > pr->n_rows) blocks = pr->n_rows > 0 ? pr->n_rows : 1;
+  P.sh.rows_per = pr->n_rows > 0 ? (pr->n_rows + blocks - 1) / blocks : 1;
+  P.sh.blocks = pr->n_rows > 0 ? (pr->n_rows + P.sh.rows_per - 1) / P.sh.rows_per : 1;
+  size_t off = 0;
+  P.off_at = off; off = align_up(off + es * (size_t)pr->n_rows * pr->n_inner, 256);
+  if (P.cdt != pr->in_dtype) {
+    P.off_bc = off; off = align_up(off + es * (size_t)pr->n_inner * pr->n_cols, 256);
+  }
+  P.off_planA = off; off = align_up(off + plan_bytes(d, pr->n_rows, P.lb), 256);
+  P.off_planB = off; off = align_up(off + plan_bytes(d, pr->n_cols, P.lb), 256);
+  P.off_qpart = off; off = align_up(off + sizeof(double) * (size_t)P.sh.blocks * d * b, 256);
+  P.off_r = off; off = align_up(off + sizeof(double) * (size_t)d * b, 256);
+  P.off_pa = off; off = align_up(off + es * (size_t)units * kc * pr->n_rows, 256);
+  P.off_pb = off; off = align_up(off + es * (size_t)units * kc * pr->n_cols, 256);
+  P.bytes = off;
+  return P;
+}
+
+cmm_status run_backward(const cmm_problem* pr, const void* W, int64_t ldw, void* dA,
+                        int64_t ldda, void* dB, int64_t lddb, char* ws, hipStream_t s) {
+  const BackwardPlan P = make_backward_plan(pr);
+  const int d = pr->d;
+  const int64_t b = (int64_t)1 << pr->log2b;
+  cmm_status st;
+  if (pr->keys) {
+    st = launch_hash(pr->keys, d, pr->n_rows, pr->n_cols, pr->log2b, pr->tab1, pr->tab2, s);
+    if (st != CMM_OK) return st;
+  }
+  if (pr->n_inner == 0) return CMM_OK;   // dA and dB are empty
+  if (pr->n_rows == 0 || pr->n_cols == 0) {
+    // C_hat is empty, so L does not depend on A or B
+    if (pr->n_rows > 0 &&
+        (st = launch_zero_matrix(dA, pr->in_dtype, pr->n_rows, pr->n_inner, ldda, s)) != CMM_OK)
+      return st;
+    if (pr->n_cols > 0 &&
+        (st = launch_zero_matrix(dB, pr->in_dtype, pr->n_inner, pr->n_cols, lddb, s)) != CMM_OK)
+      return st;
+    return CMM_OK;
+  }
+  // r = 2^-log2b H q, q = bucket sums of W
+  double* qpart = reinterpret_cast<double*>(ws + P.off_qpart);
+  double* r = reinterpret_cast<double*>(ws + P.off_r);
+  if ((st = launch_wscatter(W, pr->in_dtype, ldw, pr->tab1, pr->tab2, d, pr->n_rows, pr->n_cols,
+                            pr->log2b, P.sh, qpart, s)) != CMM_OK) return st;
+  if ((st = launch_reduce_partials(qpart, (int)P.sh.blocks, (size_t)d * b, r, s)) != CMM_OK)
+    return st;
+  if ((st = launch_fwht(r, CMM_F64, d, pr->log2b, std::ldexp(1.0, -pr->log2b), s)) != CMM_OK)
+    return st;
+  void* At = ws + P.off_at;
+  st = launch_transpose(pr->A, pr->in_dtype, pr->n_rows, pr->n_inner, pr->lda, At, P.cdt, s);
+  if (st != CMM_OK) return st;
+  const void* Bc = pr->B;
+  int64_t ldb = pr->ldb;
+  if (P.cdt != pr->in_dtype) {
+    Bc = ws + P.off_bc;
+    ldb = pr->n_cols;
+    st = launch_convert(pr->B, pr->in_dtype, pr->n_inner, pr->n_cols, pr->ldb,
+                        const_cast<void*>(Bc), P.cdt, s);
+    if (st != CMM_OK) return st;
+  }
+  AdjointArgs aa;
+  CompressArgs& a = aa.c;
+  a.ldb = ldb;
+  a.n_rows = pr->n_rows;
+  a.n_cols = pr->n_cols;
+  a.tab1 = pr->tab1;
+  a.tab2 = pr->tab2;
+  a.planA = carve_plan(ws + P.off_planA, d, pr->n_rows, P.lb);
+  a.planB = carve_plan(ws + P.off_planB, d, pr->n_cols, P.lb);
+  a.d = d;
+  a.log2b = pr->log2b;
+  a.groups = P.groups;
+  a.partial = nullptr;
+  a.ex_cap = 0;
+  a.dma = 0;
+  a.variant = 0;
+  aa.r = r;
+  aa.scale = 1.0 / d;
+  aa.partA = ws + P.off_pa;
+  aa.partB = ws + P.off_pb;
+  if ((st = launch_plan(pr->tab1, d, pr->n_rows, P.lb, a.planA, s)) != CMM_OK) return st;
+  if ((st = launch_plan(pr->tab2, d, pr->n_cols, P.lb, a.planB, s)) != CMM_OK) return st;
+  const int units = d << (pr->log2b - P.lb);
+  const size_t es = dtype_size(P.cdt);
+  for (int64_t kb = 0; kb < pr->n_inner; kb += P.kc) {
+    const int64_t kc = (pr->n_inner - kb) < P.kc ? (pr->n_inner - kb) : P.kc;
+    a.At = static_cast<const char*>(At) + es * (size_t)kb * pr->n_rows;
+    a.B = static_cast<const char*>(Bc) + es * (size_t)kb * ldb;
+    a.n_inner = kc;
+    int64_t g = P.groups < kc ? P.groups : kc;
+    while (g > 1 && (((int64_t)units * g) & 7) != 0 && g < kc) ++g;
+    a.groups = (int)g;
+    if ((st = launch_adjoint(aa, P.cdt, P.lb, s)) != CMM_OK) return st;
+    if ((st = launch_adjoint_reduce(aa.partA, P.cdt, units, kc, pr->n_rows, dA, pr->in_dtype,
+                                    ldda, kb, true, s)) != CMM_OK) return st;
+    if ((st = launch_adjoint_reduce(aa.partB, P.cdt, units, kc, pr->n_cols, dB, pr->in_dtype,
+                                    lddb, kb, false, s)) != CMM_OK) return st;
+  }
+  return CMM_OK;
+}
+
 }  // namespace
 }  // namespace cmm
 
@@ -492,6 +666,46 @@ cmm_status cmm_estimate(const cmm_problem* prob, void* workspace, size_t workspa
   }
   if (!workspace && P.bytes > 0) return invalid("cmm_estimate: workspace is null");
   return run_estimate(prob, static_cast<char*>(workspace), as_stream(stream));
+}
+
+cmm_status cmm_backward_workspace_size(const cmm_problem* prob, size_t* bytes) {
+  cmm_status s = validate_backward(prob, "cmm_backward_workspace_size");
+  if (s != CMM_OK) return s;
+  if (!bytes) return invalid("cmm_backward_workspace_size: bytes is null");
+  const BackwardPlan P = make_backward_plan(prob);
+  if (!P.ok) {
+    set_error("cmm_backward_workspace_size: the rows do not fit the adjoint kernel's LDS");
+    return CMM_EUNSUPPORTED;
+  }
+  *bytes = P.bytes;
+  return CMM_OK;
+}
+
+cmm_status cmm_estimate_backward(const cmm_problem* prob, const void* W, int64_t ldw, void* dA,
+                                 int64_t ldda, void* dB, int64_t lddb, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
+  cmm_status s = validate_backward(prob, "cmm_estimate_backward");
+  if (s != CMM_OK) return s;
+  const cmm_problem* pr = prob;
+  if (pr->n_rows > 0 && pr->n_cols > 0 && !W) return invalid("cmm_estimate_backward: W is null");
+  if (ldw < pr->n_cols) return invalid("cmm_estimate_backward: ldw < n_cols");
+  if (ldda < pr->n_inner) return invalid("cmm_estimate_backward: ldda < n_inner");
+  if (lddb < pr->n_cols) return invalid("cmm_estimate_backward: lddb < n_cols");
+  if ((pr->n_rows > 0 && pr->n_inner > 0 && !dA) || (pr->n_inner > 0 && pr->n_cols > 0 && !dB))
+    return invalid("cmm_estimate_backward: dA / dB is null");
+  const BackwardPlan P = make_backward_plan(pr);
+  if (!P.ok) {
+    set_error("cmm_estimate_backward: the rows do not fit the adjoint kernel's LDS");
+    return CMM_EUNSUPPORTED;
+  }
+  if (workspace_bytes < P.bytes) {
+    set_error("cmm_estimate_backward: workspace of " + std::to_string(workspace_bytes) +
+              " bytes, need " + std::to_string(P.bytes));
+    return CMM_ENOMEM;
+  }
+  if (!workspace && P.bytes > 0) return invalid("cmm_estimate_backward: workspace is null");
+  return run_backward(pr, W, ldw, dA, ldda, dB, lddb, static_cast<char*>(workspace),
+                      as_stream(stream));
 }
 
 }  // extern "C"

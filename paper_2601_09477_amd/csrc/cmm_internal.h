@@ -116,6 +116,37 @@ cmm_status launch_compress(const CompressArgs& a, cmm_dtype dt, int lb, hipStrea
 
 // Precision form: MFMA compress (b_lo = 2^14) on bf16 / fp16 rows.
 cmm_status launch_compress_mfma(const CompressArgs& a, cmm_dtype lp, hipStream_t s);
+// ------------------------------------------------ differentiation form
+// Shape of the W scatter (extract^T): row blocks of rows_per rows, windows
+// of 2^wb buckets.
+struct ScatterShape {
+  int wb;
+  int64_t rows_per;
+  int64_t blocks;
+};
+// q partials [blocks][d][2^log2b] (float64) of the bucket sums of W.
+cmm_status launch_wscatter(const void* W, cmm_dtype wdt, int64_t ldw, const uint32_t* tab1,
+                           const uint32_t* tab2, int d, int64_t n_rows, int64_t n_cols,
+                           int log2b, const ScatterShape& sh, double* part, hipStream_t s);
+
+struct AdjointArgs {
+  CompressArgs c;    // operands of one k-chunk (c.n_inner = chunk length), tables, plans
+  const double* r;   // [d][2^log2b]  2^-log2b H q
+  double scale;      // 1 / d
+  void* partA;       // [d * b_hi][chunk][n_rows]  per-(t, u_hi) columns of dA
+  void* partB;       // [d * b_hi][chunk][n_cols]  per-(t, u_hi) rows of dB
+};
+// out[r][c] = 0 for a rows x cols matrix (leading dimension ld) of dt.
+cmm_status launch_zero_matrix(void* out, cmm_dtype dt, int64_t rows, int64_t cols, int64_t ld,
+                              hipStream_t s);
+size_t adjoint_lds_bytes(cmm_dtype dt, int lb, int64_t n_rows, int64_t n_cols);
+cmm_status launch_adjoint(const AdjointArgs& a, cmm_dtype dt, int lb, hipStream_t s);
+// Sum P partials [P][kc][n] into out rows kb.. (transpose = false) or
+// columns kb.. (transpose = true), ascending p, in float64.
+cmm_status launch_adjoint_reduce(const void* part, cmm_dtype part_dt, int P, int64_t kc,
+                                 int64_t n, void* out, cmm_dtype out_dt, int64_t ld, int64_t kb,
+                                 bool transpose, hipStream_t s);
+
 // bf16 / fp16 copy of a float64 / float32 matrix, transposed or not.
 cmm_status launch_lp_copy(const void* in, cmm_dtype in_dt, int64_t rows, int64_t cols, int64_t ld,
                           void* out, cmm_dtype lp, bool transpose, hipStream_t s);

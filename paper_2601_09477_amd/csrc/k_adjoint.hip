@@ -1,0 +1,459 @@
+// Adjoint of the mean-over-d estimator (the differentiation form).
+//
+// For fixed hash functions the mean estimate
+//   C_hat = (1/d) sum_t L_t(A B),  L_t(C)[i][j] = s1(i) s2(j) p_t[h1(i) xor h2(j)],
+// is bilinear in (A, B), and p_t is Algorithm 1's Compress output
+//   p_t = 2^-m H z_t,  z_t = sum_k X_{t,k} o Y_{t,k},
+//   X_{t,k} = H S1_t A[:, k],  Y_{t,k} = H S2_t B[k, :]
+// (S the count-sketch matrices of Section 3.1, H the Walsh-Hadamard
+// matrix of Section 3.2).  For L = sum_ij W[i][j] C_hat[i][j] each step is
+// run backwards with its transpose:
+//   extract^T    q_t[x] = sum over h1(i) xor h2(j) = x of s1(i) s2(j) W[i][j]
+//   inverse^T    r_t = 2^-m H q_t              (H is symmetric)
+//   product      dX_{t,k} = (r_t / d) o Y_{t,k},  dY_{t,k} = (r_t / d) o X_{t,k}
+//   forward^T    H dX_{t,k},  H dY_{t,k}
+//   sketch^T     dA[i][k] = sum_t s1(i) (H dX_{t,k})[h1(i)]
+//                dB[k][j] = sum_t s2(j) (H dY_{t,k})[h2(j)]
+// (a gather: the transposed count sketch).  Per (t, k) this is four
+// length-b transforms, twice the forward work.
+//
+// The fused kernel mirrors the forward one (Kronecker split b = b_hi b_lo,
+// one work-group per (t, u_hi, k-range), rows staged in LDS and sketched by
+// gather with folded signs).  With V = H_lo (dX slice u_hi),
+//   (H dX)[r] = sum over u_hi of (-1)^popcount(u_hi & r_hi) V_{u_hi}[r_lo],
+// so a work-group contributes s1(i) (-1)^popcount(u_hi & hi(h1 i)) V[lo(h1 i)]
+// to dA[i][k]; these d * b_hi contributions are written as partials and
+// summed in a fixed order by a second kernel (deterministic, no atomics).
+#include "cmm_internal.h"
+#include "wht_regs.h"
+
+namespace cmm {
+namespace {
+
+// ---------------------------------------------------------- extract^T
+// q partials: one work-group per (row block, window of 2^wb buckets,
+// repetition t).  The window lives in LDS as float64 and is summed with LDS
+// atomics (the order of the additions inside a window is not fixed; the
+// partials are then added in ascending block order).
+constexpr int kScatterThreads = 256;
+
+template <typename TW>
+__global__ __launch_bounds__(kScatterThreads) void wscatter_kernel(
+    const TW* __restrict__ W, int64_t ldw, const uint32_t* __restrict__ tab1,
+    const uint32_t* __restrict__ tab2, int64_t n_rows, int64_t n_cols, int log2b, int wb,
+    int64_t rows_per, int64_t blocks, int cache_tab2, double* __restrict__ part) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* q = reinterpret_cast<double*>(smem);
+  const uint32_t wlen = 1u << wb;
+  uint32_t* t2c = reinterpret_cast<uint32_t*>(q + wlen);
+  const int64_t rb = blockIdx.x % blocks;
+  const uint32_t win = (uint32_t)(blockIdx.x / blocks);
+  const int t = blockIdx.y;
+  const int d = gridDim.y;
+  const uint32_t bmask = (uint32_t)(((uint64_t)1 << log2b) - 1u);
+  for (uint32_t x = threadIdx.x; x < wlen; x += kScatterThreads) q[x] = 0.0;
+  const uint32_t* t1 = tab1 + (size_t)t * n_rows;
+  const uint32_t* t2 = tab2 + (size_t)t * n_cols;
+  if (cache_tab2)
+    for (int64_t j = threadIdx.x; j < n_cols; j += kScatterThreads) t2c[j] = t2[j];
+  __syncthreads();
+  const int64_t i0 = (int64_t)rb * rows_per;
+  const int64_t i1 = (i0 + rows_per) < n_rows ? (i0 + rows_per) : n_rows;
+  for (int64_t i = i0; i < i1; ++i) {
+    const uint32_t e1 = t1[i];
+    const TW* wr = W + i * ldw;
+    for (int64_t j = threadIdx.x; j < n_cols; j += kScatterThreads) {
+      const uint32_t e2 = cache_tab2 ? t2c[j] : t2[j];
+      const uint32_t x = (e1 ^ e2) & bmask;
+      if ((x >> wb) == win) {
+        const double v = (double)wr[j];
+        atomicAdd(&q[x & (wlen - 1u)], ((e1 ^ e2) & kSignBit) ? -v : v);
+      }
+    }
+  }
+  __syncthreads();
+  const size_t b = (size_t)1 << log2b;
+  double* dst = part + ((size_t)rb * d + t) * b + ((size_t)win << wb);
+  for (uint32_t x = threadIdx.x; x < wlen; x += kScatterThreads) dst[x] = q[x];
+}
+
+// --------------------------------------------------------- fused adjoint
+template <typename T, int LB>
+__global__ __launch_bounds__((1 << LB) / 32) void adjoint_kernel(AdjointArgs aa) {
+  const CompressArgs& a = aa.c;
+  constexpr int E = Cfg<T, LB>::E;
+  constexpr int NT = Cfg<T, LB>::NT;
+  constexpr int BLO = 1 << LB;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* xbuf = reinterpret_cast<T*>(smem);                          // BLO (+ padding)
+  T* rowA = xbuf + BLO + BLO / 128;                              // n_rows (16-byte aligned)
+  T* rowB = rowA + row_pitch<T>(a.n_rows);                       // n_cols (+ pad)
+  uint32_t* gA = reinterpret_cast<uint32_t*>(rowB + row_pitch<T>(a.n_cols));   // [n_rows]
+  uint32_t* gB = gA + a.n_rows;                                                 // [n_cols]
+  uint2* exl = reinterpret_cast<uint2*>(gA + (a.n_rows + a.n_cols + 1) / 2 * 2);
+  if (threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
+
+  const int b_hi_bits = a.log2b - LB;
+  const int64_t nunits = (int64_t)a.d << b_hi_bits;
+  const int64_t wg = blockIdx.x;
+  const int64_t total = nunits * a.groups;
+  int64_t lin = wg;
+  if ((total & 7) == 0) lin = (wg & 7) * (total >> 3) + (wg >> 3);
+  const int g = (int)(lin / nunits);
+  const int64_t unit = lin - (int64_t)g * nunits;
+  const int t = (int)(unit >> b_hi_bits);
+  const uint32_t uhi = (uint32_t)(unit & (((int64_t)1 << b_hi_bits) - 1));
+  const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
+  const int64_t k0 = (int64_t)g * k_per;
+  const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
+  if (k0 >= k1) return;   // uniform over the work-group
+
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t base1 = ((uint32_t)((lane >> 4) & 1) << 5) | ((uint32_t)((lane >> 5) & 1) << 6) |
+                         ((uint32_t)(lane & 15) << 7) | ((uint32_t)w << 11);
+  const uint32_t* t1 = a.tab1 + (size_t)t * a.n_rows;
+  const uint32_t* t2 = a.tab2 + (size_t)t * a.n_cols;
+  // forward gather: first rows of the thread's buckets with folded signs
+  uint32_t fa[E / 2], fb[E / 2];
+  uint32_t nega = 0, negb = 0;
+  {
+    const int32_t* f1 = a.planA.first + (size_t)t * BLO + base1;
+    const int32_t* f2 = a.planB.first + (size_t)t * BLO + base1;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int32_t r1 = f1[e], r2 = f2[e];
+      const uint32_t en1 = t1[r1 >= 0 ? r1 : 0], en2 = t2[r2 >= 0 ? r2 : 0];
+      const uint32_t s1 = r1 >= 0 ? (en1 >> 31) ^ (__popc(uhi & ((en1 & kBucketMask) >> LB)) & 1u) : 0u;
+      const uint32_t s2 = r2 >= 0 ? (en2 >> 31) ^ (__popc(uhi & ((en2 & kBucketMask) >> LB)) & 1u) : 0u;
+      nega |= s1 << e;
+      negb |= s2 << e;
+      const uint32_t ra = r1 >= 0 ? (uint32_t)r1 : (uint32_t)a.n_rows;
+      const uint32_t rb = r2 >= 0 ? (uint32_t)r2 : (uint32_t)a.n_cols;
+      if (e & 1) { fa[e >> 1] |= ra << 16; fb[e >> 1] |= rb << 16; }
+      else { fa[e >> 1] = ra; fb[e >> 1] = rb; }
+    }
+  }
+  // transposed sketch: LDS address of lo(h(i)) in the natural-order buffer
+  // and the folded sign s(i) (-1)^popcount(u_hi & hi(h(i))) in bit 31
+  for (int64_t i = threadIdx.x; i < a.n_rows; i += NT) {
+    const uint32_t e = t1[i];
+    const uint32_t neg = (e >> 31) ^ (__popc(uhi & ((e & kBucketMask) >> LB)) & 1u);
+    gA[i] = swz(e & (uint32_t)(BLO - 1)) | (neg << 31);
+  }
+  for (int64_t j = threadIdx.x; j < a.n_cols; j += NT) {
+    const uint32_t e = t2[j];
+    const uint32_t neg = (e >> 31) ^ (__popc(uhi & ((e & kBucketMask) >> LB)) & 1u);
+    gB[j] = swz(e & (uint32_t)(BLO - 1)) | (neg << 31);
+  }
+  // collision chains, in LDS when they fit
+  const int32_t* gcA = a.planA.cstart + (size_t)t * (a.n_rows + 2);
+  const int32_t* gcB = a.planB.cstart + (size_t)t * (a.n_cols + 2);
+  const int nchA = a.planA.nchains[t], nchB = a.planB.nchains[t];
+  const int cntA = gcA[nchA], cntB = gcB[nchB];
+  const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
+  const uint2* exA;
+  const uint2* exB;
+  const uint2* gpA = a.planA.pairs + (size_t)t * a.n_rows;
+  const uint2* gpB = a.planB.pairs + (size_t)t * a.n_cols;
+  const int32_t* csA = gcA;
+  const int32_t* csB = gcB;
+  if (ex_lds) {
+    for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gpA[q];
+    for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gpB[q];
+    int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
+    for (int q = threadIdx.x; q <= nchA; q += NT) csl[q] = gcA[q];
+    for (int q = threadIdx.x; q <= nchB; q += NT) csl[nchA + 1 + q] = gcB[q];
+    exA = exl;
+    exB = exl + cntA;
+    csA = csl;
+    csB = csl + nchA + 1;
+  } else {
+    exA = gpA;
+    exB = gpB;
+  }
+
+  const uint32_t w1 = swz(l1p_lane(lane, w));
+  const uint32_t r2lane = swz(l2_lane<LB>(lane, w, false));
+  const uint32_t nat = swz(base1);   // + e: this thread's 32 consecutive buckets
+
+  // (r_t / d) on this slice, in the layout the forward transform leaves
+  T R[E];
+  {
+    const int64_t b = (int64_t)1 << a.log2b;
+    const double* rs = aa.r + (size_t)t * b + ((int64_t)uhi << LB);
+    const uint32_t r2after = l2_lane<LB>(lane, w, true);
+#pragma unroll
+    for (int e = 0; e < E; ++e) R[e] = (T)(rs[r2after | l2_reg<LB>(e, true)] * aa.scale);
+  }
+
+  const T* At = reinterpret_cast<const T*>(a.At);
+  const T* Bm = reinterpret_cast<const T*>(a.B);
+  T* oA = reinterpret_cast<T*>(aa.partA) + (size_t)unit * a.n_inner * a.n_rows;
+  T* oB = reinterpret_cast<T*>(aa.partB) + (size_t)unit * a.n_inner * a.n_cols;
+  const bool dma = a.dma != 0;
+  stage_row<T, NT>(rowA, At + k0 * a.n_rows, a.n_rows, dma);
+  stage_row<T, NT>(rowB, Bm + k0 * a.ldb, a.n_cols, dma);
+
+  for (int64_t k = k0; k < k1; ++k) {
+    if (dma) wait_dma();
+    __syncthreads();
+    if (nchA + nchB > 0) {
+      fix_chains<T, NT>(rowA, exA, csA, nchA, uhi);
+      fix_chains<T, NT>(rowB, exB, csB, nchB, uhi);
+      __syncthreads();
+    }
+    T X[E], Y[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t ra = (e & 1) ? (fa[e >> 1] >> 16) : (fa[e >> 1] & 0xFFFFu);
+      const uint32_t rb = (e & 1) ? (fb[e >> 1] >> 16) : (fb[e >> 1] & 0xFFFFu);
+      X[e] = flip_sign(rowA[ra], (nega << (31 - e)) & 0x80000000u);
+      Y[e] = flip_sign(rowB[rb], (negb << (31 - e)) & 0x80000000u);
+    }
+    __syncthreads();   // the row buffers can be refilled
+    if (k + 1 < k1) {
+      stage_row<T, NT>(rowA, At + (k + 1) * a.n_rows, a.n_rows, dma);
+      stage_row<T, NT>(rowB, Bm + (k + 1) * a.ldb, a.n_cols, dma);
+    }
+    // forward transform of both sketches (as in Compress)
+    pass1(X);
+    pass1(Y);
+#pragma unroll
+    for (int e = 0; e < E; ++e) xbuf[w1 + l1p_reg(e)] = X[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) X[e] = xbuf[r2lane + swz(l2_reg<LB>(e, false))];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xbuf[w1 + l1p_reg(e)] = Y[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) Y[e] = xbuf[r2lane + swz(l2_reg<LB>(e, false))];
+    pass2<LB>(X);
+    pass2<LB>(Y);
+    // dX = (r / d) o Y, dY = (r / d) o X
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const T x = X[e];
+      X[e] = R[e] * Y[e];
+      Y[e] = R[e] * x;
+    }
+    // H_lo again, stages in the reverse order: pass 2 on the current layout
+    // (it ends in the pre-exchange layout), LDS transpose back, pass 1 (it
+    // ends in the gather layout: bucket base1 + e in register e)
+    pass2<LB>(X);
+    pass2<LB>(Y);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xbuf[r2lane + swz(l2_reg<LB>(e, false))] = X[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) X[e] = xbuf[w1 + l1p_reg(e)];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xbuf[r2lane + swz(l2_reg<LB>(e, false))] = Y[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) Y[e] = xbuf[w1 + l1p_reg(e)];
+    pass1(X);
+    pass1(Y);
+    // transposed sketch of each operand from the natural-order buffer
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xbuf[nat + e] = X[e];
+    __syncthreads();
+    {
+      T* o = oA + (size_t)k * a.n_rows;
+      for (int64_t i = threadIdx.x; i < a.n_rows; i += NT) {
+        const uint32_t gi = gA[i];
+        o[i] = flip_sign(xbuf[gi & kBucketMask], gi & kSignBit);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xbuf[nat + e] = Y[e];
+    __syncthreads();
+    {
+      T* o = oB + (size_t)k * a.n_cols;
+      for (int64_t j = threadIdx.x; j < a.n_cols; j += NT) {
+        const uint32_t gj = gB[j];
+        o[j] = flip_sign(xbuf[gj & kBucketMask], gj & kSignBit);
+      }
+    }
+    // xbuf is rewritten next iteration only after the chain barriers
+  }
+}
+
+// ------------------------------------------------------ partial reduction
+// out = sum over p (ascending) of part[p][kk][i], summed in float64:
+//   transpose = 0:  out[(kb + kk) * ld + i]     (dB rows)
+//   transpose = 1:  out[i * ld + kb + kk]       (dA columns)
+template <typename TP, typename TO>
+__global__ __launch_bounds__(256) void adjoint_reduce_rows(const TP* __restrict__ part, int P,
+                                                           int64_t kc, int64_t n,
+                                                           TO* __restrict__ out, int64_t ld,
+                                                           int64_t kb) {
+  const int64_t kk = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) s += (double)part[((size_t)p * kc + kk) * n + i];
+  out[(kb + kk) * ld + i] = (TO)s;
+}
+
+template <typename TP, typename TO>
+__global__ __launch_bounds__(256) void adjoint_reduce_cols(const TP* __restrict__ part, int P,
+                                                           int64_t kc, int64_t n,
+                                                           TO* __restrict__ out, int64_t ld,
+                                                           int64_t kb) {
+  __shared__ double tile[64][65];
+  const int64_t i0 = (int64_t)blockIdx.x * 64, kk0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t kk = kk0 + r, i = i0 + tx;
+    double s = 0.0;
+    if (kk < kc && i < n)
+      for (int p = 0; p < P; ++p) s += (double)part[((size_t)p * kc + kk) * n + i];
+    tile[r][tx] = s;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t i = i0 + r, kk = kk0 + tx;
+    if (i < n && kk < kc) out[i * ld + kb + kk] = (TO)tile[tx][r];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void zero_matrix_kernel(T* __restrict__ out, int64_t rows,
+                                                          int64_t cols, int64_t ld) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
+    if (c < cols) out[r * ld + c] = T(0);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+cmm_status launch_zero_matrix(void* out, cmm_dtype dt, int64_t rows, int64_t cols, int64_t ld,
+                              hipStream_t s) {
+  const dim3 grid((unsigned)((cols + 255) / 256), (unsigned)(rows < 65535 ? rows : 65535));
+  if (dt == CMM_F64)
+    hipLaunchKernelGGL(zero_matrix_kernel<double>, grid, dim3(256), 0, s,
+                       static_cast<double*>(out), rows, cols, ld);
+  else
+    hipLaunchKernelGGL(zero_matrix_kernel<float>, grid, dim3(256), 0, s,
+                       static_cast<float*>(out), rows, cols, ld);
+  return hip_check(hipGetLastError(), "zero fill launch");
+}
+
+cmm_status launch_wscatter(const void* W, cmm_dtype wdt, int64_t ldw, const uint32_t* tab1,
+                           const uint32_t* tab2, int d, int64_t n_rows, int64_t n_cols,
+                           int log2b, const ScatterShape& sh, double* part, hipStream_t s) {
+  ProfScope prof_("wscatter", s);
+  const size_t qbytes = sizeof(double) << sh.wb;
+  const bool cache = qbytes + sizeof(uint32_t) * (size_t)n_cols <= 160 * 1024;
+  const size_t lds = qbytes + (cache ? sizeof(uint32_t) * (size_t)n_cols : 0);
+  const dim3 grid((unsigned)(sh.blocks << (log2b - sh.wb)), (unsigned)d);
+  if (wdt == CMM_F64) {
+    hipError_t e = hipFuncSetAttribute((const void*)wscatter_kernel<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_check(e, "wscatter: set LDS size");
+    hipLaunchKernelGGL(wscatter_kernel<double>, grid, dim3(kScatterThreads), lds, s,
+                       static_cast<const double*>(W), ldw, tab1, tab2, n_rows, n_cols, log2b,
+                       sh.wb, sh.rows_per, sh.blocks, (int)cache, part);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)wscatter_kernel<float>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_check(e, "wscatter: set LDS size");
+    hipLaunchKernelGGL(wscatter_kernel<float>, grid, dim3(kScatterThreads), lds, s,
+                       static_cast<const float*>(W), ldw, tab1, tab2, n_rows, n_cols, log2b,
+                       sh.wb, sh.rows_per, sh.blocks, (int)cache, part);
+  }
+  return hip_check(hipGetLastError(), "wscatter kernel launch");
+}
+
+size_t adjoint_lds_bytes(cmm_dtype dt, int lb, int64_t n_rows, int64_t n_cols) {
+  const size_t es = dtype_size(dt);
+  const int64_t pa = (dt == CMM_F64) ? row_pitch<double>(n_rows) : row_pitch<float>(n_rows);
+  const int64_t pb = (dt == CMM_F64) ? row_pitch<double>(n_cols) : row_pitch<float>(n_cols);
+  size_t s = es * (((size_t)1 << lb) + ((size_t)1 << (lb - 7)) + (size_t)pa + (size_t)pb);
+  s += sizeof(uint32_t) * (size_t)((n_rows + n_cols + 1) / 2 * 2);   // gather words
+  return s;
+}
+
+template <typename T, int LB>
+static cmm_status launch_adjoint_t(const AdjointArgs& a0, hipStream_t s) {
+  ProfScope prof_("adjoint", s);
+  AdjointArgs aa = a0;
+  CompressArgs& a = aa.c;
+  const int64_t blocks = ((int64_t)a.d << (a.log2b - LB)) * a.groups;
+  const size_t kMax = 160 * 1024;
+  const size_t base = adjoint_lds_bytes(sizeof(T) == 8 ? CMM_F64 : CMM_F32, LB, a.n_rows, a.n_cols);
+  if (base > kMax) { set_error("adjoint: rows do not fit in LDS"); return CMM_EUNSUPPORTED; }
+  int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
+  const int64_t want = a.n_rows + a.n_cols;
+  if (cap > want) cap = want;
+  a.ex_cap = cap;
+  const size_t lds = base + sizeof(uint2) * (size_t)cap;
+  constexpr int V = 16 / sizeof(T);
+  a.dma = (a.n_rows % V == 0) && (a.n_cols % V == 0) && (a.ldb % V == 0) &&
+          ((uintptr_t)a.At % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
+  auto kern = adjoint_kernel<T, LB>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return hip_check(e, "adjoint: set LDS size");
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(Cfg<T, LB>::NT), lds, s, aa);
+  return hip_check(hipGetLastError(), "adjoint kernel launch");
+}
+
+cmm_status launch_adjoint(const AdjointArgs& a, cmm_dtype dt, int lb, hipStream_t s) {
+  if (dt == CMM_F64) {
+    switch (lb) {
+      case 11: return launch_adjoint_t<double, 11>(a, s);
+      case 12: return launch_adjoint_t<double, 12>(a, s);
+      case 13: return launch_adjoint_t<double, 13>(a, s);
+    }
+  } else {
+    switch (lb) {
+      case 11: return launch_adjoint_t<float, 11>(a, s);
+      case 12: return launch_adjoint_t<float, 12>(a, s);
+      case 13: return launch_adjoint_t<float, 13>(a, s);
+    }
+  }
+  set_error("adjoint: unsupported b_lo");
+  return CMM_EUNSUPPORTED;
+}
+
+template <typename TP, typename TO>
+static void reduce_t(const void* part, int P, int64_t kc, int64_t n, void* out, int64_t ld,
+                     int64_t kb, bool transpose, hipStream_t s) {
+  const TP* pp = static_cast<const TP*>(part);
+  TO* o = static_cast<TO*>(out);
+  if (transpose) {
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((kc + 63) / 64));
+    hipLaunchKernelGGL((adjoint_reduce_cols<TP, TO>), grid, dim3(256), 0, s, pp, P, kc, n, o, ld, kb);
+  } else {
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)kc);
+    hipLaunchKernelGGL((adjoint_reduce_rows<TP, TO>), grid, dim3(256), 0, s, pp, P, kc, n, o, ld, kb);
+  }
+}
+
+cmm_status launch_adjoint_reduce(const void* part, cmm_dtype part_dt, int P, int64_t kc,
+                                 int64_t n, void* out, cmm_dtype out_dt, int64_t ld, int64_t kb,
+                                 bool transpose, hipStream_t s) {
+  ProfScope prof_("adjoint_reduce", s);
+  if (kc > 65535 && !transpose) { set_error("adjoint reduce: chunk too long"); return CMM_EUNSUPPORTED; }
+  if (part_dt == CMM_F64 && out_dt == CMM_F64)
+    reduce_t<double, double>(part, P, kc, n, out, ld, kb, transpose, s);
+  else if (part_dt == CMM_F32 && out_dt == CMM_F32)
+    reduce_t<float, float>(part, P, kc, n, out, ld, kb, transpose, s);
+  else if (part_dt == CMM_F32 && out_dt == CMM_F64)
+    reduce_t<float, double>(part, P, kc, n, out, ld, kb, transpose, s);
+  else {
+    set_error("adjoint reduce: unsupported types");
+    return CMM_EUNSUPPORTED;
+  }
+  return hip_check(hipGetLastError(), "adjoint reduce launch");
+}
+
+}  // namespace cmm

@@ -107,6 +107,46 @@ def test_precision_form_limits(kw):
     assert b"precision form" in L.cmm_last_error()
 
 
+@pytest.mark.parametrize("kw,status", [
+    (dict(estimator=cmm.CMM_MEDIAN), cmm.CMM_EUNSUPPORTED),       # the adjoint is of the mean
+    (dict(compute=cmm.CMM_BF16, log2b=14), cmm.CMM_EUNSUPPORTED),
+    (dict(log2b=10), cmm.CMM_EUNSUPPORTED),                      # b_lo >= 2^11
+    (dict(d=0), cmm.CMM_EINVAL),
+    (dict(A=None), cmm.CMM_EINVAL),
+])
+def test_backward_validation(kw, status):
+    L = _lib_or_skip()
+    base = dict(estimator=cmm.CMM_MEAN, log2b=12)
+    base.update(kw)
+    n = ctypes.c_size_t(0)
+    pr = _problem(**base)
+    assert L.cmm_backward_workspace_size(ctypes.byref(pr), ctypes.byref(n)) == status
+    assert L.cmm_estimate_backward(ctypes.byref(pr), 1, 8, 1, 8, 1, 8, 1, 1 << 40, None) == status
+
+
+@pytest.mark.parametrize("args", [
+    (None, 8, 1, 8, 1, 8),   # W null
+    (1, 7, 1, 8, 1, 8),      # ldw < n_cols
+    (1, 8, 1, 7, 1, 8),      # ldda < n_inner
+    (1, 8, 1, 8, 1, 7),      # lddb < n_cols
+    (1, 8, None, 8, 1, 8),   # dA null
+])
+def test_backward_arguments_rejected_on_host(args):
+    L = _lib_or_skip()
+    pr = _problem(estimator=cmm.CMM_MEAN, log2b=12)
+    assert L.cmm_estimate_backward(ctypes.byref(pr), *args, 1, 1 << 40, None) == cmm.CMM_EINVAL
+
+
+def test_backward_short_workspace():
+    L = _lib_or_skip()
+    pr = _problem(estimator=cmm.CMM_MEAN, log2b=12, n_rows=64, n_inner=32, n_cols=48, lda=32,
+                  ldb=48)
+    n = ctypes.c_size_t(0)
+    assert L.cmm_backward_workspace_size(ctypes.byref(pr), ctypes.byref(n)) == cmm.CMM_OK
+    assert L.cmm_estimate_backward(ctypes.byref(pr), 1, 48, 1, 32, 1, 48, 1, n.value - 1,
+                                   None) == cmm.CMM_ENOMEM
+
+
 def test_workspace_size_and_short_workspace():
     L = _lib_or_skip()
     n = ctypes.c_size_t(0)
