@@ -8,14 +8,16 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * - All matrix and vector pointers are DEVICE pointers owned by the caller.
- *   The library keeps no pointer after a call returns and allocates no
- *   device memory in any entry point; scratch memory comes from an explicit
- *   workspace argument where one is needed.
+ *   The library keeps no pointer after a call returns (except a batch
+ *   plan, which keeps its problems) and allocates no device memory in any
+ *   entry point; scratch memory comes from an explicit workspace argument
+ *   where one is needed.
  * - `stream` is a hipStream_t passed as void*; NULL means the default
  *   stream.  Every call only enqueues work on that stream and returns; the
  *   results are valid once the stream has reached that point.
  * - Dense matrices are row-major with a leading dimension (elements
- *   between consecutive rows), ld >= number of columns.
+ *   between consecutive rows), ld >= number of columns (not checked for a
+ *   matrix with no elements).
  * - Indices are 0-based.  h1/s1 hash the row index i of A, h2/s2 the column
  *   index j of B (Section 3.1).
  * - A hash TABLE entry is a uint32: bits [0, log2b) hold the bucket, bit 31
@@ -151,6 +153,48 @@ typedef struct {
 cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes);
 cmm_status cmm_estimate(const cmm_problem* prob, void* workspace, size_t workspace_bytes,
                         void* stream);
+
+/* ---------------------------------------------------------- batched form */
+/* Many independent problems (Algorithm 1 each, uneven sizes) with all their
+ * Compress work in ONE persistent kernel launch: work-groups take work items
+ * (problem, repetition, slice of the transform, range of k) from a queue.
+ * The rest of each problem (tables, operand copies, plans, sums of partials,
+ * inverse transform, extract) is enqueued per problem around it; nothing in
+ * cmm_estimate_batched allocates or synchronises, so the whole call can be
+ * captured into a HIP graph and replayed.
+ *   cmm_batch_create: plans a batch of `count` problems (each as for
+ *     cmm_estimate; compute CMM_F64 or CMM_F32, the same for all; log2b >= 11;
+ *     n_rows, n_cols <= 65534).  The problems' pointers are kept and used by
+ *     every later call: the buffers must stay valid while the batch exists.
+ *     Needs a device (pinned host memory holds the work-item table).
+ *   cmm_batch_workspace_size: bytes of workspace (valid for every launch
+ *     configuration, so autotuning never needs more); the workspace must be
+ *     256-byte aligned.
+ *   cmm_batch_autotune: a project-written tuner.  Times the persistent
+ *     launch over candidate configurations -- tile b_lo = 2^11..2^13, inner
+ *     indices per work item 32..256, one or two work-groups per compute unit
+ *     (LDS share), item order (largest problems first / round robin) -- by
+ *     coordinate descent from the default, and keeps the fastest.  Results
+ *     are cached per device and batch signature for the process, and in the
+ *     file named by the environment variable CMM_TUNE_CACHE when set (read,
+ *     then appended).  Synchronises the stream; not for use under capture.
+ *   cmm_batch_set_config / cmm_batch_get_config: choose or read the
+ *     configuration (source: 0 default, 1 tuned, 2 from the cache, 3 set).
+ *     Graphs captured earlier keep the configuration they were captured with.
+ *   cmm_estimate_batched: one estimate of every problem (outputs as for
+ *     cmm_estimate). */
+typedef struct cmm_batch cmm_batch;
+cmm_status cmm_batch_create(const cmm_problem* probs, int count, cmm_batch** batch);
+cmm_status cmm_batch_destroy(cmm_batch* batch);
+cmm_status cmm_batch_workspace_size(const cmm_batch* batch, size_t* bytes);
+cmm_status cmm_batch_autotune(cmm_batch* batch, void* workspace, size_t workspace_bytes,
+                              void* stream);
+cmm_status cmm_batch_set_config(cmm_batch* batch, int log2_blo, int k_per_item, int wg_per_cu,
+                                int order);
+cmm_status cmm_batch_get_config(const cmm_batch* batch, int* log2_blo, int* k_per_item,
+                                int* wg_per_cu, int* order, int* source);
+cmm_status cmm_estimate_batched(cmm_batch* batch, void* workspace, size_t workspace_bytes,
+                                void* stream);
 
 /* ------------------------------------------------------ differentiation */
 /* Gradient of L = sum_ij W[i][j] C_hat[i][j] for the mean-over-d estimator

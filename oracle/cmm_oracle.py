@@ -181,6 +181,22 @@ def bucket_sums(C: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, log2b: int,
     return p
 
 
+def bucket_sums_sparse(rows: np.ndarray, cols: np.ndarray, vals: np.ndarray, tab1: np.ndarray,
+                       tab2: np.ndarray, log2b: int) -> np.ndarray:
+    """The same definition as ``bucket_sums`` for a product C given by its
+    nonzero entries C[rows[e], cols[e]] = vals[e] (zero entries add nothing):
+    p_t[x] = sum over e with h1(rows[e]) xor h2(cols[e]) = x of
+    s1(rows[e]) s2(cols[e]) vals[e]."""
+    d = tab1.shape[0]
+    b = 1 << log2b
+    p = np.zeros((d, b))
+    for t in range(d):
+        idx = bucket(tab1[t][rows]) ^ bucket(tab2[t][cols])
+        w = sign(tab1[t][rows]) * sign(tab2[t][cols]) * np.asarray(vals, dtype=np.float64)
+        p[t] = np.bincount(idx, weights=w, minlength=b)
+    return p
+
+
 def product(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     """C = A B in float64 (library matmul as a step)."""
     return np.asarray(A, dtype=np.float64) @ np.asarray(B, dtype=np.float64)

@@ -29,7 +29,9 @@ CMM_MEDIAN, CMM_MEAN = range(2)
 
 EXPORTED = ["cmm_hash", "cmm_sketch", "cmm_fwht", "cmm_accumulate", "cmm_extract",
             "cmm_workspace_size", "cmm_estimate", "cmm_backward_workspace_size",
-            "cmm_estimate_backward", "cmm_status_string", "cmm_last_error",
+            "cmm_estimate_backward", "cmm_batch_create", "cmm_batch_destroy",
+            "cmm_batch_workspace_size", "cmm_batch_autotune", "cmm_batch_set_config",
+            "cmm_batch_get_config", "cmm_estimate_batched", "cmm_status_string", "cmm_last_error",
             "cmm_abi_version", "cmm_profile_enable", "cmm_profile_query"]
 
 
@@ -83,6 +85,15 @@ def lib() -> ctypes.CDLL:
         "cmm_estimate_backward": [ctypes.POINTER(Problem), vp, i64, vp, i64, vp, i64, vp,
                                   ctypes.c_size_t, vp],
     }
+    sig.update({
+        "cmm_batch_create": [ctypes.POINTER(Problem), i32, ctypes.POINTER(vp)],
+        "cmm_batch_destroy": [vp],
+        "cmm_batch_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "cmm_batch_autotune": [vp, vp, ctypes.c_size_t, vp],
+        "cmm_batch_set_config": [vp, i32, i32, i32, i32],
+        "cmm_batch_get_config": [vp] + [ctypes.POINTER(i32)] * 5,
+        "cmm_estimate_batched": [vp, vp, ctypes.c_size_t, vp],
+    })
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
@@ -272,6 +283,80 @@ def estimate(A, B, d: int, log2b: int, *, keys=None, tab1=None, tab2=None,
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
     cmm_estimate(pr, workspace, nbytes, stream)
     return Estimate(C_hat, p, tab1, tab2)
+
+
+class Batch:
+    """A planned batch of problems (``cmm_batch``): all Compress work of the
+    batch runs in one persistent launch.  Keeps the problems (and so their
+    tensors) alive; ``run`` enqueues one estimate of every problem and can be
+    captured into a graph."""
+
+    def __init__(self, problems):
+        self._problems = list(problems)
+        arr = (Problem * len(self._problems))(*self._problems)
+        h = ctypes.c_void_p()
+        _check("cmm_batch_create", lib().cmm_batch_create(arr, len(self._problems), ctypes.byref(h)))
+        self._h = h
+
+    def workspace_size(self) -> int:
+        n = ctypes.c_size_t(0)
+        _check("cmm_batch_workspace_size", lib().cmm_batch_workspace_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, device="cuda"):
+        """A fresh workspace tensor of the required size (256-byte aligned)."""
+        torch = _torch()
+        return torch.empty(max(self.workspace_size(), 1), dtype=torch.uint8, device=device)
+
+    def autotune(self, workspace, stream=None) -> dict:
+        _check("cmm_batch_autotune", lib().cmm_batch_autotune(
+            self._h, _ptr(workspace), workspace.numel(), _stream(stream)))
+        return self.config()
+
+    def set_config(self, log2_blo: int, k_per_item: int, wg_per_cu: int, order: int) -> None:
+        _check("cmm_batch_set_config",
+               lib().cmm_batch_set_config(self._h, log2_blo, k_per_item, wg_per_cu, order))
+
+    def config(self) -> dict:
+        v = [ctypes.c_int(0) for _ in range(5)]
+        _check("cmm_batch_get_config", lib().cmm_batch_get_config(self._h, *[ctypes.byref(x) for x in v]))
+        return {"log2_blo": v[0].value, "k_per_item": v[1].value, "wg_per_cu": v[2].value,
+                "order": ["largest first", "round robin"][v[3].value],
+                "source": ["default", "tuned", "cache", "set"][v[4].value]}
+
+    def run(self, workspace, stream=None) -> None:
+        _check("cmm_estimate_batched", lib().cmm_estimate_batched(
+            self._h, _ptr(workspace), workspace.numel(), _stream(stream)))
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            lib().cmm_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_batch(pairs, *, compute: str = "f32", estimator: str = "median", dense: bool = True):
+    """Batch of (A, B, d, log2b, keys) tuples.  Returns (Batch, [Estimate])
+    whose outputs are filled by every ``Batch.run``."""
+    torch = _torch()
+    problems, results = [], []
+    for A, B, d, log2b, keys in pairs:
+        dev = A.device
+        if not hasattr(keys, "data_ptr"):
+            keys = keys_tensor(keys, dev)
+        tab1 = torch.empty((d, A.shape[0]), dtype=torch.int32, device=dev)
+        tab2 = torch.empty((d, B.shape[1]), dtype=torch.int32, device=dev)
+        p = torch.empty((d, 1 << log2b), dtype=torch.float64, device=dev)
+        C_hat = torch.empty((A.shape[0], B.shape[1]), dtype=A.dtype, device=dev) if dense else None
+        problems.append(make_problem(A, B, d, log2b, keys=keys, tab1=tab1, tab2=tab2, p=p,
+                                     C_hat=C_hat, compute=compute, estimator=estimator))
+        results.append(Estimate(C_hat, p, tab1, tab2))
+    return Batch(problems), results
 
 
 def tables_to_numpy(tab) -> np.ndarray:

@@ -95,6 +95,8 @@ struct EstimatePlan {
   size_t bytes = 0;
 };
 
+}  // namespace
+
 cmm_status validate_problem(const cmm_problem* pr, const char* fn) {
   if (!pr) return invalid(std::string(fn) + ": null problem");
   if (pr->n_rows < 0 || pr->n_inner < 0 || pr->n_cols < 0)
@@ -115,7 +117,8 @@ cmm_status validate_problem(const cmm_problem* pr, const char* fn) {
   if (pr->compute != CMM_F64 && pr->compute != CMM_F32 && pr->compute != CMM_BF16 &&
       pr->compute != CMM_F16)
     return invalid(std::string(fn) + ": unknown compute type");
-  if (pr->lda < pr->n_inner || pr->ldb < pr->n_cols)
+  // leading dimensions matter only for matrices that hold elements
+  if ((pr->n_rows > 0 && pr->lda < pr->n_inner) || (pr->n_inner > 0 && pr->ldb < pr->n_cols))
     return invalid(std::string(fn) + ": leading dimension smaller than the row length");
   if (pr->n_rows > 0 && pr->n_inner > 0 && !pr->A) return invalid(std::string(fn) + ": A is null");
   if (pr->n_inner > 0 && pr->n_cols > 0 && !pr->B) return invalid(std::string(fn) + ": B is null");
@@ -136,10 +139,12 @@ cmm_status validate_problem(const cmm_problem* pr, const char* fn) {
   if (pr->C_hat) {
     if (!is_f64_or_f32(pr->out_dtype))
       return invalid(std::string(fn) + ": out_dtype must be CMM_F64 or CMM_F32");
-    if (pr->ldc < pr->n_cols) return invalid(std::string(fn) + ": ldc < n_cols");
+    if (pr->n_rows > 0 && pr->ldc < pr->n_cols) return invalid(std::string(fn) + ": ldc < n_cols");
   }
   return CMM_OK;
 }
+
+namespace {
 
 EstimatePlan make_plan(const cmm_problem* pr) {
   EstimatePlan P;
@@ -688,9 +693,11 @@ cmm_status cmm_estimate_backward(const cmm_problem* prob, const void* W, int64_t
   if (s != CMM_OK) return s;
   const cmm_problem* pr = prob;
   if (pr->n_rows > 0 && pr->n_cols > 0 && !W) return invalid("cmm_estimate_backward: W is null");
-  if (ldw < pr->n_cols) return invalid("cmm_estimate_backward: ldw < n_cols");
-  if (ldda < pr->n_inner) return invalid("cmm_estimate_backward: ldda < n_inner");
-  if (lddb < pr->n_cols) return invalid("cmm_estimate_backward: lddb < n_cols");
+  if (pr->n_rows > 0 && ldw < pr->n_cols) return invalid("cmm_estimate_backward: ldw < n_cols");
+  if (pr->n_rows > 0 && ldda < pr->n_inner)
+    return invalid("cmm_estimate_backward: ldda < n_inner");
+  if (pr->n_inner > 0 && lddb < pr->n_cols)
+    return invalid("cmm_estimate_backward: lddb < n_cols");
   if ((pr->n_rows > 0 && pr->n_inner > 0 && !dA) || (pr->n_inner > 0 && pr->n_cols > 0 && !dB))
     return invalid("cmm_estimate_backward: dA / dB is null");
   const BackwardPlan P = make_backward_plan(pr);

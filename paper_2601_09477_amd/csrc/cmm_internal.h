@@ -15,6 +15,9 @@ constexpr uint32_t kBucketMask = 0x7FFFFFFFu;
 // Thread-local message for cmm_last_error().
 void set_error(const std::string& msg);
 
+// Host checks shared by every entry point that takes a cmm_problem.
+cmm_status validate_problem(const cmm_problem* pr, const char* fn);
+
 // Returns CMM_EINVAL after recording msg.
 cmm_status invalid(const std::string& msg);
 
@@ -33,7 +36,7 @@ inline size_t dtype_size(cmm_dtype t) {
   return 0;
 }
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ------------------------------------------------------------ kernel timing
 // While timing is enabled (cmm_profile_enable), launchers bracket their
@@ -109,10 +112,47 @@ struct CompressArgs {
 
 size_t plan_bytes(int d, int64_t n, int lb);
 size_t plan_lds_bytes(int64_t n, int lb);
-PlanView carve_plan(char* p, int d, int64_t n, int lb);
+// The plan's arrays at p (plan_bytes(d, n, lb) bytes), in this order.
+__host__ __device__ inline PlanView carve_plan(char* p, int d, int64_t n, int lb) {
+  const size_t blo = (size_t)1 << lb;
+  PlanView v;
+  v.first = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d * blo, 256);
+  v.pairs = reinterpret_cast<uint2*>(p); p += align_up(sizeof(uint2) * d * (size_t)n, 256);
+  v.cstart = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d * (size_t)(n + 2), 256);
+  v.nchains = reinterpret_cast<int32_t*>(p);
+  return v;
+}
 cmm_status launch_plan(const uint32_t* tab, int d, int64_t n, int lb, const PlanView& pv,
                        hipStream_t s);
 cmm_status launch_compress(const CompressArgs& a, cmm_dtype dt, int lb, hipStream_t s);
+// LDS bytes of the fused kernel (b_lo = 2^lb, 32 elements per thread)
+// before the collision lists.
+size_t compress_lds_base(cmm_dtype dt, int lb, int64_t n_rows, int64_t n_cols);
+
+// ------------------------------------------------------------ batched form
+// One problem of a batch as the persistent kernel reads it: workspace
+// buffers as byte offsets from the workspace base (so that the table does
+// not depend on where the workspace lives), caller buffers as pointers.
+struct BatchPair {
+  int64_t at;              // A^T in the compute type
+  int64_t bc;              // converted B, or -1 to read the caller's B
+  const void* B;
+  int64_t ldb, n_rows, n_cols, n_inner;
+  const uint32_t* tab1;
+  const uint32_t* tab2;
+  int64_t planA, planB;    // plans (carve_plan layout)
+  int64_t partial;         // [groups][d][2^log2b] float64
+  int64_t ex_cap;
+  int d, log2b, groups, dma;
+};
+struct BatchItem {
+  uint32_t pair, unit, group;   // unit = t * b_hi + u_hi
+};
+// Persistent Compress over all items: `wgs` work-groups take items from
+// the queue counter (zeroed before the launch) until none are left.
+cmm_status launch_compress_batched(char* ws, const BatchPair* pairs, const BatchItem* items,
+                                   int n_items, int* queue, cmm_dtype dt, int lb, int wgs,
+                                   size_t lds, hipStream_t s);
 
 // Precision form: MFMA compress (b_lo = 2^14) on bf16 / fp16 rows.
 cmm_status launch_compress_mfma(const CompressArgs& a, cmm_dtype lp, hipStream_t s);

@@ -172,33 +172,20 @@ namespace cmm {
 namespace {
 
 // ------------------------------------------------------------ main kernel
+// One work unit: repetition t, slice u_hi, inner indices [k0, k1) (group g
+// of the partial p_hat).  Starts by writing LDS, so a caller running units
+// back to back separates them with a barrier.
 template <typename T, int LB>
-__global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a) {
+__device__ __forceinline__ void compress_unit(const CompressArgs& a, int g, int t, uint32_t uhi,
+                                              int64_t k0, int64_t k1, unsigned char* smem) {
   constexpr int E = Cfg<T, LB>::E;
   constexpr int NT = Cfg<T, LB>::NT;
   constexpr int BLO = 1 << LB;
-  extern __shared__ __align__(16) unsigned char smem[];
   T* xbuf = reinterpret_cast<T*>(smem);                          // BLO
   T* rowA = xbuf + BLO + BLO / 128;                              // n_rows (16-byte aligned)
   T* rowB = rowA + row_pitch<T>(a.n_rows);                       // n_cols (+ pad)
   uint2* exl = reinterpret_cast<uint2*>(rowB + row_pitch<T>(a.n_cols));
   if (threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
-
-  const int b_hi_bits = a.log2b - LB;
-  const int64_t nunits = (int64_t)a.d << b_hi_bits;
-  // XCD-aware order: work-groups are dealt to the 8 XCDs round robin, so
-  // the groups one XCD runs share a k-range (their input rows hit its L2).
-  const int64_t wg = blockIdx.x;
-  const int64_t total = nunits * a.groups;
-  int64_t lin = wg;
-  if ((total & 7) == 0) lin = (wg & 7) * (total >> 3) + (wg >> 3);
-  const int g = (int)(lin / nunits);
-  const int64_t unit = lin - (int64_t)g * nunits;
-  const int t = (int)(unit >> b_hi_bits);
-  const uint32_t uhi = (uint32_t)(unit & (((int64_t)1 << b_hi_bits) - 1));
-  const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
-  const int64_t k0 = (int64_t)g * k_per;
-  const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t base1 = ((uint32_t)((lane >> 4) & 1) << 5) | ((uint32_t)((lane >> 5) & 1) << 6) |
@@ -318,6 +305,72 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a
   const uint32_t r2after = l2_lane<LB>(lane, w, true);
 #pragma unroll
   for (int e = 0; e < E; ++e) dst[r2after | l2_reg<LB>(e, true)] = (double)acc[e];
+}
+
+template <typename T, int LB>
+__global__ __launch_bounds__((1 << LB) / 32) void compress_kernel(CompressArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b_hi_bits = a.log2b - LB;
+  const int64_t nunits = (int64_t)a.d << b_hi_bits;
+  // XCD-aware order: work-groups are dealt to the 8 XCDs round robin, so
+  // the groups one XCD runs share a k-range (their input rows hit its L2).
+  const int64_t wg = blockIdx.x;
+  const int64_t total = nunits * a.groups;
+  int64_t lin = wg;
+  if ((total & 7) == 0) lin = (wg & 7) * (total >> 3) + (wg >> 3);
+  const int g = (int)(lin / nunits);
+  const int64_t unit = lin - (int64_t)g * nunits;
+  const int t = (int)(unit >> b_hi_bits);
+  const uint32_t uhi = (uint32_t)(unit & (((int64_t)1 << b_hi_bits) - 1));
+  const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
+  const int64_t k0 = (int64_t)g * k_per;
+  const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
+  compress_unit<T, LB>(a, g, t, uhi, k0, k1, smem);
+}
+
+// Persistent form over a batch of problems: every work-group takes work
+// items (pair, repetition, slice, k-range) from a queue, in the order of
+// the item list, until the queue is empty.
+template <typename T, int LB>
+__global__ __launch_bounds__((1 << LB) / 32) void compress_batched_kernel(
+    char* __restrict__ ws, const BatchPair* __restrict__ pairs,
+    const BatchItem* __restrict__ items, int n_items, int* __restrict__ queue) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();   // the previous unit is done with LDS and s_item
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= n_items) break;   // uniform: every wave leaves
+    const BatchItem bi = items[it];
+    const BatchPair bp = pairs[bi.pair];
+    CompressArgs a;
+    a.At = ws + bp.at;
+    a.B = bp.bc >= 0 ? static_cast<const void*>(ws + bp.bc) : bp.B;
+    a.ldb = bp.ldb;
+    a.n_rows = bp.n_rows;
+    a.n_cols = bp.n_cols;
+    a.n_inner = bp.n_inner;
+    a.tab1 = bp.tab1;
+    a.tab2 = bp.tab2;
+    a.planA = carve_plan(ws + bp.planA, bp.d, bp.n_rows, LB);
+    a.planB = carve_plan(ws + bp.planB, bp.d, bp.n_cols, LB);
+    a.d = bp.d;
+    a.log2b = bp.log2b;
+    a.groups = bp.groups;
+    a.partial = reinterpret_cast<double*>(ws + bp.partial);
+    a.ex_cap = bp.ex_cap;
+    a.dma = bp.dma;
+    a.variant = 0;
+    const int b_hi_bits = a.log2b - LB;
+    const int t = (int)(bi.unit >> b_hi_bits);
+    const uint32_t uhi = bi.unit & ((1u << b_hi_bits) - 1u);
+    const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
+    const int64_t k0 = (int64_t)bi.group * k_per;
+    const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
+    compress_unit<T, LB>(a, (int)bi.group, t, uhi, k0, k1, smem);
+  }
 }
 
 // ------------------------------------------------ 16 elements per thread
@@ -583,16 +636,6 @@ size_t plan_bytes(int d, int64_t n, int lb) {
   return s;
 }
 
-PlanView carve_plan(char* p, int d, int64_t n, int lb) {
-  const size_t blo = (size_t)1 << lb;
-  PlanView v;
-  v.first = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d * blo, 256);
-  v.pairs = reinterpret_cast<uint2*>(p); p += align_up(sizeof(uint2) * d * (size_t)n, 256);
-  v.cstart = reinterpret_cast<int32_t*>(p); p += align_up(sizeof(int32_t) * d * (size_t)(n + 2), 256);
-  v.nchains = reinterpret_cast<int32_t*>(p);
-  return v;
-}
-
 size_t plan_lds_bytes(int64_t n, int lb) {
   return sizeof(int32_t) * (2 * ((size_t)1 << lb) + ((size_t)n + 1) / 2 + 2 + kPlanThreads / 64);
 }
@@ -671,6 +714,47 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   if (e != hipSuccess) return hip_check(e, "compress: set LDS size");
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(512), lds, s, a);
   return hip_check(hipGetLastError(), "compress kernel launch");
+}
+
+size_t compress_lds_base(cmm_dtype dt, int lb, int64_t n_rows, int64_t n_cols) {
+  if (dt == CMM_F64)
+    return sizeof(double) * (((size_t)1 << lb) + ((size_t)1 << (lb - 7)) +
+                             (size_t)row_pitch<double>(n_rows) + (size_t)row_pitch<double>(n_cols));
+  return sizeof(float) * (((size_t)1 << lb) + ((size_t)1 << (lb - 7)) +
+                          (size_t)row_pitch<float>(n_rows) + (size_t)row_pitch<float>(n_cols));
+}
+
+template <typename T, int LB>
+static cmm_status launch_batched_t(char* ws, const BatchPair* pairs, const BatchItem* items,
+                                   int n_items, int* queue, int wgs, size_t lds, hipStream_t s) {
+  ProfScope prof_("compress", s);
+  auto kern = compress_batched_kernel<T, LB>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return hip_check(e, "compress (batched): set LDS size");
+  hipLaunchKernelGGL(kern, dim3((unsigned)wgs), dim3(Cfg<T, LB>::NT), lds, s, ws, pairs, items,
+                     n_items, queue);
+  return hip_check(hipGetLastError(), "compress (batched) launch");
+}
+
+cmm_status launch_compress_batched(char* ws, const BatchPair* pairs, const BatchItem* items,
+                                   int n_items, int* queue, cmm_dtype dt, int lb, int wgs,
+                                   size_t lds, hipStream_t s) {
+  if (dt == CMM_F64) {
+    switch (lb) {
+      case 11: return launch_batched_t<double, 11>(ws, pairs, items, n_items, queue, wgs, lds, s);
+      case 12: return launch_batched_t<double, 12>(ws, pairs, items, n_items, queue, wgs, lds, s);
+      case 13: return launch_batched_t<double, 13>(ws, pairs, items, n_items, queue, wgs, lds, s);
+    }
+  } else {
+    switch (lb) {
+      case 11: return launch_batched_t<float, 11>(ws, pairs, items, n_items, queue, wgs, lds, s);
+      case 12: return launch_batched_t<float, 12>(ws, pairs, items, n_items, queue, wgs, lds, s);
+      case 13: return launch_batched_t<float, 13>(ws, pairs, items, n_items, queue, wgs, lds, s);
+    }
+  }
+  set_error("compress (batched): unsupported b_lo");
+  return CMM_EUNSUPPORTED;
 }
 
 cmm_status launch_compress(const CompressArgs& a, cmm_dtype dt, int lb, hipStream_t s) {

@@ -215,6 +215,28 @@ def test_identity_hash_reduces_to_matmul():
     assert np.array_equal(O.extract(p, t1, t2, "mean"), brute)
 
 
+def test_bucket_sums_sparse_equals_dense_definition():
+    # the nonzero-entry form of the bucket sums against the dense form on a
+    # sparse product, and against brute force over the entries
+    rng = np.random.default_rng(4)
+    n_rows, n_cols, log2b = 40, 30, 6
+    C = np.zeros((n_rows, n_cols))
+    pos = rng.choice(n_rows * n_cols, size=50, replace=False)
+    C.flat[pos] = rng.standard_normal(50)
+    t1, t2 = O.hash_tables(draw_keys(3, 61), n_rows, n_cols, log2b)
+    r, c = np.nonzero(C)
+    ps = O.bucket_sums_sparse(r, c, C[r, c], t1, t2, log2b)
+    pd = O.bucket_sums(C, t1, t2, log2b)
+    assert np.allclose(ps, pd, rtol=0, atol=1e-14)
+    brute = np.zeros_like(ps)
+    for t in range(3):
+        for i, j in zip(r, c):
+            x = (int(t1[t][i]) & 63) ^ (int(t2[t][j]) & 63)
+            sg = (-1.0 if t1[t][i] >> 31 else 1.0) * (-1.0 if t2[t][j] >> 31 else 1.0)
+            brute[t, x] += sg * C[i, j]
+    assert np.allclose(ps, brute, rtol=0, atol=1e-14)
+
+
 def test_bucket_sums_brute_force_tiny():
     rng = np.random.default_rng(6)
     C = rng.integers(-9, 9, (5, 6)).astype(float)
