@@ -8,7 +8,10 @@ Default workload: n = 4096, b = 2^16, d = 9, float64, +-1 entries with
 4096 planted pairs A[i] = 4 B[:, j] (synthetic).  The metric is the
 DGEMM-equivalent rate 2 n^3 / t, reported with heavy-hitter recall; the
 fused compress kernel is reported against the FP64 VALU add roofline, and
-the CPU oracle is timed on the host beside it.
+the CPU oracle is timed on the host beside it.  Beside it: the precision
+form (bf16 / fp16 on MFMA, n = 8192), the batched form (64 uneven pairs in
+one persistent launch, autotuned, graph replays) and the differentiation
+form (forward + adjoint at n = 2048).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -30,6 +33,10 @@ sys.path.insert(0, ROOT)
 PEAK_F64_ADD = 256 * 4 * 16 * 2.4e9
 PEAK_HBM = 8.0e12
 PEAK_MFMA_16 = 2.5e15   # dense bf16 / fp16 matrix-core peak
+# float32 adds: 2 per lane and cycle with packed instructions (78.6e12/s);
+# this build keeps packed float32 instructions out of its code, which
+# leaves one per lane and cycle (39.3e12/s) attainable.
+PEAK_F32_ADD = 2 * 256 * 4 * 16 * 2.4e9
 
 
 def compress_ops(n: int, d: int, log2b: int) -> float:
@@ -149,6 +156,124 @@ def precision_form(steps: int, warmup: int) -> dict:
     return out
 
 
+def batched_form(steps: int, warmup: int) -> dict:
+    """The batched form: 64 pairs, n uniform over {512, 1024, 2048, 4096},
+    b = 16 n, d = 7, float32, all Compress work in one persistent launch;
+    autotuned, then timed eagerly and as replays of a captured graph."""
+    import torch
+
+    import paper_2601_09477_amd as cmm
+    from workloads import batched_mix
+    from workloads.metrics import planted_recall
+    ws_list = batched_mix(0)
+    pairs = [(torch.from_numpy(w.A).to("cuda", torch.float32),
+              torch.from_numpy(w.B).to("cuda", torch.float32), w.d, w.log2b, w.keys)
+             for w in ws_list]
+    batch, res = cmm.make_batch(pairs, compute="f32")
+    ws = batch.workspace()
+    t0 = time.perf_counter()
+    cfg = batch.autotune(ws)
+    tune_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        batch.run(ws)
+    torch.cuda.synchronize()
+    cmm.cmm_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.run(ws)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) / steps * 1e3
+    ms_c, n_c = cmm.cmm_profile_query("compress")
+    cmm.cmm_profile_enable(False)
+    avg_c = ms_c / max(1, n_c) * 1e-3
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.run(ws)
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(g):
+        batch.run(ws)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) / steps * 1e3
+    flops = sum(2.0 * w.n ** 3 for w in ws_list)
+    ops = sum(compress_ops(w.n, w.d, w.log2b) for w in ws_list)
+    recalled = planted = 0
+    for q, w in enumerate(ws_list):
+        if w.kind == "planted":
+            r = planted_recall(res[q].C_hat.cpu().numpy(), w.rows, w.cols, w.tau)
+            recalled += r["recalled"]
+            planted += r["planted"]
+    out = {"workload": "64 pairs, n in {512,1024,2048,4096} (seed 0), b=16n, d=7, float32; "
+                       "32 exactly-sparse Hadamard pairs, 32 planted +-1 pairs",
+           "sizes": {str(n): sum(1 for w in ws_list if w.n == n) for n in (512, 1024, 2048, 4096)},
+           "config": cfg, "autotune_s": tune_s,
+           "ms_per_batch_eager": eager_ms, "ms_per_batch_graph": graph_ms,
+           "value": flops / (graph_ms * 1e-3) / 1e12, "unit": "TFLOP/s-equivalent (sum 2n^3/s)",
+           "compress_ms": avg_c * 1e3,
+           "planted_recall": {"recalled": recalled, "planted": planted},
+           "compress_roofline": {
+               "bound": "alu", "achieved": ops / avg_c / 1e12, "peak": PEAK_F32_ADD / 1e12,
+               "unit": "TFLOP/s", "frac": ops / avg_c / PEAK_F32_ADD,
+               "note": "float32 add peak with packed math; 39.3 without"}}
+    batch.close()
+    del ws, res, pairs
+    torch.cuda.empty_cache()
+    return out
+
+
+def differentiation_form(steps: int, warmup: int) -> dict:
+    """The differentiation form at n = 2048, b = 2^15, d = 7, float32, mean
+    estimator: forward (cmm_estimate) plus the hand-written adjoint
+    (cmm_estimate_backward) through the autograd Function."""
+    import torch
+
+    import paper_2601_09477_amd as cmm
+    from paper_2601_09477_amd.autograd import compressed_matmul
+    from workloads import gradient_2048
+    w = gradient_2048(0)
+    A = torch.from_numpy(w.A).to("cuda", torch.float32).requires_grad_(True)
+    B = torch.from_numpy(w.B).to("cuda", torch.float32).requires_grad_(True)
+    W = torch.from_numpy(w.W).to("cuda", torch.float32)
+
+    def step():
+        A.grad = None
+        B.grad = None
+        C = compressed_matmul(A, B, w.d, w.log2b, keys=w.keys, compute="f32")
+        C.backward(W)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    cmm.cmm_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    kern = {k: cmm.cmm_profile_query(k) for k in ("compress", "extract", "wscatter", "adjoint",
+                                                  "adjoint_reduce", "plan", "transpose", "fwht")}
+    cmm.cmm_profile_enable(False)
+    b = 1 << w.log2b
+    n, d = w.n, w.d
+    # adjoint: forward transforms again, the transposed transforms (4 d n b log2 b),
+    # the products (2 d n b), sketches and transposed sketches (4 d n^2)
+    adj_ops = 4.0 * d * n * b * w.log2b + 2.0 * d * n * b + 4.0 * d * n * n
+    ms_a, n_a = kern["adjoint"]
+    avg_a = ms_a / max(1, n_a) * 1e-3
+    return {"workload": "Gaussian + 2048 planted rows (3x), n=2048, b=2^15, d=7, float32, mean",
+            "ms_per_step_fwd_bwd": ms,
+            "kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
+            "adjoint_roofline": {"bound": "alu", "achieved": adj_ops / avg_a / 1e12,
+                                 "peak": PEAK_F32_ADD / 1e12, "unit": "TFLOP/s",
+                                 "frac": adj_ops / avg_a / PEAK_F32_ADD}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +321,8 @@ def main() -> int:
     del C_hat
     if not args.no_forms:
         out["mfma_form"] = precision_form(max(3, args.steps // 4), 1)
+        out["batched_form"] = batched_form(max(3, args.steps // 4), 1)
+        out["differentiation_form"] = differentiation_form(max(3, args.steps // 2), 2)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))
