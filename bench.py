@@ -39,6 +39,32 @@ PEAK_MFMA_16 = 2.5e15   # dense bf16 / fp16 matrix-core peak
 PEAK_F32_ADD = 2 * 256 * 4 * 16 * 2.4e9
 
 
+# HBM bytes of one float64 compress launch at the default workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
+#   bench.py --steps 2 --warmup 1 --no-cpu --no-forms --copy-probe 1024
+# each scaled by what the same counter reads for the probe's plain 1 GiB
+# elementwise copy (fetch x2.000, write x1.000; profiles/
+# compress_f64_planted_n4096_b2e16_d9_counters.md).  Reported only while the
+# kernel's sources are the ones the counters were taken on.
+TRAFFIC_SOURCES = ["paper_2601_09477_amd/csrc/k_compress.hip",
+                   "paper_2601_09477_amd/csrc/wht_regs.h",
+                   "paper_2601_09477_amd/csrc/cmm_internal.h"]
+TRAFFIC_MEASURED = {"sha1": "b1af5188b46b091906f5e169ed12fa07b62afc7b",
+                    "fetch_bytes": 2.3027e9, "write_bytes": 1.3684e8}
+
+
+def compress_traffic():
+    """Measured HBM bytes per launch, or None once the kernel has changed."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC_MEASURED["sha1"]:
+        return None
+    return TRAFFIC_MEASURED["fetch_bytes"] + TRAFFIC_MEASURED["write_bytes"]
+
+
 def compress_ops(n: int, d: int, log2b: int) -> float:
     """Algorithmic work of Compress (per launch = all k): 2 d n b log2 b
     butterfly adds + 2 d n^2 sketch adds + d n b accumulate FMAs."""
@@ -282,6 +308,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form leg")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run one plain elementwise copy of MIB MiB (read MIB, write "
+                         "MIB): the reference dispatch for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -291,6 +320,13 @@ def main() -> int:
     from workloads import planted_4096
     from workloads.metrics import planted_recall
 
+    if args.copy_probe > 0:
+        import torch
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     w = planted_4096(args.seed)
     n, d, log2b = w.n, w.d, w.log2b
     ms_per_step, kern, C_hat, _ = run_estimate(w, "f64", args.steps, args.warmup)
@@ -316,7 +352,7 @@ def main() -> int:
                      "achieved": achieved / 1e12, "peak": PEAK_F64_ADD / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_F64_ADD,
                      "work_per_launch": ops, "avg_launch_ms": avg_comp * 1e3,
-                     "traffic": None},
+                     "traffic": compress_traffic()},
     }
     del C_hat
     if not args.no_forms:
