@@ -171,10 +171,11 @@ cmm_status cmm_estimate(const cmm_problem* prob, void* workspace, size_t workspa
  *     configuration, so autotuning never needs more); the workspace must be
  *     256-byte aligned.
  *   cmm_batch_autotune: a project-written tuner.  Times the persistent
- *     launch over candidate configurations -- tile b_lo = 2^11..2^13, inner
- *     indices per work item 32..256, one or two work-groups per compute unit
- *     (LDS share), item order (largest problems first / round robin) -- by
- *     coordinate descent from the default, and keeps the fastest.  Results
+ *     launch over candidate configurations -- tile b_lo = 2^11..2^13, radix
+ *     (16 elements per thread, b_lo = 2^13, or 32), inner indices per work
+ *     item 32..256, one or two work-groups per compute unit (LDS share),
+ *     item order (largest problems first / round robin) -- by coordinate
+ *     descent from the default, and keeps the fastest.  Results
  *     are cached per device and batch signature for the process, and in the
  *     file named by the environment variable CMM_TUNE_CACHE when set (read,
  *     then appended).  Synchronises the stream; not for use under capture.
@@ -190,9 +191,9 @@ cmm_status cmm_batch_workspace_size(const cmm_batch* batch, size_t* bytes);
 cmm_status cmm_batch_autotune(cmm_batch* batch, void* workspace, size_t workspace_bytes,
                               void* stream);
 cmm_status cmm_batch_set_config(cmm_batch* batch, int log2_blo, int k_per_item, int wg_per_cu,
-                                int order);
+                                int order, int radix);
 cmm_status cmm_batch_get_config(const cmm_batch* batch, int* log2_blo, int* k_per_item,
-                                int* wg_per_cu, int* order, int* source);
+                                int* wg_per_cu, int* order, int* radix, int* source);
 cmm_status cmm_estimate_batched(cmm_batch* batch, void* workspace, size_t workspace_bytes,
                                 void* stream);
 

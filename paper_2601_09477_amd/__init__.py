@@ -90,8 +90,8 @@ def lib() -> ctypes.CDLL:
         "cmm_batch_destroy": [vp],
         "cmm_batch_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "cmm_batch_autotune": [vp, vp, ctypes.c_size_t, vp],
-        "cmm_batch_set_config": [vp, i32, i32, i32, i32],
-        "cmm_batch_get_config": [vp] + [ctypes.POINTER(i32)] * 5,
+        "cmm_batch_set_config": [vp, i32, i32, i32, i32, i32],
+        "cmm_batch_get_config": [vp] + [ctypes.POINTER(i32)] * 6,
         "cmm_estimate_batched": [vp, vp, ctypes.c_size_t, vp],
     })
     for name, args in sig.items():
@@ -313,16 +313,17 @@ class Batch:
             self._h, _ptr(workspace), workspace.numel(), _stream(stream)))
         return self.config()
 
-    def set_config(self, log2_blo: int, k_per_item: int, wg_per_cu: int, order: int) -> None:
+    def set_config(self, log2_blo: int, k_per_item: int, wg_per_cu: int, order: int,
+                   radix: int = 16) -> None:
         _check("cmm_batch_set_config",
-               lib().cmm_batch_set_config(self._h, log2_blo, k_per_item, wg_per_cu, order))
+               lib().cmm_batch_set_config(self._h, log2_blo, k_per_item, wg_per_cu, order, radix))
 
     def config(self) -> dict:
-        v = [ctypes.c_int(0) for _ in range(5)]
+        v = [ctypes.c_int(0) for _ in range(6)]
         _check("cmm_batch_get_config", lib().cmm_batch_get_config(self._h, *[ctypes.byref(x) for x in v]))
         return {"log2_blo": v[0].value, "k_per_item": v[1].value, "wg_per_cu": v[2].value,
-                "order": ["largest first", "round robin"][v[3].value],
-                "source": ["default", "tuned", "cache", "set"][v[4].value]}
+                "order": ["largest first", "round robin"][v[3].value], "radix": v[4].value,
+                "source": ["default", "tuned", "cache", "set"][v[5].value]}
 
     def run(self, workspace, stream=None) -> None:
         _check("cmm_estimate_batched", lib().cmm_estimate_batched(

@@ -61,7 +61,6 @@ ProfScope::~ProfScope() {
 
 namespace {
 
-int g_compress_variant = 0;   // selected by cmm_set_option("compress_variant")
 
 constexpr int kMaxLog2b = 30;
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -175,13 +174,15 @@ EstimatePlan make_plan(const cmm_problem* pr) {
   }
   // fused path: b_lo = 2^lb with 11 <= lb <= log2b; LDS holds the transpose
   // buffer and one staged row of each operand.
-  const int lb_max = P.cdt == CMM_F64 ? 13 : 14;
+  // b_lo = 2^13 for both types: the 16-element layout (512 threads) for
+  // b >= 2^13, the 32-element one below
+  const int lb_max = 13;
   int lb = pr->log2b < lb_max ? pr->log2b : lb_max;
   auto fits = [&](int l) {
     const size_t v = 16 / es;
     const size_t ra = ((size_t)pr->n_rows + v) / v * v, rb = ((size_t)pr->n_cols + v) / v * v;
-    // the float64 b_lo = 2^13 kernel can also time-share one row buffer
-    const size_t rows = (P.cdt == CMM_F64 && l == 13) ? (ra > rb ? ra : rb) : ra + rb;
+    // the b_lo = 2^13 kernel can also time-share one row buffer
+    const size_t rows = (l == 13) ? (ra > rb ? ra : rb) : ra + rb;
     const size_t xb = ((size_t)1 << l) + ((size_t)1 << (l - 6)) + 16;
     return (xb + rows) * es <= kLdsBytes && plan_lds_bytes(pr->n_rows, l) <= kLdsBytes &&
            plan_lds_bytes(pr->n_cols, l) <= kLdsBytes;
@@ -299,7 +300,7 @@ cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
     a.partial = reinterpret_cast<double*>(ws + P.off_part);
     a.ex_cap = 0;
     a.dma = 0;
-    a.variant = g_compress_variant;
+    a.variant = 0;
     if ((st = launch_plan(pr->tab1, d, pr->n_rows, P.lb, a.planA, s)) != CMM_OK) return st;
     if ((st = launch_plan(pr->tab2, d, pr->n_cols, P.lb, a.planB, s)) != CMM_OK) return st;
     if ((st = launch_compress(a, P.cdt, P.lb, s)) != CMM_OK) return st;

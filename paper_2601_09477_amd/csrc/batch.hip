@@ -39,10 +39,17 @@ struct BatchConfig {
   int kgrain = 64;     // inner indices per work item
   int wg_per_cu = 1;   // LDS share: 160 KB / wg_per_cu per work-group
   int order = 0;       // 0: largest problems first; 1: round robin over problems
+  int radix = 16;      // elements per thread: 16 (b_lo = 2^13) or 32
   bool operator<(const BatchConfig& o) const {
-    return std::tie(lb, kgrain, wg_per_cu, order) < std::tie(o.lb, o.kgrain, o.wg_per_cu, o.order);
+    return std::tie(lb, kgrain, wg_per_cu, order, radix) <
+           std::tie(o.lb, o.kgrain, o.wg_per_cu, o.order, o.radix);
   }
 };
+
+size_t lds_base(cmm_dtype dt, const BatchConfig& c, int64_t n_rows, int64_t n_cols) {
+  return c.radix == 16 ? compress16_lds_base(dt, n_rows, n_cols)
+                       : compress_lds_base(dt, c.lb, n_rows, n_cols);
+}
 
 struct BatchLayout {
   bool ok = false;
@@ -93,10 +100,10 @@ BatchLayout make_layout(const cmm_batch& b, const BatchConfig& c) {
   for (int i = 0; i < n; ++i) {
     const cmm_problem& p = b.probs[i];
     if (!active(p)) continue;
-    if (p.log2b < c.lb) return L;
+    if (p.log2b < c.lb || (c.radix == 16 && c.lb != 13)) return L;
     groups[i] = (p.n_inner + c.kgrain - 1) / c.kgrain;
     units[i] = (int64_t)p.d << (p.log2b - c.lb);
-    const size_t base = compress_lds_base(b.cdt, c.lb, p.n_rows, p.n_cols);
+    const size_t base = lds_base(b.cdt, c, p.n_rows, p.n_cols);
     if (base > lds_cap) return L;
     const size_t want = base + sizeof(uint2) * (size_t)(p.n_rows + p.n_cols + (p.n_rows + p.n_cols + 8) / 2);
     lds = std::max(lds, std::min(want, lds_cap));
@@ -162,7 +169,7 @@ BatchLayout make_layout(const cmm_batch& b, const BatchConfig& c) {
     bp.planA = (int64_t)off; off = align_up(off + plan_bytes(p.d, p.n_rows, c.lb), 256);
     bp.planB = (int64_t)off; off = align_up(off + plan_bytes(p.d, p.n_cols, c.lb), 256);
     bp.partial = (int64_t)off; off = align_up(off + sizeof(double) * groups[i] * p.d * blen, 256);
-    const size_t base = compress_lds_base(b.cdt, c.lb, p.n_rows, p.n_cols);
+    const size_t base = lds_base(b.cdt, c, p.n_rows, p.n_cols);
     int64_t cap = (int64_t)((lds - std::min(lds, base)) / sizeof(uint2));
     bp.ex_cap = std::min<int64_t>(cap, p.n_rows + p.n_cols);
     // 16-byte row copies: the workspace is 256-byte aligned, the caller's B is checked here
@@ -183,9 +190,11 @@ const BatchLayout& layout_of(cmm_batch& b, const BatchConfig& c) {
 std::vector<BatchConfig> candidates(const cmm_batch& b) {
   std::vector<BatchConfig> out;
   for (int lb : b.lbs)
-    for (int kg : kKGrains)
-      for (int wg = 1; wg <= 2; ++wg)
-        for (int ord = 0; ord <= 1; ++ord) out.push_back(BatchConfig{lb, kg, wg, ord});
+    for (int radix : {16, 32})
+      if (radix == 32 || lb == 13)
+        for (int kg : kKGrains)
+          for (int wg = 1; wg <= 2; ++wg)
+            for (int ord = 0; ord <= 1; ++ord) out.push_back(BatchConfig{lb, kg, wg, ord, radix});
   return out;
 }
 
@@ -257,7 +266,7 @@ cmm_status compress_all(cmm_batch& b, const BatchConfig& c, char* ws, hipStream_
   return launch_compress_batched(ws, reinterpret_cast<const BatchPair*>(ws + L.off_desc),
                                  reinterpret_cast<const BatchItem*>(ws + L.off_items),
                                  (int)L.items.size(), reinterpret_cast<int*>(ws + L.off_queue),
-                                 b.cdt, c.lb, wgs, L.lds, s);
+                                 b.cdt, c.lb, c.radix, wgs, L.lds, s);
 }
 
 // Per-problem work after Compress: partial sums, inverse transform, extract.
@@ -331,7 +340,7 @@ void read_tune_file_locked() {
     std::istringstream is(line);
     uint64_t key;
     BatchConfig c;
-    if (is >> std::hex >> key >> std::dec >> c.lb >> c.kgrain >> c.wg_per_cu >> c.order)
+    if (is >> std::hex >> key >> std::dec >> c.lb >> c.kgrain >> c.wg_per_cu >> c.order >> c.radix)
       g_tune[key] = c;
   }
 }
@@ -342,7 +351,7 @@ void write_tune_entry_locked(uint64_t key, const BatchConfig& c) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
   f << std::hex << key << std::dec << ' ' << c.lb << ' ' << c.kgrain << ' ' << c.wg_per_cu << ' '
-    << c.order << '\n';
+    << c.order << ' ' << c.radix << '\n';
 }
 
 cmm_status time_config(cmm_batch& b, const BatchConfig& c, char* ws, hipStream_t s, float* ms) {
@@ -401,7 +410,7 @@ cmm_status cmm_batch_create(const cmm_problem* probs, int count, cmm_batch** out
     bool ok = true;
     for (const cmm_problem& p : b->probs) {
       if (!active(p)) continue;
-      ok = ok && p.log2b >= lb && compress_lds_base(b->cdt, lb, p.n_rows, p.n_cols) <= kLds &&
+      ok = ok && p.log2b >= lb && compress_lds_base(b->cdt, lb, p.n_rows, p.n_cols) <= kLds - 256 &&
            plan_lds_bytes(p.n_rows, lb) <= kLds && plan_lds_bytes(p.n_cols, lb) <= kLds;
     }
     if (ok) b->lbs.push_back(lb);
@@ -416,7 +425,7 @@ cmm_status cmm_batch_create(const cmm_problem* probs, int count, cmm_batch** out
     if (L.ok) mx = std::max(mx, L.bytes);
   }
   b->ws_bytes = mx;
-  b->cfg = BatchConfig{b->lbs.back(), 64, 1, 0};
+  b->cfg = BatchConfig{b->lbs.back(), 64, 1, 0, b->lbs.back() == 13 ? 16 : 32};
   if (!layout_of(*b, b->cfg).ok) {
     bool found = false;
     for (const BatchConfig& c : candidates(*b))
@@ -444,9 +453,9 @@ cmm_status cmm_batch_workspace_size(const cmm_batch* batch, size_t* bytes) {
 }
 
 cmm_status cmm_batch_set_config(cmm_batch* batch, int log2_blo, int k_per_item, int wg_per_cu,
-                                int order) {
+                                int order, int radix) {
   if (!batch) return invalid("cmm_batch_set_config: null batch");
-  const BatchConfig c{log2_blo, k_per_item, wg_per_cu, order};
+  const BatchConfig c{log2_blo, k_per_item, wg_per_cu, order, radix};
   bool known = false;
   for (const BatchConfig& x : candidates(*batch)) known = known || (!(x < c) && !(c < x));
   if (!known) return invalid("cmm_batch_set_config: not a candidate configuration");
@@ -463,9 +472,10 @@ cmm_status cmm_batch_set_config(cmm_batch* batch, int log2_blo, int k_per_item, 
 }
 
 cmm_status cmm_batch_get_config(const cmm_batch* batch, int* log2_blo, int* k_per_item,
-                                int* wg_per_cu, int* order, int* source) {
-  if (!batch || !log2_blo || !k_per_item || !wg_per_cu || !order || !source)
+                                int* wg_per_cu, int* order, int* radix, int* source) {
+  if (!batch || !log2_blo || !k_per_item || !wg_per_cu || !order || !radix || !source)
     return invalid("cmm_batch_get_config: null pointer");
+  *radix = batch->cfg.radix;
   *log2_blo = batch->cfg.lb;
   *k_per_item = batch->cfg.kgrain;
   *wg_per_cu = batch->cfg.wg_per_cu;
@@ -511,15 +521,21 @@ cmm_status cmm_batch_autotune(cmm_batch* batch, void* workspace, size_t workspac
     else if ((r = prepare(*batch, layout_of(*batch, cur), cur.lb, ws, s, false)) != CMM_OK) return r;
     return CMM_OK;
   };
-  // coordinate descent: k-range, LDS share, tile, order
+  // coordinate descent: k-range, LDS share, tile and radix, order
+  auto with = [&](int lb, int kg, int wg, int ord, int radix) { return BatchConfig{lb, kg, wg, ord, radix}; };
   for (int kg : kKGrains)
-    if (kg != cur.kgrain && (st = try_cfg(BatchConfig{cur.lb, kg, cur.wg_per_cu, cur.order})) != CMM_OK) return st;
+    if (kg != cur.kgrain &&
+        (st = try_cfg(with(cur.lb, kg, cur.wg_per_cu, cur.order, cur.radix))) != CMM_OK) return st;
   for (int wg = 1; wg <= 2; ++wg)
-    if (wg != cur.wg_per_cu && (st = try_cfg(BatchConfig{cur.lb, cur.kgrain, wg, cur.order})) != CMM_OK) return st;
+    if (wg != cur.wg_per_cu &&
+        (st = try_cfg(with(cur.lb, cur.kgrain, wg, cur.order, cur.radix))) != CMM_OK) return st;
   for (int lb : batch->lbs)
-    if (lb != cur.lb && (st = try_cfg(BatchConfig{lb, cur.kgrain, cur.wg_per_cu, cur.order})) != CMM_OK) return st;
+    for (int radix : {16, 32})
+      if ((lb != cur.lb || radix != cur.radix) && (radix == 32 || lb == 13) &&
+          (st = try_cfg(with(lb, cur.kgrain, cur.wg_per_cu, cur.order, radix))) != CMM_OK) return st;
   for (int ord = 0; ord <= 1; ++ord)
-    if (ord != cur.order && (st = try_cfg(BatchConfig{cur.lb, cur.kgrain, cur.wg_per_cu, ord})) != CMM_OK) return st;
+    if (ord != cur.order &&
+        (st = try_cfg(with(cur.lb, cur.kgrain, cur.wg_per_cu, ord, cur.radix))) != CMM_OK) return st;
   void* h = nullptr;
   if ((st = staging_of(*batch, cur, &h)) != CMM_OK) return st;
   batch->cfg = cur;

@@ -128,6 +128,8 @@ cmm_status launch_compress(const CompressArgs& a, cmm_dtype dt, int lb, hipStrea
 // LDS bytes of the fused kernel (b_lo = 2^lb, 32 elements per thread)
 // before the collision lists.
 size_t compress_lds_base(cmm_dtype dt, int lb, int64_t n_rows, int64_t n_cols);
+// The same for the 16-element layout (b_lo = 2^13, 512 threads).
+size_t compress16_lds_base(cmm_dtype dt, int64_t n_rows, int64_t n_cols);
 
 // ------------------------------------------------------------ batched form
 // One problem of a batch as the persistent kernel reads it: workspace
@@ -150,9 +152,11 @@ struct BatchItem {
 };
 // Persistent Compress over all items: `wgs` work-groups take items from
 // the queue counter (zeroed before the launch) until none are left.
+// radix: elements per thread of the transform layout (32: b_lo from 2^11
+// to 2^13; 16: b_lo = 2^13).
 cmm_status launch_compress_batched(char* ws, const BatchPair* pairs, const BatchItem* items,
-                                   int n_items, int* queue, cmm_dtype dt, int lb, int wgs,
-                                   size_t lds, hipStream_t s);
+                                   int n_items, int* queue, cmm_dtype dt, int lb, int radix,
+                                   int wgs, size_t lds, hipStream_t s);
 
 // Precision form: MFMA compress (b_lo = 2^14) on bf16 / fp16 rows.
 cmm_status launch_compress_mfma(const CompressArgs& a, cmm_dtype lp, hipStream_t s);

@@ -434,13 +434,13 @@ __device__ __forceinline__ void pass2_16(T (&v)[16], T sgn8) {
 // SINGLE: one row buffer shared by the two operands (A staged, fixed up and
 // gathered before B), for rows too long to stage both at once.
 template <typename T, bool SINGLE>
-__global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
+__device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, int t, uint32_t uhi,
+                                                int64_t k0, int64_t k1, unsigned char* smem) {
   constexpr int LB = 13;
   constexpr int E = 16;
   constexpr int NT = 512;
   constexpr int BLO = 1 << LB;
   constexpr int XLEN = BLO + BLO / 64 + 16;   // padded transpose buffer
-  extern __shared__ __align__(16) unsigned char smem[];
   T* xbuf = reinterpret_cast<T*>(smem);
   T* rowA = xbuf + XLEN;
   const int64_t pitch1 = SINGLE ? (row_pitch<T>(a.n_rows) > row_pitch<T>(a.n_cols)
@@ -450,20 +450,6 @@ __global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
   uint2* exl = reinterpret_cast<uint2*>(rowB + (SINGLE ? 0 : row_pitch<T>(a.n_cols)) +
                                         (SINGLE ? pitch1 : 0));
   if (!SINGLE && threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
-
-  const int b_hi_bits = a.log2b - LB;
-  const int64_t nunits = (int64_t)a.d << b_hi_bits;
-  const int64_t wg = blockIdx.x;
-  const int64_t total = nunits * a.groups;
-  int64_t lin = wg;
-  if ((total & 7) == 0) lin = (wg & 7) * (total >> 3) + (wg >> 3);
-  const int g = (int)(lin / nunits);
-  const int64_t unit = lin - (int64_t)g * nunits;
-  const int t = (int)(unit >> b_hi_bits);
-  const uint32_t uhi = (uint32_t)(unit & (((int64_t)1 << b_hi_bits) - 1));
-  const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
-  const int64_t k0 = (int64_t)g * k_per;
-  const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
 
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t l4 = (lane >> 4) & 1, l5 = (lane >> 5) & 1, l3 = (lane >> 3) & 1;
@@ -594,13 +580,14 @@ __global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) xbuf[wr_t + wr_e(e)] = Y[e];
+    // pass 2 of X overlaps the LDS writes of Y and the row copies of k + 1
+    pass2_16(X, sgn8);
     if (more && dma) wait_dma();
     __syncthreads();   // Y transposed and the rows of k + 1 have landed
 #pragma unroll
     for (int e = 0; e < E; ++e) Y[e] = xbuf[rd_t + rd_e(e)];
     // the collision fix-ups of k + 1 run while other waves do pass 2 of k
     if (more) fixups();
-    pass2_16(X, sgn8);
     pass2_16(Y, sgn8);
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = fma(X[e], Y[e], acc[e]);
@@ -620,6 +607,75 @@ __global__ __launch_bounds__(512) void compress16_kernel(CompressArgs a) {
     const uint32_t fe = ((uint32_t)(e & 1) << 10) | ((uint32_t)((e >> 1) & 1) << 11) |
                         ((uint32_t)((e >> 2) & 3) << 8);
     dst[fin_t | fe] = (double)acc[e];
+  }
+}
+
+// Two waves per SIMD for both types: at four (128 registers) the float32
+// variant spills, which costs more than the extra occupancy gains.
+template <typename T>
+constexpr int waves16() { return 2; }
+
+template <typename T, bool SINGLE>
+__global__ __launch_bounds__(512, waves16<T>()) void compress16_kernel(CompressArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int LB = 13;
+  const int b_hi_bits = a.log2b - LB;
+  const int64_t nunits = (int64_t)a.d << b_hi_bits;
+  const int64_t wg = blockIdx.x;
+  const int64_t total = nunits * a.groups;
+  int64_t lin = wg;
+  if ((total & 7) == 0) lin = (wg & 7) * (total >> 3) + (wg >> 3);
+  const int g = (int)(lin / nunits);
+  const int64_t unit = lin - (int64_t)g * nunits;
+  const int t = (int)(unit >> b_hi_bits);
+  const uint32_t uhi = (uint32_t)(unit & (((int64_t)1 << b_hi_bits) - 1));
+  const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
+  const int64_t k0 = (int64_t)g * k_per;
+  const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
+  compress16_unit<T, SINGLE>(a, g, t, uhi, k0, k1, smem);
+}
+
+// The persistent batched form with the 16-element layout (b_lo = 2^13).
+template <typename T>
+__global__ __launch_bounds__(512, waves16<T>()) void compress16_batched_kernel(
+    char* __restrict__ ws, const BatchPair* __restrict__ pairs,
+    const BatchItem* __restrict__ items, int n_items, int* __restrict__ queue) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_item;
+  constexpr int LB = 13;
+  for (;;) {
+    __syncthreads();   // the previous unit is done with LDS and s_item
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= n_items) break;   // uniform: every wave leaves
+    const BatchItem bi = items[it];
+    const BatchPair bp = pairs[bi.pair];
+    CompressArgs a;
+    a.At = ws + bp.at;
+    a.B = bp.bc >= 0 ? static_cast<const void*>(ws + bp.bc) : bp.B;
+    a.ldb = bp.ldb;
+    a.n_rows = bp.n_rows;
+    a.n_cols = bp.n_cols;
+    a.n_inner = bp.n_inner;
+    a.tab1 = bp.tab1;
+    a.tab2 = bp.tab2;
+    a.planA = carve_plan(ws + bp.planA, bp.d, bp.n_rows, LB);
+    a.planB = carve_plan(ws + bp.planB, bp.d, bp.n_cols, LB);
+    a.d = bp.d;
+    a.log2b = bp.log2b;
+    a.groups = bp.groups;
+    a.partial = reinterpret_cast<double*>(ws + bp.partial);
+    a.ex_cap = bp.ex_cap;
+    a.dma = bp.dma;
+    a.variant = 0;
+    const int b_hi_bits = a.log2b - LB;
+    const int t = (int)(bi.unit >> b_hi_bits);
+    const uint32_t uhi = bi.unit & ((1u << b_hi_bits) - 1u);
+    const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
+    const int64_t k0 = (int64_t)bi.group * k_per;
+    const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
+    compress16_unit<T, false>(a, (int)bi.group, t, uhi, k0, k1, smem);
   }
 }
 
@@ -701,8 +757,7 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   }
   if (base > kMax) { set_error("compress: rows do not fit in LDS"); return CMM_EUNSUPPORTED; }
   int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
-  const int64_t want = a.n_rows + a.n_cols;
-  if (cap > want) cap = want;
+  if (cap > a.n_rows + a.n_cols) cap = a.n_rows + a.n_cols;
   a.ex_cap = cap;
   const size_t lds = base + sizeof(uint2) * (size_t)cap;
   constexpr int V = 16 / sizeof(T);
@@ -714,6 +769,13 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   if (e != hipSuccess) return hip_check(e, "compress: set LDS size");
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(512), lds, s, a);
   return hip_check(hipGetLastError(), "compress kernel launch");
+}
+
+size_t compress16_lds_base(cmm_dtype dt, int64_t n_rows, int64_t n_cols) {
+  const size_t xlen = ((size_t)1 << 13) + ((size_t)1 << 7) + 16;
+  if (dt == CMM_F64)
+    return sizeof(double) * (xlen + (size_t)row_pitch<double>(n_rows) + (size_t)row_pitch<double>(n_cols));
+  return sizeof(float) * (xlen + (size_t)row_pitch<float>(n_rows) + (size_t)row_pitch<float>(n_cols));
 }
 
 size_t compress_lds_base(cmm_dtype dt, int lb, int64_t n_rows, int64_t n_cols) {
@@ -737,9 +799,29 @@ static cmm_status launch_batched_t(char* ws, const BatchPair* pairs, const Batch
   return hip_check(hipGetLastError(), "compress (batched) launch");
 }
 
+template <typename T>
+static cmm_status launch_batched16_t(char* ws, const BatchPair* pairs, const BatchItem* items,
+                                     int n_items, int* queue, int wgs, size_t lds, hipStream_t s) {
+  ProfScope prof_("compress", s);
+  auto kern = compress16_batched_kernel<T>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return hip_check(e, "compress (batched): set LDS size");
+  hipLaunchKernelGGL(kern, dim3((unsigned)wgs), dim3(512), lds, s, ws, pairs, items, n_items, queue);
+  return hip_check(hipGetLastError(), "compress (batched) launch");
+}
+
 cmm_status launch_compress_batched(char* ws, const BatchPair* pairs, const BatchItem* items,
-                                   int n_items, int* queue, cmm_dtype dt, int lb, int wgs,
-                                   size_t lds, hipStream_t s) {
+                                   int n_items, int* queue, cmm_dtype dt, int lb, int radix,
+                                   int wgs, size_t lds, hipStream_t s) {
+  if (radix == 16) {
+    if (lb != 13) {
+      set_error("compress (batched): the 16-element layout needs b_lo = 2^13");
+      return CMM_EUNSUPPORTED;
+    }
+    if (dt == CMM_F64) return launch_batched16_t<double>(ws, pairs, items, n_items, queue, wgs, lds, s);
+    return launch_batched16_t<float>(ws, pairs, items, n_items, queue, wgs, lds, s);
+  }
   if (dt == CMM_F64) {
     switch (lb) {
       case 11: return launch_batched_t<double, 11>(ws, pairs, items, n_items, queue, wgs, lds, s);
@@ -770,7 +852,9 @@ cmm_status launch_compress(const CompressArgs& a, cmm_dtype dt, int lb, hipStrea
     switch (lb) {
       case 11: return launch_compress_t<float, 11>(a, s);
       case 12: return launch_compress_t<float, 12>(a, s);
-      case 13: return launch_compress_t<float, 13>(a, s);
+      case 13:
+        if (a.variant == 1) return launch_compress_t<float, 13>(a, s);
+        return launch_compress16<float>(a, s);
       case 14: return launch_compress_t<float, 14>(a, s);
     }
   }

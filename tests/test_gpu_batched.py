@@ -61,8 +61,8 @@ def test_batched_f64_integer_bit_exact_every_config():
     refs = [_oracle(*p) for p in probs]
     batch, res, _ = _device_batch(probs, "f64", torch().float64)
     ws = batch.workspace()
-    configs = [(lb, kg, wg, o) for lb in (11, 12, 13) for kg in (32, 64, 128, 256)
-               for wg in (1, 2) for o in (0, 1)]
+    configs = [(lb, kg, wg, o, r) for lb in (11, 12, 13) for kg in (32, 64, 128, 256)
+               for wg in (1, 2) for o in (0, 1) for r in (16, 32) if r == 32 or lb == 13]
     for cfg in configs:
         announce(f"batched f64 config {cfg}")
         batch.set_config(*cfg)
@@ -158,8 +158,8 @@ def test_batched_autotune_and_cache():
     batch2, res2, _ = _device_batch(probs, "f64", torch().float64)
     cfg2 = batch2.autotune(batch2.workspace())
     assert cfg2["source"] == "cache"
-    assert {k: cfg2[k] for k in ("log2_blo", "k_per_item", "wg_per_cu", "order")} == \
-        {k: cfg[k] for k in ("log2_blo", "k_per_item", "wg_per_cu", "order")}
+    keys = ("log2_blo", "k_per_item", "wg_per_cu", "order", "radix")
+    assert {k: cfg2[k] for k in keys} == {k: cfg[k] for k in keys}
 
 
 def test_batched_mix_64_pairs_full_size():
