@@ -151,26 +151,21 @@ __global__ __launch_bounds__((1 << LB) / 32) void adjoint_kernel(AdjointArgs aa)
   const int nchA = a.planA.nchains[t], nchB = a.planB.nchains[t];
   const int cntA = gcA[nchA], cntB = gcB[nchB];
   const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
-  const uint2* exA;
-  const uint2* exB;
   const uint2* gpA = a.planA.pairs + (size_t)t * a.n_rows;
   const uint2* gpB = a.planB.pairs + (size_t)t * a.n_cols;
-  const int32_t* csA = gcA;
-  const int32_t* csB = gcB;
   if (ex_lds) {
     for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gpA[q];
     for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gpB[q];
     int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
     for (int q = threadIdx.x; q <= nchA; q += NT) csl[q] = gcA[q];
     for (int q = threadIdx.x; q <= nchB; q += NT) csl[nchA + 1 + q] = gcB[q];
-    exA = exl;
-    exB = exl + cntA;
-    csA = csl;
-    csB = csl + nchA + 1;
-  } else {
-    exA = gpA;
-    exB = gpB;
   }
+  // LDS views of the lists; each fix-up call below takes either these or the
+  // global lists, so the compiler knows every pointer's memory space
+  const uint2* lexA = exl;
+  const uint2* lexB = exl + cntA;
+  const int32_t* lcsA = reinterpret_cast<const int32_t*>(exl + cntA + cntB);
+  const int32_t* lcsB = lcsA + nchA + 1;
 
   const uint32_t w1 = swz(l1p_lane(lane, w));
   const uint32_t r2lane = swz(l2_lane<LB>(lane, w, false));
@@ -198,8 +193,8 @@ __global__ __launch_bounds__((1 << LB) / 32) void adjoint_kernel(AdjointArgs aa)
     if (dma) wait_dma();
     __syncthreads();
     if (nchA + nchB > 0) {
-      fix_chains<T, NT>(rowA, exA, csA, nchA, uhi);
-      fix_chains<T, NT>(rowB, exB, csB, nchB, uhi);
+      { if (ex_lds) fix_chains<T, NT>(rowA, lexA, lcsA, nchA, uhi); else fix_chains<T, NT>(rowA, gpA, gcA, nchA, uhi); }
+      { if (ex_lds) fix_chains<T, NT>(rowB, lexB, lcsB, nchB, uhi); else fix_chains<T, NT>(rowB, gpB, gcB, nchB, uhi); }
       __syncthreads();
     }
     T X[E], Y[E];

@@ -221,26 +221,21 @@ __device__ __forceinline__ void compress_unit(const CompressArgs& a, int g, int 
   const int cntA = gcA[nchA], cntB = gcB[nchB];
   // entries (8 bytes) plus chain starts (4 bytes each, two per 8-byte slot)
   const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
-  const uint2* exA;
-  const uint2* exB;
   const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
   const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
-  const int32_t* csA = gcA;
-  const int32_t* csB = gcB;
   if (ex_lds) {
     for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gA[q];
     for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gB[q];
     int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
     for (int q = threadIdx.x; q <= nchA; q += NT) csl[q] = gcA[q];
     for (int q = threadIdx.x; q <= nchB; q += NT) csl[nchA + 1 + q] = gcB[q];
-    exA = exl;
-    exB = exl + cntA;
-    csA = csl;
-    csB = csl + nchA + 1;
-  } else {
-    exA = gA;
-    exB = gB;
   }
+  // LDS views of the lists; each fix-up call below takes either these or the
+  // global lists, so the compiler knows every pointer's memory space
+  const uint2* lexA = exl;
+  const uint2* lexB = exl + cntA;
+  const int32_t* lcsA = reinterpret_cast<const int32_t*>(exl + cntA + cntB);
+  const int32_t* lcsB = lcsA + nchA + 1;
 
   const uint32_t w1 = swz(l1p_lane(lane, w));          // + l1p_reg(e) (additive)
   const uint32_t r2lane = swz(l2_lane<LB>(lane, w, false));   // + swz(l2_reg(e))
@@ -263,8 +258,8 @@ __device__ __forceinline__ void compress_unit(const CompressArgs& a, int g, int 
     __syncthreads();
     // rank rounds of both operands share the barriers
     if (nchA + nchB > 0) {
-      fix_chains<T, NT>(rowA, exA, csA, nchA, uhi);
-      fix_chains<T, NT>(rowB, exB, csB, nchB, uhi);
+      { if (ex_lds) fix_chains<T, NT>(rowA, lexA, lcsA, nchA, uhi); else fix_chains<T, NT>(rowA, gA, gcA, nchA, uhi); }
+      { if (ex_lds) fix_chains<T, NT>(rowB, lexB, lcsB, nchB, uhi); else fix_chains<T, NT>(rowB, gB, gcB, nchB, uhi); }
       __syncthreads();
     }
     T X[E], Y[E];
@@ -483,26 +478,21 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   const int cntA = gcA[nchA], cntB = gcB[nchB];
   // entries (8 bytes) plus chain starts (4 bytes each, two per 8-byte slot)
   const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
-  const uint2* exA;
-  const uint2* exB;
   const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
   const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
-  const int32_t* csA = gcA;
-  const int32_t* csB = gcB;
   if (ex_lds) {
     for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gA[q];
     for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gB[q];
     int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
     for (int q = threadIdx.x; q <= nchA; q += NT) csl[q] = gcA[q];
     for (int q = threadIdx.x; q <= nchB; q += NT) csl[nchA + 1 + q] = gcB[q];
-    exA = exl;
-    exB = exl + cntA;
-    csA = csl;
-    csB = csl + nchA + 1;
-  } else {
-    exA = gA;
-    exB = gB;
   }
+  // LDS views of the lists; each fix-up call below takes either these or the
+  // global lists, so the compiler knows every pointer's memory space
+  const uint2* lexA = exl;
+  const uint2* lexB = exl + cntA;
+  const int32_t* lcsA = reinterpret_cast<const int32_t*>(exl + cntA + cntB);
+  const int32_t* lcsB = lcsA + nchA + 1;
   // transpose addresses: thread part (padded) + register part
   const uint32_t wr_t = pad16(l4 | (l5 << 1) | ((lane & 15) << 6) | (w << 10));
   const uint32_t rd_t = pad16((lane & 7) | (w << 3) | (l4 << 10) | (l5 << 11) | (l3 << 12));
@@ -528,8 +518,8 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
     if (!SINGLE) stage_row<T, NT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
   };
   auto fixups = [&]() {
-    fix_chains<T, NT>(rowA, exA, csA, nchA, uhi);
-    if (!SINGLE) fix_chains<T, NT>(rowB, exB, csB, nchB, uhi);
+    { if (ex_lds) fix_chains<T, NT>(rowA, lexA, lcsA, nchA, uhi); else fix_chains<T, NT>(rowA, gA, gcA, nchA, uhi); }
+    if (!SINGLE) { if (ex_lds) fix_chains<T, NT>(rowB, lexB, lcsB, nchB, uhi); else fix_chains<T, NT>(rowB, gB, gcB, nchB, uhi); }
   };
   auto gather = [&]() {
 #pragma unroll
@@ -546,7 +536,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
     stage_row<T, NT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
     if (dma) wait_dma();
     __syncthreads();
-    fix_chains<T, NT>(rowB, exB, csB, nchB, uhi);
+    { if (ex_lds) fix_chains<T, NT>(rowB, lexB, lcsB, nchB, uhi); else fix_chains<T, NT>(rowB, gB, gcB, nchB, uhi); }
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e)

@@ -200,21 +200,19 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
   const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
   const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
-  const uint2* exA = gA;
-  const uint2* exB = gB;
-  const int32_t* csA = gcA;
-  const int32_t* csB = gcB;
   if (ex_lds) {
     for (int q = threadIdx.x; q < cntA; q += kNT) exl[q] = gA[q];
     for (int q = threadIdx.x; q < cntB; q += kNT) exl[cntA + q] = gB[q];
     int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
     for (int q = threadIdx.x; q <= nchA; q += kNT) csl[q] = gcA[q];
     for (int q = threadIdx.x; q <= nchB; q += kNT) csl[nchA + 1 + q] = gcB[q];
-    exA = exl;
-    exB = exl + cntA;
-    csA = csl;
-    csB = csl + nchA + 1;
   }
+  // LDS views of the lists; each fix-up call below takes either these or the
+  // global lists, so the compiler knows every pointer's memory space
+  const uint2* lexA = exl;
+  const uint2* lexB = exl + cntA;
+  const int32_t* lcsA = reinterpret_cast<const int32_t*>(exl + cntA + cntB);
+  const int32_t* lcsB = lcsA + nchA + 1;
 
   // H16 as the B operand (passes 1, 3) and as the A operand (pass 2): lane
   // holds H[4 lg + v][lm] = H[lm][4 lg + v].  Pass 4: M4 = H4 x I4 on the
@@ -340,8 +338,8 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
     if (dma) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();   // rows of k staged; the transpose buffers are free
     if (nchA + nchB > 0) {
-      fix_chains_lp<IN, kNT>(rowA, exA, csA, nchA, uhi);
-      fix_chains_lp<IN, kNT>(rowB, exB, csB, nchB, uhi);
+      { if (ex_lds) fix_chains_lp<IN, kNT>(rowA, lexA, lcsA, nchA, uhi); else fix_chains_lp<IN, kNT>(rowA, gA, gcA, nchA, uhi); }
+      { if (ex_lds) fix_chains_lp<IN, kNT>(rowB, lexB, lcsB, nchB, uhi); else fix_chains_lp<IN, kNT>(rowB, gB, gcB, nchB, uhi); }
       __syncthreads();
     }
     front(rowA16, idxA, tbufX);
