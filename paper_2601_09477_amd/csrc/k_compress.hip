@@ -480,7 +480,10 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
   const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
   const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
-  if (ex_lds) {
+  // (float32 only: the float64 variant has no registers to spare for them)
+  const bool use_desc = sizeof(T) == 4 && !SINGLE && nchA <= 2 * NT && nchB <= 2 * NT &&
+                        4 * NT <= a.ex_cap;
+  if (ex_lds && !use_desc) {
     for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gA[q];
     for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gB[q];
     int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
@@ -493,6 +496,69 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   const uint2* lexB = exl + cntA;
   const int32_t* lcsA = reinterpret_cast<const int32_t*>(exl + cntA + cntB);
   const int32_t* lcsB = lcsA + nchA + 1;
+  // Collision descriptors (the usual case: at most 2 NT chains per operand).
+  // Thread tid owns chains tid and tid + NT of each operand; its descriptor
+  // (8 bytes, in LDS, built once per work unit) holds the chain's target
+  // (the bucket's first row), its next two rows and their signs relative to
+  // the target, as row indices, with the zero pad index n for absent rows
+  // and the target of an absent chain.  Longer chains keep their remaining
+  // rows in the plan's list.  A fix-up per k is then one descriptor load,
+  // three independent row loads and a store, with no branches.
+  uint2* dsc = exl;   // [operand][slot][NT]; replaces the LDS lists
+  auto build_desc = [&](int op, const int32_t* gc, const uint2* gp, int nch, uint32_t pad) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = (int)threadIdx.x + j * NT;
+      uint32_t tgt = pad, m1 = pad, m2 = pad, flags = 0;
+      if (c < nch) {
+        const int beg = gc[c], end = gc[c + 1];
+        const uint2 x0 = gp[beg];
+        tgt = x0.x >> 16;
+        m1 = x0.x & 0xFFFFu;
+        flags = (x0.y >> 31) ^ (__popc(uhi & (x0.y & kBucketMask)) & 1u);
+        if (end - beg >= 2) {
+          const uint2 x1 = gp[beg + 1];
+          m2 = x1.x & 0xFFFFu;
+          flags |= ((x1.y >> 31) ^ (__popc(uhi & (x1.y & kBucketMask)) & 1u)) << 1;
+        }
+        if (end - beg > 2) flags |= 4u;
+      }
+      dsc[(op * 2 + j) * NT + threadIdx.x] = make_uint2(tgt | (m1 << 16), m2 | (flags << 16));
+    }
+  };
+  if (use_desc) {
+    build_desc(0, gcA, gA, nchA, (uint32_t)a.n_rows);
+    build_desc(1, gcB, gB, nchB, (uint32_t)a.n_cols);
+  }
+  // one operand's fix-ups from its descriptors (rows of k staged)
+  auto fix_desc = [&](T* row, int op, const int32_t* gc, const uint2* gp) {
+    uint2 q[2];
+    T v[2][3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) q[j] = dsc[(op * 2 + j) * NT + threadIdx.x];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      v[j][0] = row[q[j].x & 0xFFFFu];
+      v[j][1] = row[q[j].x >> 16];
+      v[j][2] = row[q[j].y & 0xFFFFu];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const uint32_t f = q[j].y >> 16;
+      T acc_ = v[j][0] + flip_sign(v[j][1], f << 31);
+      acc_ = acc_ + flip_sign(v[j][2], (f >> 1) << 31);
+      if (f & 4u) {   // rows beyond the third (rare)
+        const int c = (int)threadIdx.x + j * NT;
+        const int beg = gc[c], end = gc[c + 1];
+        for (int r = beg + 2; r < end; ++r) {
+          const uint2 y = gp[r];
+          const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+          acc_ = acc_ + flip_sign(row[y.x & 0xFFFFu], neg << 31);
+        }
+      }
+      row[q[j].x & 0xFFFFu] = acc_;
+    }
+  };
   // transpose addresses: thread part (padded) + register part
   const uint32_t wr_t = pad16(l4 | (l5 << 1) | ((lane & 15) << 6) | (w << 10));
   const uint32_t rd_t = pad16((lane & 7) | (w << 3) | (l4 << 10) | (l5 << 11) | (l3 << 12));
@@ -518,6 +584,11 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
     if (!SINGLE) stage_row<T, NT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
   };
   auto fixups = [&]() {
+    if (use_desc) {
+      fix_desc(rowA, 0, gcA, gA);
+      fix_desc(rowB, 1, gcB, gB);
+      return;
+    }
     { if (ex_lds) fix_chains<T, NT>(rowA, lexA, lcsA, nchA, uhi); else fix_chains<T, NT>(rowA, gA, gcA, nchA, uhi); }
     if (!SINGLE) { if (ex_lds) fix_chains<T, NT>(rowB, lexB, lcsB, nchB, uhi); else fix_chains<T, NT>(rowB, gB, gcB, nchB, uhi); }
   };
