@@ -279,6 +279,201 @@ __global__ __launch_bounds__((1 << LB) / 32) void adjoint_kernel(AdjointArgs aa)
   }
 }
 
+// ---------------------------------------------- fused adjoint, 16 elements
+// The same steps on the 16-element layout (b_lo = 2^13, 512 threads, two
+// waves per SIMD): forward passes 1 and 2 leave layout L2'; pass 2 applied
+// again runs the same stages (ending in layout L2), the transpose back
+// gives L1', and pass 1 ends in the gather layout, bucket base1 + e in
+// register e.
+template <typename T>
+__global__ __launch_bounds__(512, 2) void adjoint16_kernel(AdjointArgs aa) {
+  const CompressArgs& a = aa.c;
+  constexpr int LB = 13;
+  constexpr int E = 16;
+  constexpr int NT = 512;
+  constexpr int BLO = 1 << LB;
+  constexpr int XLEN = BLO + BLO / 64 + 16;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* xbuf = reinterpret_cast<T*>(smem);
+  T* rowA = xbuf + XLEN;
+  T* rowB = rowA + row_pitch<T>(a.n_rows);
+  uint32_t* gA = reinterpret_cast<uint32_t*>(rowB + row_pitch<T>(a.n_cols));   // [n_rows]
+  uint32_t* gB = gA + a.n_rows;                                                 // [n_cols]
+  uint2* exl = reinterpret_cast<uint2*>(gA + (a.n_rows + a.n_cols + 1) / 2 * 2);
+  if (threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
+
+  const int b_hi_bits = a.log2b - LB;
+  const int64_t nunits = (int64_t)a.d << b_hi_bits;
+  const int64_t wg = blockIdx.x;
+  const int64_t total = nunits * a.groups;
+  int64_t lin = wg;
+  if ((total & 7) == 0) lin = (wg & 7) * (total >> 3) + (wg >> 3);
+  const int g = (int)(lin / nunits);
+  const int64_t unit = lin - (int64_t)g * nunits;
+  const int t = (int)(unit >> b_hi_bits);
+  const uint32_t uhi = (uint32_t)(unit & (((int64_t)1 << b_hi_bits) - 1));
+  const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
+  const int64_t k0 = (int64_t)g * k_per;
+  const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
+  if (k0 >= k1) return;   // uniform over the work-group
+
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t l4 = (lane >> 4) & 1, l5 = (lane >> 5) & 1, l3 = (lane >> 3) & 1;
+  const uint32_t base1 = (l4 << 4) | (l5 << 5) | ((lane & 15) << 6) | (w << 10);
+  const uint32_t* t1 = a.tab1 + (size_t)t * a.n_rows;
+  const uint32_t* t2 = a.tab2 + (size_t)t * a.n_cols;
+  // forward gather: byte offsets of the first rows of the thread's buckets
+  // (the zero pad when empty) and their folded signs
+  uint32_t offA[E], offB[E];
+  uint32_t nega = 0, negb = 0;
+  {
+    const int32_t* f1 = a.planA.first + (size_t)t * BLO + base1;
+    const int32_t* f2 = a.planB.first + (size_t)t * BLO + base1;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int32_t r1 = f1[e], r2 = f2[e];
+      const uint32_t en1 = t1[r1 >= 0 ? r1 : 0], en2 = t2[r2 >= 0 ? r2 : 0];
+      const uint32_t s1 = r1 >= 0 ? (en1 >> 31) ^ (__popc(uhi & ((en1 & kBucketMask) >> LB)) & 1u) : 0u;
+      const uint32_t s2 = r2 >= 0 ? (en2 >> 31) ^ (__popc(uhi & ((en2 & kBucketMask) >> LB)) & 1u) : 0u;
+      nega |= s1 << e;
+      negb |= s2 << e;
+      const uint32_t ra = r1 >= 0 ? (uint32_t)r1 : (uint32_t)a.n_rows;
+      const uint32_t rb = r2 >= 0 ? (uint32_t)r2 : (uint32_t)a.n_cols;
+      offA[e] = (uint32_t)((const unsigned char*)(rowA + ra) - smem);
+      offB[e] = (uint32_t)((const unsigned char*)(rowB + rb) - smem);
+    }
+  }
+  // transposed sketch: padded address of lo(h(i)) and the folded sign
+  for (int64_t i = threadIdx.x; i < a.n_rows; i += NT) {
+    const uint32_t e = t1[i];
+    const uint32_t neg = (e >> 31) ^ (__popc(uhi & ((e & kBucketMask) >> LB)) & 1u);
+    gA[i] = pad16(e & (uint32_t)(BLO - 1)) | (neg << 31);
+  }
+  for (int64_t j = threadIdx.x; j < a.n_cols; j += NT) {
+    const uint32_t e = t2[j];
+    const uint32_t neg = (e >> 31) ^ (__popc(uhi & ((e & kBucketMask) >> LB)) & 1u);
+    gB[j] = pad16(e & (uint32_t)(BLO - 1)) | (neg << 31);
+  }
+  // collision chains, in LDS when they fit
+  const int32_t* gcA = a.planA.cstart + (size_t)t * (a.n_rows + 2);
+  const int32_t* gcB = a.planB.cstart + (size_t)t * (a.n_cols + 2);
+  const int nchA = a.planA.nchains[t], nchB = a.planB.nchains[t];
+  const int cntA = gcA[nchA], cntB = gcB[nchB];
+  const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
+  const uint2* gpA = a.planA.pairs + (size_t)t * a.n_rows;
+  const uint2* gpB = a.planB.pairs + (size_t)t * a.n_cols;
+  if (ex_lds) {
+    for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gpA[q];
+    for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gpB[q];
+    int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
+    for (int q = threadIdx.x; q <= nchA; q += NT) csl[q] = gcA[q];
+    for (int q = threadIdx.x; q <= nchB; q += NT) csl[nchA + 1 + q] = gcB[q];
+  }
+  const uint2* lexA = exl;
+  const uint2* lexB = exl + cntA;
+  const int32_t* lcsA = reinterpret_cast<const int32_t*>(exl + cntA + cntB);
+  const int32_t* lcsB = lcsA + nchA + 1;
+
+  // transpose addresses (as in Compress): L1' <-> L2
+  const uint32_t wr_t = pad16(l4 | (l5 << 1) | ((lane & 15) << 6) | (w << 10));
+  const uint32_t rd_t = pad16((lane & 7) | (w << 3) | (l4 << 10) | (l5 << 11) | (l3 << 12));
+  auto wr_e = [](int e) -> uint32_t {
+    return ((uint32_t)(e & 1) << 4) | ((uint32_t)((e >> 1) & 1) << 5) | (uint32_t)(e & 12);
+  };
+  auto rd_e = [](int e) -> uint32_t { return pad16((uint32_t)e << 6); };
+  const T sgn8 = l3 ? T(-1) : T(1);
+  const uint32_t nat = pad16(base1);   // + e: the thread's 16 consecutive buckets
+
+  // (r_t / d) on this slice in layout L2' (where the forward passes end)
+  T R[E];
+  {
+    const int64_t b = (int64_t)1 << a.log2b;
+    const double* rs = aa.r + (size_t)t * b + ((int64_t)uhi << LB);
+    const uint32_t fin_t = (lane & 7) | (w << 3) | (l4 << 6) | (l5 << 7) | (l3 << 12);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t fe = ((uint32_t)(e & 1) << 10) | ((uint32_t)((e >> 1) & 1) << 11) |
+                          ((uint32_t)((e >> 2) & 3) << 8);
+      R[e] = (T)(rs[fin_t | fe] * aa.scale);
+    }
+  }
+
+  const T* At = reinterpret_cast<const T*>(a.At);
+  const T* Bm = reinterpret_cast<const T*>(a.B);
+  T* oA = reinterpret_cast<T*>(aa.partA) + (size_t)unit * a.n_inner * a.n_rows;
+  T* oB = reinterpret_cast<T*>(aa.partB) + (size_t)unit * a.n_inner * a.n_cols;
+  const bool dma = a.dma != 0;
+  stage_row<T, NT>(rowA, At + k0 * a.n_rows, a.n_rows, dma);
+  stage_row<T, NT>(rowB, Bm + k0 * a.ldb, a.n_cols, dma);
+
+  // one operand through the transpose buffer: write in one layout, read in
+  // the other (barriers around the buffer's reuse)
+  auto through = [&](T (&v)[E], bool forward) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xbuf[forward ? wr_t + wr_e(e) : rd_t + rd_e(e)] = v[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = xbuf[forward ? rd_t + rd_e(e) : wr_t + wr_e(e)];
+  };
+  // one operand's transposed sketch from the natural-order buffer
+  auto scatter_out = [&](const T (&v)[E], const uint32_t* gt, int64_t n, T* o) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xbuf[nat + e] = v[e];
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += NT) {
+      const uint32_t gi = gt[i];
+      o[i] = flip_sign(xbuf[gi & kBucketMask], gi & kSignBit);
+    }
+  };
+
+  for (int64_t k = k0; k < k1; ++k) {
+    if (dma) wait_dma();
+    __syncthreads();
+    if (nchA + nchB > 0) {
+      { if (ex_lds) fix_chains<T, NT>(rowA, lexA, lcsA, nchA, uhi); else fix_chains<T, NT>(rowA, gpA, gcA, nchA, uhi); }
+      { if (ex_lds) fix_chains<T, NT>(rowB, lexB, lcsB, nchB, uhi); else fix_chains<T, NT>(rowB, gpB, gcB, nchB, uhi); }
+      __syncthreads();
+    }
+    T X[E], Y[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      X[e] = flip_sign(*reinterpret_cast<const T*>(smem + offA[e]), (nega << (31 - e)) & 0x80000000u);
+      Y[e] = flip_sign(*reinterpret_cast<const T*>(smem + offB[e]), (negb << (31 - e)) & 0x80000000u);
+    }
+    __syncthreads();   // the row buffers can be refilled
+    if (k + 1 < k1) {
+      stage_row<T, NT>(rowA, At + (k + 1) * a.n_rows, a.n_rows, dma);
+      stage_row<T, NT>(rowB, Bm + (k + 1) * a.ldb, a.n_cols, dma);
+    }
+    // forward transforms (as in Compress)
+    pass1_16(X);
+    pass1_16(Y);
+    through(X, true);
+    through(Y, true);
+    pass2_16(X, sgn8);
+    pass2_16(Y, sgn8);
+    // dX = (r / d) o Y, dY = (r / d) o X
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const T x = X[e];
+      X[e] = R[e] * Y[e];
+      Y[e] = R[e] * x;
+    }
+    // H_lo again, ending in the gather layout
+    pass2_16(X, sgn8);
+    pass2_16(Y, sgn8);
+    through(X, false);
+    through(Y, false);
+    pass1_16(X);
+    pass1_16(Y);
+    scatter_out(X, gA, a.n_rows, oA + (size_t)(k - 0) * a.n_rows);
+    scatter_out(Y, gB, a.n_cols, oB + (size_t)(k - 0) * a.n_cols);
+    // the next iteration's first barrier ends the reads of the buffer
+  }
+}
+
 // ------------------------------------------------------ partial reduction
 // out = sum over p (ascending) of part[p][kk][i], summed in float64:
 //   transpose = 0:  out[(kb + kk) * ld + i]     (dB rows)
@@ -376,6 +571,39 @@ size_t adjoint_lds_bytes(cmm_dtype dt, int lb, int64_t n_rows, int64_t n_cols) {
   return s;
 }
 
+size_t adjoint16_lds_bytes(cmm_dtype dt, int64_t n_rows, int64_t n_cols) {
+  const size_t es = dtype_size(dt);
+  const int64_t pa = (dt == CMM_F64) ? row_pitch<double>(n_rows) : row_pitch<float>(n_rows);
+  const int64_t pb = (dt == CMM_F64) ? row_pitch<double>(n_cols) : row_pitch<float>(n_cols);
+  const size_t xlen = ((size_t)1 << 13) + ((size_t)1 << 7) + 16;
+  return es * (xlen + (size_t)pa + (size_t)pb) +
+         sizeof(uint32_t) * (size_t)((n_rows + n_cols + 1) / 2 * 2);
+}
+
+template <typename T>
+static cmm_status launch_adjoint16_t(const AdjointArgs& a0, hipStream_t s) {
+  ProfScope prof_("adjoint", s);
+  AdjointArgs aa = a0;
+  CompressArgs& a = aa.c;
+  const int64_t blocks = ((int64_t)a.d << (a.log2b - 13)) * a.groups;
+  const size_t kMax = 160 * 1024;
+  const size_t base = adjoint16_lds_bytes(sizeof(T) == 8 ? CMM_F64 : CMM_F32, a.n_rows, a.n_cols);
+  if (base > kMax) { set_error("adjoint: rows do not fit in LDS"); return CMM_EUNSUPPORTED; }
+  int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
+  if (cap > a.n_rows + a.n_cols) cap = a.n_rows + a.n_cols;
+  a.ex_cap = cap;
+  const size_t lds = base + sizeof(uint2) * (size_t)cap;
+  constexpr int V = 16 / sizeof(T);
+  a.dma = (a.n_rows % V == 0) && (a.n_cols % V == 0) && (a.ldb % V == 0) &&
+          ((uintptr_t)a.At % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
+  auto kern = adjoint16_kernel<T>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return hip_check(e, "adjoint: set LDS size");
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(512), lds, s, aa);
+  return hip_check(hipGetLastError(), "adjoint kernel launch");
+}
+
 template <typename T, int LB>
 static cmm_status launch_adjoint_t(const AdjointArgs& a0, hipStream_t s) {
   ProfScope prof_("adjoint", s);
@@ -402,6 +630,11 @@ static cmm_status launch_adjoint_t(const AdjointArgs& a0, hipStream_t s) {
 }
 
 cmm_status launch_adjoint(const AdjointArgs& a, cmm_dtype dt, int lb, hipStream_t s) {
+  // b_lo = 2^13: the 16-element layout when its LDS holds the rows
+  if (lb == 13 && adjoint16_lds_bytes(dt, a.c.n_rows, a.c.n_cols) + 2048 <= 160 * 1024) {
+    if (dt == CMM_F64) return launch_adjoint16_t<double>(a, s);
+    return launch_adjoint16_t<float>(a, s);
+  }
   if (dt == CMM_F64) {
     switch (lb) {
       case 11: return launch_adjoint_t<double, 11>(a, s);

@@ -369,62 +369,7 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_batched_kernel(
 }
 
 // ------------------------------------------------ 16 elements per thread
-// The float64 variant for b_lo = 2^13 with 512 threads (two wavefronts per
-// SIMD): 4 register bits, 6 lane bits, 3 wave bits.
-//   L1 (gather, pass 1): reg -> u_lo bits 0..3, lane bits 4,5 -> 4,5,
-//       lane bits 0..3 -> 6..9, waves -> 10..12.  Pass 1: stages 0..3 in
-//       registers, stages 4 and 5 after permlane16/32 swaps with reg bits 0/1.
-//   L2 (pass 2): reg -> 6..9, lane bits 4,5 -> 10,11 (permlane swaps),
-//       lane bit 3 -> 12 (a DPP row_ror:8 butterfly, i.e. partner lane
-//       xor 8), lane bits 0..2 -> 0..2, waves -> 3..5.
-// Transpose buffer padding g(x) = x + (x >> 6) + 8 * bit12(x) makes both
-// the L1' writes and the L2 reads free of bank conflicts and is additive in
-// the register part of the index.
-
-__device__ __forceinline__ uint32_t pad16(uint32_t x) { return x + (x >> 6) + ((x >> 9) & 8u); }
-
-// Butterfly across lane bit 3: lanes with bit 3 clear keep a + b, lanes
-// with it set b' = a - b, where the partner value comes from lane xor 8
-// (row_ror:8 within 16-lane rows).
-__device__ __forceinline__ double dpp_xor8(double x) {
-  const uint64_t u = (uint64_t)__double_as_longlong(x);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x128, 0xF, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x128, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-__device__ __forceinline__ float dpp_xor8(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
-}
-
-template <int J, typename T>
-__device__ __forceinline__ void stage_reg16(T (&v)[16]) {
-#pragma unroll
-  for (int e = 0; e < 16; ++e)
-    if ((e & (1 << J)) == 0) bfly(v[e], v[e | (1 << J)]);
-}
-template <int J, int S, typename T>
-__device__ __forceinline__ void swap_reg16(T (&v)[16]) {
-#pragma unroll
-  for (int e = 0; e < 16; ++e)
-    if ((e & (1 << J)) == 0) {
-      if (S == 16) xswap16(v[e], v[e | (1 << J)]);
-      else xswap32(v[e], v[e | (1 << J)]);
-    }
-}
-template <typename T>
-__device__ __forceinline__ void pass1_16(T (&v)[16]) {
-  stage_reg16<0>(v); stage_reg16<1>(v); stage_reg16<2>(v); stage_reg16<3>(v);
-  swap_reg16<0, 16>(v); stage_reg16<0>(v);
-  swap_reg16<1, 32>(v); stage_reg16<1>(v);
-}
-template <typename T>
-__device__ __forceinline__ void pass2_16(T (&v)[16], T sgn8) {
-  stage_reg16<0>(v); stage_reg16<1>(v); stage_reg16<2>(v); stage_reg16<3>(v);
-  swap_reg16<0, 16>(v); stage_reg16<0>(v);
-  swap_reg16<1, 32>(v); stage_reg16<1>(v);
-#pragma unroll
-  for (int e = 0; e < 16; ++e) v[e] = fma(v[e], sgn8, dpp_xor8(v[e]));
-}
+// (layout and transform passes in wht_regs.h)
 
 // SINGLE: one row buffer shared by the two operands (A staged, fixed up and
 // gathered before B), for rows too long to stage both at once.
