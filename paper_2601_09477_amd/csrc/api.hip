@@ -412,8 +412,11 @@ BackwardPlan make_backward_plan(const cmm_problem* pr) {
   if (g < 1) g = 1;
   while (g > 1 && ((units * g) & 7) != 0 && g < kc) ++g;
   P.groups = (int)g;
-  // W scatter: float64 windows of 2^13 buckets, about 512 work-groups
-  P.sh.wb = pr->log2b < 13 ? pr->log2b : 13;
+  // W scatter: LDS windows of 128 KB (2^15 float32 or 2^14 float64 sums),
+  // about 512 work-groups
+  P.sh.f32 = P.cdt == CMM_F32;
+  const int wb_max = P.sh.f32 ? 15 : 14;
+  P.sh.wb = pr->log2b < wb_max ? pr->log2b : wb_max;
   const int64_t nwin = (int64_t)1 << (pr->log2b - P.sh.wb);
   int64_t blocks = 512 / ((int64_t)d * nwin);
   if (blocks < 1) blocks = 1;

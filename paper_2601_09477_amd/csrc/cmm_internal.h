@@ -162,11 +162,12 @@ cmm_status launch_compress_batched(char* ws, const BatchPair* pairs, const Batch
 cmm_status launch_compress_mfma(const CompressArgs& a, cmm_dtype lp, hipStream_t s);
 // ------------------------------------------------ differentiation form
 // Shape of the W scatter (extract^T): row blocks of rows_per rows, windows
-// of 2^wb buckets.
+// of 2^wb buckets (at most 128 KB of LDS).
 struct ScatterShape {
   int wb;
   int64_t rows_per;
   int64_t blocks;
+  bool f32;          // window sums in float32 (the float32 form), else float64
 };
 // q partials [blocks][d][2^log2b] (float64) of the bucket sums of W.
 cmm_status launch_wscatter(const void* W, cmm_dtype wdt, int64_t ldw, const uint32_t* tab1,

@@ -32,18 +32,19 @@ namespace {
 
 // ---------------------------------------------------------- extract^T
 // q partials: one work-group per (row block, window of 2^wb buckets,
-// repetition t).  The window lives in LDS as float64 and is summed with LDS
-// atomics (the order of the additions inside a window is not fixed; the
-// partials are then added in ascending block order).
+// repetition t).  The window lives in LDS (float64, or float32 for the
+// float32 form, where a block adds a few terms per bucket) and is summed
+// with LDS atomics (the order of the additions inside a window is not
+// fixed); the partials are then added in ascending block order in float64.
 constexpr int kScatterThreads = 256;
 
-template <typename TW>
+template <typename TW, typename TA>
 __global__ __launch_bounds__(kScatterThreads) void wscatter_kernel(
     const TW* __restrict__ W, int64_t ldw, const uint32_t* __restrict__ tab1,
     const uint32_t* __restrict__ tab2, int64_t n_rows, int64_t n_cols, int log2b, int wb,
     int64_t rows_per, int64_t blocks, int cache_tab2, double* __restrict__ part) {
   extern __shared__ __align__(16) unsigned char smem[];
-  double* q = reinterpret_cast<double*>(smem);
+  TA* q = reinterpret_cast<TA*>(smem);
   const uint32_t wlen = 1u << wb;
   uint32_t* t2c = reinterpret_cast<uint32_t*>(q + wlen);
   const int64_t rb = blockIdx.x % blocks;
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(kScatterThreads) void wscatter_kernel(
   const int t = blockIdx.y;
   const int d = gridDim.y;
   const uint32_t bmask = (uint32_t)(((uint64_t)1 << log2b) - 1u);
-  for (uint32_t x = threadIdx.x; x < wlen; x += kScatterThreads) q[x] = 0.0;
+  for (uint32_t x = threadIdx.x; x < wlen; x += kScatterThreads) q[x] = TA(0);
   const uint32_t* t1 = tab1 + (size_t)t * n_rows;
   const uint32_t* t2 = tab2 + (size_t)t * n_cols;
   if (cache_tab2)
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(kScatterThreads) void wscatter_kernel(
       const uint32_t e2 = cache_tab2 ? t2c[j] : t2[j];
       const uint32_t x = (e1 ^ e2) & bmask;
       if ((x >> wb) == win) {
-        const double v = (double)wr[j];
+        const TA v = (TA)wr[j];
         atomicAdd(&q[x & (wlen - 1u)], ((e1 ^ e2) & kSignBit) ? -v : v);
       }
     }
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kScatterThreads) void wscatter_kernel(
   __syncthreads();
   const size_t b = (size_t)1 << log2b;
   double* dst = part + ((size_t)rb * d + t) * b + ((size_t)win << wb);
-  for (uint32_t x = threadIdx.x; x < wlen; x += kScatterThreads) dst[x] = q[x];
+  for (uint32_t x = threadIdx.x; x < wlen; x += kScatterThreads) dst[x] = (double)q[x];
 }
 
 // --------------------------------------------------------- fused adjoint
@@ -478,38 +479,83 @@ __global__ __launch_bounds__(512, 2) void adjoint16_kernel(AdjointArgs aa) {
 // out = sum over p (ascending) of part[p][kk][i], summed in float64:
 //   transpose = 0:  out[(kb + kk) * ld + i]     (dB rows)
 //   transpose = 1:  out[i * ld + kb + kk]       (dA columns)
-template <typename TP, typename TO>
+// Four consecutive i per thread (one 16- or 32-byte load per partial) when
+// n is a multiple of four; otherwise one.
+template <typename TP, int VW>
+struct VecOf;
+template <> struct VecOf<float, 4> { typedef float4 type; };
+template <> struct VecOf<double, 4> { typedef double4 type; };
+
+template <typename TP, int VW>
+__device__ __forceinline__ void load_vw(const TP* __restrict__ p, double (&v)[VW]) {
+  if constexpr (VW == 4) {
+    const typename VecOf<TP, 4>::type x = *reinterpret_cast<const typename VecOf<TP, 4>::type*>(p);
+    v[0] = (double)x.x; v[1] = (double)x.y; v[2] = (double)x.z; v[3] = (double)x.w;
+  } else {
+    v[0] = (double)p[0];
+  }
+}
+
+template <typename TP, typename TO, int VW>
 __global__ __launch_bounds__(256) void adjoint_reduce_rows(const TP* __restrict__ part, int P,
                                                            int64_t kc, int64_t n,
                                                            TO* __restrict__ out, int64_t ld,
                                                            int64_t kb) {
   const int64_t kk = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * VW;
   if (i >= n) return;
-  double s = 0.0;
-  for (int p = 0; p < P; ++p) s += (double)part[((size_t)p * kc + kk) * n + i];
-  out[(kb + kk) * ld + i] = (TO)s;
+  double s[VW], v[VW];
+#pragma unroll
+  for (int q = 0; q < VW; ++q) s[q] = 0.0;
+  for (int p = 0; p < P; ++p) {
+    load_vw<TP, VW>(part + ((size_t)p * kc + kk) * n + i, v);
+#pragma unroll
+    for (int q = 0; q < VW; ++q) s[q] += v[q];
+  }
+#pragma unroll
+  for (int q = 0; q < VW; ++q) out[(kb + kk) * ld + i + q] = (TO)s[q];
 }
 
-template <typename TP, typename TO>
+template <typename TP, typename TO, int VW>
 __global__ __launch_bounds__(256) void adjoint_reduce_cols(const TP* __restrict__ part, int P,
                                                            int64_t kc, int64_t n,
                                                            TO* __restrict__ out, int64_t ld,
                                                            int64_t kb) {
+  // tile of 64 k x 64 i; 16 x 16 threads, each 4 i (VW = 4) or 1 i at a stride
   __shared__ double tile[64][65];
   const int64_t i0 = (int64_t)blockIdx.x * 64, kk0 = (int64_t)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t kk = kk0 + r, i = i0 + tx;
-    double s = 0.0;
-    if (kk < kc && i < n)
-      for (int p = 0; p < P; ++p) s += (double)part[((size_t)p * kc + kk) * n + i];
-    tile[r][tx] = s;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  for (int r = ty; r < 64; r += 16) {
+    const int64_t kk = kk0 + r;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (kk < kc) {
+      if constexpr (VW == 4) {
+        const int64_t i = i0 + 4 * tx;
+        if (i < n) {
+          double v[4];
+          for (int p = 0; p < P; ++p) {
+            load_vw<TP, 4>(part + ((size_t)p * kc + kk) * n + i, v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] += v[q];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t i = i0 + tx + 16 * q;
+          if (i < n)
+            for (int p = 0; p < P; ++p) s[q] += (double)part[((size_t)p * kc + kk) * n + i];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tile[r][VW == 4 ? 4 * tx + q : tx + 16 * q] = s[q];
   }
   __syncthreads();
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t i = i0 + r, kk = kk0 + tx;
-    if (i < n && kk < kc) out[i * ld + kb + kk] = (TO)tile[tx][r];
+  const int c = threadIdx.x & 63, rr = threadIdx.x >> 6;   // 64 x 4 for the writes
+  for (int r = rr; r < 64; r += 4) {
+    const int64_t i = i0 + r, kk = kk0 + c;
+    if (i < n && kk < kc) out[i * ld + kb + kk] = (TO)tile[c][r];
   }
 }
 
@@ -536,30 +582,39 @@ cmm_status launch_zero_matrix(void* out, cmm_dtype dt, int64_t rows, int64_t col
   return hip_check(hipGetLastError(), "zero fill launch");
 }
 
+template <typename TW, typename TA>
+static cmm_status launch_wscatter_t(const TW* W, int64_t ldw, const uint32_t* tab1,
+                                    const uint32_t* tab2, int d, int64_t n_rows, int64_t n_cols,
+                                    int log2b, const ScatterShape& sh, double* part,
+                                    hipStream_t s) {
+  const size_t qbytes = sizeof(TA) << sh.wb;
+  const bool cache = qbytes + sizeof(uint32_t) * (size_t)n_cols <= 160 * 1024;
+  const size_t lds = qbytes + (cache ? sizeof(uint32_t) * (size_t)n_cols : 0);
+  const dim3 grid((unsigned)(sh.blocks << (log2b - sh.wb)), (unsigned)d);
+  auto kern = wscatter_kernel<TW, TA>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return hip_check(e, "wscatter: set LDS size");
+  hipLaunchKernelGGL(kern, grid, dim3(kScatterThreads), lds, s, W, ldw, tab1, tab2, n_rows, n_cols,
+                     log2b, sh.wb, sh.rows_per, sh.blocks, (int)cache, part);
+  return hip_check(hipGetLastError(), "wscatter kernel launch");
+}
+
 cmm_status launch_wscatter(const void* W, cmm_dtype wdt, int64_t ldw, const uint32_t* tab1,
                            const uint32_t* tab2, int d, int64_t n_rows, int64_t n_cols,
                            int log2b, const ScatterShape& sh, double* part, hipStream_t s) {
   ProfScope prof_("wscatter", s);
-  const size_t qbytes = sizeof(double) << sh.wb;
-  const bool cache = qbytes + sizeof(uint32_t) * (size_t)n_cols <= 160 * 1024;
-  const size_t lds = qbytes + (cache ? sizeof(uint32_t) * (size_t)n_cols : 0);
-  const dim3 grid((unsigned)(sh.blocks << (log2b - sh.wb)), (unsigned)d);
-  if (wdt == CMM_F64) {
-    hipError_t e = hipFuncSetAttribute((const void*)wscatter_kernel<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return hip_check(e, "wscatter: set LDS size");
-    hipLaunchKernelGGL(wscatter_kernel<double>, grid, dim3(kScatterThreads), lds, s,
-                       static_cast<const double*>(W), ldw, tab1, tab2, n_rows, n_cols, log2b,
-                       sh.wb, sh.rows_per, sh.blocks, (int)cache, part);
-  } else {
-    hipError_t e = hipFuncSetAttribute((const void*)wscatter_kernel<float>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return hip_check(e, "wscatter: set LDS size");
-    hipLaunchKernelGGL(wscatter_kernel<float>, grid, dim3(kScatterThreads), lds, s,
-                       static_cast<const float*>(W), ldw, tab1, tab2, n_rows, n_cols, log2b,
-                       sh.wb, sh.rows_per, sh.blocks, (int)cache, part);
-  }
-  return hip_check(hipGetLastError(), "wscatter kernel launch");
+  if (sh.f32)
+    return wdt == CMM_F64
+               ? launch_wscatter_t<double, float>(static_cast<const double*>(W), ldw, tab1, tab2,
+                                                  d, n_rows, n_cols, log2b, sh, part, s)
+               : launch_wscatter_t<float, float>(static_cast<const float*>(W), ldw, tab1, tab2, d,
+                                                 n_rows, n_cols, log2b, sh, part, s);
+  return wdt == CMM_F64
+             ? launch_wscatter_t<double, double>(static_cast<const double*>(W), ldw, tab1, tab2, d,
+                                                 n_rows, n_cols, log2b, sh, part, s)
+             : launch_wscatter_t<float, double>(static_cast<const float*>(W), ldw, tab1, tab2, d,
+                                                n_rows, n_cols, log2b, sh, part, s);
 }
 
 size_t adjoint_lds_bytes(cmm_dtype dt, int lb, int64_t n_rows, int64_t n_cols) {
@@ -657,12 +712,22 @@ static void reduce_t(const void* part, int P, int64_t kc, int64_t n, void* out, 
                      int64_t kb, bool transpose, hipStream_t s) {
   const TP* pp = static_cast<const TP*>(part);
   TO* o = static_cast<TO*>(out);
+  // vector loads need every row of the partials 4-element aligned
+  const bool vec = n % 4 == 0 && (uintptr_t)part % (4 * sizeof(TP)) == 0;
   if (transpose) {
     const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((kc + 63) / 64));
-    hipLaunchKernelGGL((adjoint_reduce_cols<TP, TO>), grid, dim3(256), 0, s, pp, P, kc, n, o, ld, kb);
+    if (vec)
+      hipLaunchKernelGGL((adjoint_reduce_cols<TP, TO, 4>), grid, dim3(256), 0, s, pp, P, kc, n, o, ld, kb);
+    else
+      hipLaunchKernelGGL((adjoint_reduce_cols<TP, TO, 1>), grid, dim3(256), 0, s, pp, P, kc, n, o, ld, kb);
   } else {
-    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)kc);
-    hipLaunchKernelGGL((adjoint_reduce_rows<TP, TO>), grid, dim3(256), 0, s, pp, P, kc, n, o, ld, kb);
+    if (vec) {
+      const dim3 grid((unsigned)((n / 4 + 255) / 256), (unsigned)kc);
+      hipLaunchKernelGGL((adjoint_reduce_rows<TP, TO, 4>), grid, dim3(256), 0, s, pp, P, kc, n, o, ld, kb);
+    } else {
+      const dim3 grid((unsigned)((n + 255) / 256), (unsigned)kc);
+      hipLaunchKernelGGL((adjoint_reduce_rows<TP, TO, 1>), grid, dim3(256), 0, s, pp, P, kc, n, o, ld, kb);
+    }
   }
 }
 
