@@ -112,6 +112,31 @@ cmm_status cmm_extract(const double* p, const uint32_t* tab1, const uint32_t* ta
                        int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
                        void* C_hat, cmm_dtype out_dtype, int64_t ldc, void* stream);
 
+/* ---------------------------------------------------------- sparse queries */
+/* Decompress at a list of entries (Algorithm 1's Decompress, one pair at a
+ * time, without the dense output):
+ *   out[q] = Median_t ( s1_t(rows[q]) s2_t(cols[q]) p[t][h1_t(rows[q]) xor h2_t(cols[q])] )
+ * (or the mean) for q < count.  rows, cols: device int64[count]; an index
+ * outside [0, n_rows) x [0, n_cols) gives NaN.  out: device out_dtype[count]. */
+cmm_status cmm_extract_entries(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                               int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
+                               const int64_t* rows, const int64_t* cols, int64_t count, void* out,
+                               cmm_dtype out_dtype, void* stream);
+
+/* Heavy hitters: every (i, j) of the n_rows x n_cols grid whose estimate has
+ * |C_hat[i][j]| >= threshold (the large entries of the product, which the
+ * compressed product is meant to find, Section 1), without writing the
+ * dense C_hat.  The hits are written to out_rows / out_cols (device int64)
+ * and out_vals (device out_dtype) in no particular order; *count (device
+ * int64, zeroed by the call) receives the number of hits.  When it exceeds
+ * capacity only `capacity` of them (an arbitrary subset) are written.
+ * The values are those cmm_extract gives, bit for bit. */
+cmm_status cmm_extract_heavy(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                             int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
+                             double threshold, int64_t* out_rows, int64_t* out_cols,
+                             void* out_vals, cmm_dtype out_dtype, int64_t capacity,
+                             int64_t* count, void* stream);
+
 /* ------------------------------------------------------------- end to end */
 /* One compressed product C_hat ~ A B (Algorithm 1 Compress + dense
  * Decompress).
@@ -228,7 +253,7 @@ cmm_status cmm_estimate_backward(const cmm_problem* prob, const void* W, int64_t
  * cmm_profile_query returns the summed elapsed time and the number of
  * launches of one kernel ("hash", "transpose", "plan", "compress",
  * "reduce", "fwht", "extract", "sketch", "accumulate", "wscatter",
- * "adjoint", "adjoint_reduce") since the last
+ * "adjoint", "adjoint_reduce", "extract_entries", "extract_heavy") since the last
  * cmm_profile_enable call.  Enabling or disabling discards the records.
  * query waits for the recorded events.  Off by default. */
 void cmm_profile_enable(int on);

@@ -233,6 +233,24 @@ def extract(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, estimator: str = 
     return out
 
 
+def extract_entries(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, rows, cols,
+                    estimator: str = "median") -> np.ndarray:
+    """Algorithm 1, Decompress, at a list of entries (rows[q], cols[q]): the
+    median (odd d) or mean over t of s1 s2 p[t][h1 xor h2]; NaN for an index
+    outside the tables."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    d = p.shape[0]
+    out = np.full(len(rows), np.nan)
+    ok = (rows >= 0) & (rows < tab1.shape[1]) & (cols >= 0) & (cols < tab2.shape[1])
+    r, c = rows[ok], cols[ok]
+    x = np.empty((d, len(r)))
+    for t in range(d):
+        x[t] = sign(tab1[t][r]) * sign(tab2[t][c]) * p[t][bucket(tab1[t][r]) ^ bucket(tab2[t][c])]
+    out[ok] = np.median(x, axis=0) if estimator == "median" else x.mean(axis=0)
+    return out
+
+
 def estimate(A: np.ndarray, B: np.ndarray, keys: np.ndarray, log2b: int,
              estimator: str = "median"):
     """Compress + dense Decompress through the plain definition.

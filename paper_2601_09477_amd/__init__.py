@@ -28,6 +28,7 @@ CMM_F64, CMM_F32, CMM_BF16, CMM_F16 = range(4)
 CMM_MEDIAN, CMM_MEAN = range(2)
 
 EXPORTED = ["cmm_hash", "cmm_sketch", "cmm_fwht", "cmm_accumulate", "cmm_extract",
+            "cmm_extract_entries", "cmm_extract_heavy",
             "cmm_workspace_size", "cmm_estimate", "cmm_backward_workspace_size",
             "cmm_estimate_backward", "cmm_batch_create", "cmm_batch_destroy",
             "cmm_batch_workspace_size", "cmm_batch_autotune", "cmm_batch_set_config",
@@ -79,6 +80,9 @@ def lib() -> ctypes.CDLL:
         "cmm_fwht": [vp, i32, i64, i32, dbl, vp],
         "cmm_accumulate": [vp, vp, i32, i32, i64, i32, vp, vp],
         "cmm_extract": [vp, vp, vp, i32, i64, i64, i32, i32, vp, i32, i64, vp],
+        "cmm_extract_entries": [vp, vp, vp, i32, i64, i64, i32, i32, vp, vp, i64, vp, i32, vp],
+        "cmm_extract_heavy": [vp, vp, vp, i32, i64, i64, i32, i32, dbl, vp, vp, vp, i32, i64, vp,
+                              vp],
         "cmm_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
         "cmm_estimate": [ctypes.POINTER(Problem), vp, ctypes.c_size_t, vp],
         "cmm_backward_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
@@ -177,6 +181,46 @@ def cmm_extract(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat, ldc=N
     _check("cmm_extract", lib().cmm_extract(_ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols,
                                             log2b, estimator, _ptr(C_hat), _dtype_code(C_hat),
                                             ldc, _stream(stream)))
+
+
+def cmm_extract_entries(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, rows, cols, out,
+                        stream=None) -> None:
+    """out[q] = estimate at (rows[q], cols[q]); rows, cols int64 device tensors."""
+    _check("cmm_extract_entries", lib().cmm_extract_entries(
+        _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, estimator, _ptr(rows),
+        _ptr(cols), rows.numel(), _ptr(out), _dtype_code(out), _stream(stream)))
+
+
+def cmm_extract_heavy(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, threshold, out_rows,
+                      out_cols, out_vals, count, stream=None) -> None:
+    """Entries with |C_hat| >= threshold into the lists (capacity = their length);
+    count: int64 device tensor of one element, receives the number of hits."""
+    _check("cmm_extract_heavy", lib().cmm_extract_heavy(
+        _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, estimator, float(threshold),
+        _ptr(out_rows), _ptr(out_cols), _ptr(out_vals), _dtype_code(out_vals), out_rows.numel(),
+        _ptr(count), _stream(stream)))
+
+
+def heavy_hitters(est: "Estimate", threshold: float, capacity: int = 1 << 20,
+                  estimator: str = "median", out_dtype=None):
+    """(rows, cols, values) of every entry with |C_hat| >= threshold of an
+    estimate made with dense=False, sorted by (row, column)."""
+    torch = _torch()
+    dev = est.p.device
+    d, b = est.p.shape
+    n_rows, n_cols = est.tab1.shape[1], est.tab2.shape[1]
+    rows = torch.empty(capacity, dtype=torch.int64, device=dev)
+    cols = torch.empty(capacity, dtype=torch.int64, device=dev)
+    vals = torch.empty(capacity, dtype=out_dtype or torch.float64, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    est_code = CMM_MEDIAN if estimator == "median" else CMM_MEAN
+    cmm_extract_heavy(est.p, est.tab1, est.tab2, d, n_rows, n_cols, int(b).bit_length() - 1,
+                      est_code, threshold, rows, cols, vals, count)
+    k = int(count.item())
+    if k > capacity:
+        raise CmmError("heavy_hitters", CMM_ENOMEM, f"{k} hits exceed capacity {capacity}")
+    order = torch.argsort(rows[:k] * n_cols + cols[:k])
+    return rows[:k][order], cols[:k][order], vals[:k][order]
 
 
 def cmm_workspace_size(prob: Problem) -> int:

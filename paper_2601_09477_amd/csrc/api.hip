@@ -651,6 +651,61 @@ cmm_status cmm_extract(const double* p, const uint32_t* tab1, const uint32_t* ta
                         ldc, as_stream(stream));
 }
 
+static cmm_status check_decompress(const double* p, const uint32_t* tab1, const uint32_t* tab2,
+                                   int d, int64_t n_rows, int64_t n_cols, int log2b,
+                                   cmm_estimator estimator, cmm_dtype out_dtype, const char* fn) {
+  cmm_status s;
+  if ((s = check_d(d, fn)) != CMM_OK) return s;
+  if ((s = check_log2b(log2b, fn)) != CMM_OK) return s;
+  if (estimator != CMM_MEDIAN && estimator != CMM_MEAN)
+    return invalid(std::string(fn) + ": unknown estimator");
+  if (estimator == CMM_MEDIAN && d % 2 == 0)
+    return invalid(std::string(fn) + ": the median estimator needs an odd d");
+  if (d > 63 && estimator == CMM_MEDIAN) {
+    set_error(std::string(fn) + ": median over more than 63 repetitions is not implemented");
+    return CMM_EUNSUPPORTED;
+  }
+  if (!is_f64_or_f32(out_dtype)) return invalid(std::string(fn) + ": out_dtype must be CMM_F64 or CMM_F32");
+  if (n_rows < 0 || n_cols < 0) return invalid(std::string(fn) + ": negative size");
+  if (n_rows > kMaxHashDomain || n_cols > kMaxHashDomain)
+    return invalid(std::string(fn) + ": sizes must be <= 2^32");
+  if ((n_rows > 0 && n_cols > 0) && (!p || !tab1 || !tab2))
+    return invalid(std::string(fn) + ": null pointer");
+  return CMM_OK;
+}
+
+cmm_status cmm_extract_entries(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                               int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
+                               const int64_t* rows, const int64_t* cols, int64_t count, void* out,
+                               cmm_dtype out_dtype, void* stream) {
+  cmm_status s = check_decompress(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, out_dtype,
+                                  "cmm_extract_entries");
+  if (s != CMM_OK) return s;
+  if (count < 0) return invalid("cmm_extract_entries: negative count");
+  if (count == 0) return CMM_OK;
+  if (!rows || !cols || !out) return invalid("cmm_extract_entries: null pointer");
+  return launch_extract_entries(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, rows, cols,
+                                count, out, out_dtype, as_stream(stream));
+}
+
+cmm_status cmm_extract_heavy(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                             int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
+                             double threshold, int64_t* out_rows, int64_t* out_cols,
+                             void* out_vals, cmm_dtype out_dtype, int64_t capacity,
+                             int64_t* count, void* stream) {
+  cmm_status s = check_decompress(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, out_dtype,
+                                  "cmm_extract_heavy");
+  if (s != CMM_OK) return s;
+  if (!count) return invalid("cmm_extract_heavy: count is null");
+  if (capacity < 0) return invalid("cmm_extract_heavy: negative capacity");
+  if (capacity > 0 && (!out_rows || !out_cols || !out_vals))
+    return invalid("cmm_extract_heavy: null output list");
+  if (!(threshold >= 0.0)) return invalid("cmm_extract_heavy: threshold must be >= 0 (not NaN)");
+  return launch_extract_heavy(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, threshold,
+                              out_rows, out_cols, out_vals, out_dtype, capacity, count,
+                              as_stream(stream));
+}
+
 cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes) {
   cmm_status s = validate_problem(prob, "cmm_workspace_size");
   if (s != CMM_OK) return s;

@@ -75,6 +75,16 @@ cmm_status launch_extract(const double* p, const uint32_t* tab1, const uint32_t*
                           int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator est,
                           void* C_hat, cmm_dtype out_dt, int64_t ldc, hipStream_t s);
 
+cmm_status launch_extract_entries(const double* p, const uint32_t* tab1, const uint32_t* tab2,
+                                  int d, int64_t n_rows, int64_t n_cols, int log2b,
+                                  cmm_estimator est, const int64_t* rows, const int64_t* cols,
+                                  int64_t count, void* out, cmm_dtype out_dt, hipStream_t s);
+cmm_status launch_extract_heavy(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                                int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator est,
+                                double threshold, int64_t* rows, int64_t* cols, void* vals,
+                                cmm_dtype out_dt, int64_t capacity, int64_t* count,
+                                hipStream_t s);
+
 // Fill n doubles with zero (a kernel, not hipMemsetAsync, so that the
 // sequence stays valid under stream capture).
 cmm_status launch_zero(double* x, size_t n, hipStream_t s);

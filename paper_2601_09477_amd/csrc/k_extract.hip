@@ -97,6 +97,142 @@ __global__ __launch_bounds__(kCols) void extract_generic_kernel(
   }
 }
 
+// ------------------------------------------------------- sparse queries
+// Decompress at a list of entries: one thread per (rows[q], cols[q]).
+template <typename OutT>
+__global__ __launch_bounds__(256) void extract_entries_kernel(
+    const double* __restrict__ p, const uint32_t* __restrict__ tab1,
+    const uint32_t* __restrict__ tab2, int d, int64_t n_rows, int64_t n_cols, int log2b, int mean,
+    const int64_t* __restrict__ rows, const int64_t* __restrict__ cols, int64_t count,
+    OutT* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= count) return;
+  const int64_t i = rows[q], j = cols[q];
+  if (i < 0 || i >= n_rows || j < 0 || j >= n_cols) {
+    out[q] = (OutT)__builtin_nan("");
+    return;
+  }
+  const int64_t b = (int64_t)1 << log2b;
+  double v[kMaxD];
+  double s = 0.0;
+  for (int t = 0; t < d; ++t) {
+    const uint32_t e = tab1[(size_t)t * n_rows + i] ^ tab2[(size_t)t * n_cols + j];
+    const double x = p[(size_t)t * b + (e & (uint32_t)(b - 1))];
+    const double y = (e & kSignBit) ? -x : x;
+    s += y;
+    if (!mean) {
+      int r = t;
+      while (r > 0 && v[r - 1] > y) { v[r] = v[r - 1]; --r; }
+      v[r] = y;
+    }
+  }
+  out[q] = (OutT)(mean ? s / d : v[d / 2]);
+}
+
+// Heavy hitters over the dense grid: the tile structure of extract_kernel,
+// but an entry is written only when |C_hat| >= thr.  The hits of a wave are
+// counted with a ballot and reserved with one atomic add; each hit lane
+// writes at the base plus the number of hit lanes below it.
+template <typename OutT, int D>
+__global__ __launch_bounds__(kCols) void heavy_kernel(
+    const double* __restrict__ p, const uint32_t* __restrict__ tab1,
+    const uint32_t* __restrict__ tab2, int64_t n_rows, int64_t n_cols, int log2b, int mean,
+    double thr, int64_t* __restrict__ out_rows, int64_t* __restrict__ out_cols,
+    OutT* __restrict__ out_vals, int64_t capacity, unsigned long long* __restrict__ count) {
+  const int64_t j = (int64_t)blockIdx.y * kCols + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * kRows;
+  const int64_t b = (int64_t)1 << log2b;
+  const uint32_t bmask = (uint32_t)(b - 1);
+  const bool jok = j < n_cols;
+  const uint32_t lane = threadIdx.x & 63;
+  double v[kRows][D];
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    const uint32_t e2 = jok ? tab2[(size_t)t * n_cols + j] : 0u;
+    const double* pt = p + (size_t)t * b;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const int64_t i = i0 + r < n_rows ? i0 + r : n_rows - 1;
+      const uint32_t e = tab1[(size_t)t * n_rows + i] ^ e2;
+      const double x = pt[e & bmask];
+      v[r][t] = (e & kSignBit) ? -x : x;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    double o;
+    if (mean) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < D; ++t) s += v[r][t];
+      o = s / D;
+    } else {
+      sort_net<D>(v[r]);
+      o = v[r][D / 2];
+    }
+    const bool hit = jok && (i0 + r < n_rows) && fabs(o) >= thr;
+    const unsigned long long mask = __ballot(hit);   // every lane of the wave takes part
+    if (mask == 0ull) continue;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+    base = __shfl(base, 0);
+    if (hit) {
+      const unsigned long long slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+      if (slot < (unsigned long long)capacity) {
+        out_rows[slot] = i0 + r;
+        out_cols[slot] = j;
+        out_vals[slot] = (OutT)o;
+      }
+    }
+  }
+}
+
+template <typename OutT>
+__global__ __launch_bounds__(kCols) void heavy_generic_kernel(
+    const double* __restrict__ p, const uint32_t* __restrict__ tab1,
+    const uint32_t* __restrict__ tab2, int d, int64_t n_rows, int64_t n_cols, int log2b,
+    int mean, double thr, int64_t* __restrict__ out_rows, int64_t* __restrict__ out_cols,
+    OutT* __restrict__ out_vals, int64_t capacity, unsigned long long* __restrict__ count) {
+  const int64_t j = (int64_t)blockIdx.y * kCols + threadIdx.x;
+  const int64_t b = (int64_t)1 << log2b;
+  const uint32_t lane = threadIdx.x & 63;
+  const bool jok = j < n_cols;
+  for (int r = 0; r < kRows; ++r) {
+    const int64_t i = (int64_t)blockIdx.x * kRows + r;
+    double o = 0.0;
+    if (jok && i < n_rows) {
+      double v[kMaxD];
+      double s = 0.0;
+      for (int t = 0; t < d; ++t) {
+        const uint32_t e = tab1[(size_t)t * n_rows + i] ^ tab2[(size_t)t * n_cols + j];
+        const double x = p[(size_t)t * b + (e & (uint32_t)(b - 1))];
+        const double y = (e & kSignBit) ? -x : x;
+        s += y;
+        int q = t;
+        while (q > 0 && v[q - 1] > y) { v[q] = v[q - 1]; --q; }
+        v[q] = y;
+      }
+      o = mean ? s / d : v[d / 2];
+    }
+    const bool hit = jok && i < n_rows && fabs(o) >= thr;
+    const unsigned long long mask = __ballot(hit);
+    if (mask == 0ull) continue;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+    base = __shfl(base, 0);
+    if (hit) {
+      const unsigned long long slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+      if (slot < (unsigned long long)capacity) {
+        out_rows[slot] = i;
+        out_cols[slot] = j;
+        out_vals[slot] = (OutT)o;
+      }
+    }
+  }
+}
+
+__global__ void zero_counter_kernel(unsigned long long* c) { *c = 0ull; }
+
 template <typename OutT>
 cmm_status run(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
                int64_t n_rows, int64_t n_cols, int log2b, int mean, OutT* C, int64_t ldc,
@@ -139,6 +275,75 @@ cmm_status launch_extract(const double* p, const uint32_t* tab1, const uint32_t*
   if (out_dt == CMM_F64)
     return run<double>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, (double*)C_hat, ldc, s);
   return run<float>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, (float*)C_hat, ldc, s);
+}
+
+cmm_status launch_extract_entries(const double* p, const uint32_t* tab1, const uint32_t* tab2,
+                                  int d, int64_t n_rows, int64_t n_cols, int log2b,
+                                  cmm_estimator est, const int64_t* rows, const int64_t* cols,
+                                  int64_t count, void* out, cmm_dtype out_dt, hipStream_t s) {
+  ProfScope prof_("extract_entries", s);
+  const int mean = est == CMM_MEAN;
+  const int64_t blocks = (count + 255) / 256;
+  if (blocks > 0x7FFFFFFF) { set_error("cmm_extract_entries: too many entries"); return CMM_EUNSUPPORTED; }
+  if (out_dt == CMM_F64)
+    hipLaunchKernelGGL(extract_entries_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, p,
+                       tab1, tab2, d, n_rows, n_cols, log2b, mean, rows, cols, count,
+                       static_cast<double*>(out));
+  else
+    hipLaunchKernelGGL(extract_entries_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, p,
+                       tab1, tab2, d, n_rows, n_cols, log2b, mean, rows, cols, count,
+                       static_cast<float*>(out));
+  return hip_check(hipGetLastError(), "extract_entries kernel launch");
+}
+
+template <typename OutT>
+static cmm_status heavy_run(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                            int64_t n_rows, int64_t n_cols, int log2b, int mean, double thr,
+                            int64_t* rows, int64_t* cols, OutT* vals, int64_t capacity,
+                            unsigned long long* count, hipStream_t s) {
+  const int64_t gx = (n_rows + kRows - 1) / kRows;
+  const int64_t gy = (n_cols + kCols - 1) / kCols;
+  if (gx > 0x7FFFFFFF || gy > 65535) {
+    set_error("cmm_extract_heavy: n_cols above 65535 * 256 is not supported");
+    return CMM_EUNSUPPORTED;
+  }
+  const dim3 grid((unsigned)gx, (unsigned)gy);
+#define CMM_HEAVY_CASE(DV)                                                                      \
+  case DV:                                                                                      \
+    hipLaunchKernelGGL((heavy_kernel<OutT, DV>), grid, dim3(kCols), 0, s, p, tab1, tab2, n_rows, \
+                       n_cols, log2b, mean, thr, rows, cols, vals, capacity, count);            \
+    break;
+  switch (d) {
+    CMM_HEAVY_CASE(1)
+    CMM_HEAVY_CASE(3)
+    CMM_HEAVY_CASE(5)
+    CMM_HEAVY_CASE(7)
+    CMM_HEAVY_CASE(9)
+    CMM_HEAVY_CASE(11)
+    default:
+      hipLaunchKernelGGL(heavy_generic_kernel<OutT>, grid, dim3(kCols), 0, s, p, tab1, tab2, d,
+                         n_rows, n_cols, log2b, mean, thr, rows, cols, vals, capacity, count);
+  }
+#undef CMM_HEAVY_CASE
+  return hip_check(hipGetLastError(), "heavy kernel launch");
+}
+
+cmm_status launch_extract_heavy(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                                int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator est,
+                                double threshold, int64_t* rows, int64_t* cols, void* vals,
+                                cmm_dtype out_dt, int64_t capacity, int64_t* count,
+                                hipStream_t s) {
+  ProfScope prof_("extract_heavy", s);
+  unsigned long long* c = reinterpret_cast<unsigned long long*>(count);
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, c);
+  cmm_status st = hip_check(hipGetLastError(), "heavy counter reset");
+  if (st != CMM_OK || n_rows == 0 || n_cols == 0) return st;
+  const int mean = est == CMM_MEAN;
+  if (out_dt == CMM_F64)
+    return heavy_run<double>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, threshold, rows, cols,
+                             static_cast<double*>(vals), capacity, c, s);
+  return heavy_run<float>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, threshold, rows, cols,
+                          static_cast<float*>(vals), capacity, c, s);
 }
 
 }  // namespace cmm

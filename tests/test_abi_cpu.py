@@ -65,6 +65,13 @@ def test_problem_struct_layout_matches_header():
     lambda L: L.cmm_extract(1, 1, 1, 4, 8, 8, 8, 0, 1, 0, 8, None),     # median with even d
     lambda L: L.cmm_extract(1, 1, 1, 3, 8, 8, 8, 0, 1, 0, 7, None),     # ldc < n_cols
     lambda L: L.cmm_extract(1, 1, 1, 3, 8, 8, 8, 5, 1, 0, 8, None),     # unknown estimator
+    lambda L: L.cmm_extract_entries(1, 1, 1, 4, 8, 8, 8, 0, 1, 1, 4, 1, 0, None),  # median, even d
+    lambda L: L.cmm_extract_entries(1, 1, 1, 3, 8, 8, 8, 0, None, 1, 4, 1, 0, None),  # rows null
+    lambda L: L.cmm_extract_entries(1, 1, 1, 3, 8, 8, 8, 0, 1, 1, -1, 1, 0, None),  # count < 0
+    lambda L: L.cmm_extract_heavy(1, 1, 1, 3, 8, 8, 8, 0, float("nan"), 1, 1, 1, 0, 4, 1, None),
+    lambda L: L.cmm_extract_heavy(1, 1, 1, 3, 8, 8, 8, 0, 1.0, 1, 1, 1, 0, 4, None, None),  # count
+    lambda L: L.cmm_extract_heavy(1, 1, 1, 3, 8, 8, 8, 0, 1.0, None, 1, 1, 0, 4, 1, None),  # list
+    lambda L: L.cmm_extract_heavy(1, 1, 1, 3, 8, 8, 8, 0, 1.0, 1, 1, 1, 2, 4, 1, None),  # bf16 out
 ])
 def test_invalid_arguments_rejected_on_host(call):
     L = _lib_or_skip()

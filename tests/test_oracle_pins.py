@@ -237,6 +237,20 @@ def test_bucket_sums_sparse_equals_dense_definition():
     assert np.allclose(ps, brute, rtol=0, atol=1e-14)
 
 
+def test_extract_entries_equals_dense_extract():
+    # the list form of Decompress against the dense form at the same entries
+    w = small_random(30, 20, 25, 7, 5, seed=8)
+    t1, t2 = O.hash_tables(w.keys, 30, 25, 7)
+    p = O.bucket_sums(O.product(w.A, w.B), t1, t2, 7)
+    rng = np.random.default_rng(2)
+    rows, cols = rng.integers(0, 30, 40), rng.integers(0, 25, 40)
+    for est in ("median", "mean"):
+        dense = O.extract(p, t1, t2, est)
+        assert np.array_equal(O.extract_entries(p, t1, t2, rows, cols, est), dense[rows, cols])
+    out = O.extract_entries(p, t1, t2, [-1, 30, 3], [0, 0, 25])
+    assert np.all(np.isnan(out))
+
+
 def test_bucket_sums_brute_force_tiny():
     rng = np.random.default_rng(6)
     C = rng.integers(-9, 9, (5, 6)).astype(float)
