@@ -137,6 +137,34 @@ def run_estimate(w, compute: str, steps: int, warmup: int, out_dtype=None):
     return elapsed / steps * 1e3, kern, C_hat, p
 
 
+def heavy_hitter_extract(w, p, steps: int) -> dict:
+    """The heavy hitters above tau straight from the sketch p (no dense
+    output), timed beside the dense extract of the headline step."""
+    import torch
+
+    import paper_2601_09477_amd as cmm
+    dev = p.device
+    tab1 = torch.empty((w.d, w.n), dtype=torch.int32, device=dev)
+    tab2 = torch.empty_like(tab1)
+    keys = cmm.keys_tensor(w.keys, dev)
+    cmm.cmm_hash(keys, w.d, w.n, w.n, w.log2b, tab1, tab2)
+    cap = 1 << 20
+    rows = torch.empty(cap, dtype=torch.int64, device=dev)
+    cols = torch.empty(cap, dtype=torch.int64, device=dev)
+    vals = torch.empty(cap, dtype=torch.float64, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    args = (p, tab1, tab2, w.d, w.n, w.n, w.log2b, cmm.CMM_MEDIAN, w.tau, rows, cols, vals, count)
+    cmm.cmm_extract_heavy(*args)
+    torch.cuda.synchronize()
+    cmm.cmm_profile_enable(True)
+    for _ in range(steps):
+        cmm.cmm_extract_heavy(*args)
+    torch.cuda.synchronize()
+    ms, n = cmm.cmm_profile_query("extract_heavy")
+    cmm.cmm_profile_enable(False)
+    return {"threshold": w.tau, "hits": int(count.item()), "ms": ms / max(1, n)}
+
+
 def precision_form(steps: int, warmup: int) -> dict:
     """The precision form at n = 8192, b = 2^18, d = 9 (planted +-1, two
     planted columns per row): bf16 and fp16 on MFMA against plain float64 on
@@ -329,8 +357,9 @@ def main() -> int:
         del src, dst
     w = planted_4096(args.seed)
     n, d, log2b = w.n, w.d, w.log2b
-    ms_per_step, kern, C_hat, _ = run_estimate(w, "f64", args.steps, args.warmup)
+    ms_per_step, kern, C_hat, p = run_estimate(w, "f64", args.steps, args.warmup)
     rec = planted_recall(C_hat.cpu().numpy(), w.rows, w.cols, w.tau)
+    heavy = heavy_hitter_extract(w, p, args.steps)
     ms_comp, n_comp = kern["compress"]
     avg_comp = ms_comp / max(1, n_comp) * 1e-3
     ops = compress_ops(n, d, log2b)
@@ -348,6 +377,7 @@ def main() -> int:
                    "recall": rec["recall"], "background_ge_tau": rec["background_ge_tau"],
                    "tau": w.tau},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
+        "heavy_hitter_extract": heavy,
         "roofline": {"kernel": "compress (fused sketch + WHT + accumulate)", "bound": "alu",
                      "achieved": achieved / 1e12, "peak": PEAK_F64_ADD / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_F64_ADD,
