@@ -129,7 +129,7 @@ cmm_status validate_problem(const cmm_problem* pr, const char* fn) {
       return CMM_EUNSUPPORTED;
     }
     if (pr->n_rows > 16383 || pr->n_cols > 16383 ||
-        (2 * 16384 + (pr->n_rows + 8) / 8 * 8 + (pr->n_cols + 8) / 8 * 8) * 2 > 160 * 1024 ||
+        (2 * 16384 + (pr->n_rows + 72) / 8 * 8 + (pr->n_cols + 72) / 8 * 8) * 2 > 160 * 1024 - 256 ||
         plan_lds_bytes(pr->n_rows, 14) > 160 * 1024 || plan_lds_bytes(pr->n_cols, 14) > 160 * 1024) {
       set_error(std::string(fn) + ": the bf16/f16 precision form needs n_rows, n_cols <= 16383");
       return CMM_EUNSUPPORTED;

@@ -135,7 +135,14 @@ __device__ __forceinline__ uint32_t pack2(float x, float y, _Float16*) {
   return __builtin_bit_cast(uint32_t, r);
 }
 
-template <typename IN>
+// Collision fix-ups: DESC = true uses per-thread descriptors (the common
+// case, when their LDS fits); DESC = false walks the plan's chain lists.
+// They are separate instances because the chain-walking code alone, even
+// unexecuted, costs the loop a quarter of its speed.
+constexpr int kSlots = 4;      // descriptor slots per thread and operand
+constexpr int kDescLds = 2 * kSlots * kNT * 12;   // three words per descriptor
+
+template <typename IN, bool DESC>
 __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   typedef typename Mf<IN>::vec vec;
   typedef __attribute__((ext_vector_type(2))) uint32_t u2;
@@ -143,8 +150,10 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   constexpr int NS = kTiles * 4;   // gather slots per thread and operand
   extern __shared__ __align__(16) unsigned char smem[];
   // rows first (small LDS offsets), then the two transpose buffers
-  const int64_t pitchA = (a.n_rows + 1 + 7) / 8 * 8;     // 16-byte aligned rows + zero pad
-  const int64_t pitchB = (a.n_cols + 1 + 7) / 8 * 8;
+  // 16-byte aligned rows: the row, a zero pad at index n, then 64 spare
+  // elements (per-lane targets of absent collision slots)
+  const int64_t pitchA = (a.n_rows + 1 + 64 + 7) / 8 * 8;
+  const int64_t pitchB = (a.n_cols + 1 + 64 + 7) / 8 * 8;
   IN* rowA = reinterpret_cast<IN*>(smem);
   IN* rowB = rowA + pitchA;
   IN* tbufX = rowB + pitchB;                             // BLO
@@ -200,7 +209,7 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
   const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
   const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
-  if (ex_lds) {
+  if (!DESC && ex_lds) {
     for (int q = threadIdx.x; q < cntA; q += kNT) exl[q] = gA[q];
     for (int q = threadIdx.x; q < cntB; q += kNT) exl[cntA + q] = gB[q];
     int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
@@ -213,6 +222,126 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   const uint2* lexB = exl + cntA;
   const int32_t* lcsA = reinterpret_cast<const int32_t*>(exl + cntA + cntB);
   const int32_t* lcsB = lcsA + nchA + 1;
+  // Collision descriptors.  Thread tid owns chains tid + j kNT (j < kSlots).
+  // A descriptor (three words in LDS, built once per work unit) holds the
+  // chain's target and its next five rows as 15-bit row indices with their
+  // signs relative to the target (absent rows: the zero pad index n; an
+  // absent chain targets the lane's spare element after the pad):
+  //   w0 = target | m1 << 15 | s1 << 30 | more << 31
+  //   w1 = m2 | m3 << 15 | s2 << 30 | s3 << 31
+  //   w2 = m4 | m5 << 15 | s4 << 30 | s5 << 31
+  // A chain with more rows (a bucket of seven or more: about one in a
+  // million) and chains beyond the slots are finished from the plan's lists.
+  uint32_t* dsc = reinterpret_cast<uint32_t*>(exl);   // [word][operand][slot][kNT]
+  auto dref = [&](int word, int op, int j) -> uint32_t& {
+    return dsc[((word * 2 + op) * kSlots + j) * kNT + threadIdx.x];
+  };
+  auto build_desc = [&](int op, const int32_t* gc, const uint2* gp, int nch, uint32_t pad) {
+    for (int j = 0; j < kSlots; ++j) {
+      const int c = (int)threadIdx.x + j * kNT;
+      uint32_t m[6] = {pad + 1u + (threadIdx.x & 63u), pad, pad, pad, pad, pad};
+      uint32_t sg[6] = {0, 0, 0, 0, 0, 0};
+      uint32_t more = 0;
+      if (c < nch) {
+        const int beg = gc[c], end = gc[c + 1];
+        m[0] = gp[beg].x >> 16;
+        for (int r = 0; r < 5 && beg + r < end; ++r) {
+          const uint2 y = gp[beg + r];
+          m[r + 1] = y.x & 0xFFFFu;
+          sg[r + 1] = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+        }
+        more = end - beg > 5 ? 1u : 0u;
+      }
+      dref(0, op, j) = m[0] | (m[1] << 15) | (sg[1] << 30) | (more << 31);
+      dref(1, op, j) = m[2] | (m[3] << 15) | (sg[2] << 30) | (sg[3] << 31);
+      dref(2, op, j) = m[4] | (m[5] << 15) | (sg[4] << 30) | (sg[5] << 31);
+    }
+  };
+  if (DESC) {
+    build_desc(0, gcA, gA, nchA, (uint32_t)a.n_rows);
+    build_desc(1, gcB, gB, nchB, (uint32_t)a.n_cols);
+  }
+  // Fix-ups of both operands from their descriptors, straight-line: every
+  // slot loads its six values, sums them (float32, rank order) and stores
+  // once; a slot with more rows stores to its lane's spare element and is
+  // finished, still rounded once, in the rare pass.
+  auto fix_desc = [&](const int32_t* gcA_, const uint2* gpA_, const int32_t* gcB_, const uint2* gpB_) {
+    uint32_t q[2][kSlots][3];
+    float v[2][kSlots][6];
+    float sum[2][kSlots];
+#pragma unroll
+    for (int op = 0; op < 2; ++op)
+#pragma unroll
+      for (int j = 0; j < kSlots; ++j)
+#pragma unroll
+        for (int wd = 0; wd < 3; ++wd) q[op][j][wd] = dref(wd, op, j);
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      const IN* row = op ? rowB : rowA;
+#pragma unroll
+      for (int j = 0; j < kSlots; ++j)
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+          v[op][j][r] = to_f(row[(q[op][j][r >> 1] >> (15 * (r & 1))) & 0x7FFFu]);
+    }
+    bool rare = false;
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      IN* row = op ? rowB : rowA;
+      const uint32_t spare = (uint32_t)(op ? a.n_cols : a.n_rows) + 1u + (threadIdx.x & 63u);
+#pragma unroll
+      for (int j = 0; j < kSlots; ++j) {
+        float acc_ = v[op][j][0];
+#pragma unroll
+        for (int r = 1; r < 6; ++r) {
+          // sign of member r: w0 bit 30 for r = 1, else bit 30 + (r & 1) of word r / 2
+          const uint32_t word = q[op][j][r >> 1];
+          const uint32_t neg = (r == 1) ? (word >> 30) & 1u : (word >> (30 + (r & 1))) & 1u;
+          acc_ = acc_ + (neg ? -v[op][j][r] : v[op][j][r]);
+        }
+        sum[op][j] = acc_;
+        const bool more = (q[op][j][0] >> 31) != 0u;
+        rare = rare || more;
+        row[more ? spare : (q[op][j][0] & 0x7FFFu)] = (IN)acc_;
+      }
+    }
+    const bool extra = nchA > kSlots * kNT || nchB > kSlots * kNT;
+    if (rare || extra) {
+#pragma unroll
+      for (int op = 0; op < 2; ++op) {
+        IN* row = op ? rowB : rowA;
+        const int32_t* gc = op ? gcB_ : gcA_;
+        const uint2* gp = op ? gpB_ : gpA_;
+        for (int j = 0; j < kSlots; ++j) {
+          if (!(q[op][j][0] >> 31)) continue;
+          float acc_ = sum[op][j];
+          const int c = (int)threadIdx.x + j * kNT;
+          const int beg = gc[c], end = gc[c + 1];
+          for (int r = beg + 5; r < end; ++r) {
+            const uint2 y = gp[r];
+            const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+            const float w = to_f(row[y.x & 0xFFFFu]);
+            acc_ = acc_ + (neg ? -w : w);
+          }
+          row[q[op][j][0] & 0x7FFFu] = (IN)acc_;
+        }
+        // chains beyond the slots (disjoint targets)
+        const int nch = op ? nchB : nchA;
+        for (int c = kSlots * kNT + (int)threadIdx.x; c < nch; c += kNT) {
+          const int beg = gc[c], end = gc[c + 1];
+          const uint32_t tgt = gp[beg].x >> 16;
+          float acc_ = to_f(row[tgt]);
+          for (int r = beg; r < end; ++r) {
+            const uint2 y = gp[r];
+            const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+            const float w = to_f(row[y.x & 0xFFFFu]);
+            acc_ = acc_ + (neg ? -w : w);
+          }
+          row[tgt] = (IN)acc_;
+        }
+      }
+    }
+  };
 
   // H16 as the B operand (passes 1, 3) and as the A operand (pass 2): lane
   // holds H[4 lg + v][lm] = H[lm][4 lg + v].  Pass 4: M4 = H4 x I4 on the
@@ -338,8 +467,12 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
     if (dma) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();   // rows of k staged; the transpose buffers are free
     if (nchA + nchB > 0) {
-      { if (ex_lds) fix_chains_lp<IN, kNT>(rowA, lexA, lcsA, nchA, uhi); else fix_chains_lp<IN, kNT>(rowA, gA, gcA, nchA, uhi); }
-      { if (ex_lds) fix_chains_lp<IN, kNT>(rowB, lexB, lcsB, nchB, uhi); else fix_chains_lp<IN, kNT>(rowB, gB, gcB, nchB, uhi); }
+      if constexpr (DESC) {
+        fix_desc(gcA, gA, gcB, gB);
+      } else {
+        { if (ex_lds) fix_chains_lp<IN, kNT>(rowA, lexA, lcsA, nchA, uhi); else fix_chains_lp<IN, kNT>(rowA, gA, gcA, nchA, uhi); }
+        { if (ex_lds) fix_chains_lp<IN, kNT>(rowB, lexB, lcsB, nchB, uhi); else fix_chains_lp<IN, kNT>(rowB, gB, gcB, nchB, uhi); }
+      }
       __syncthreads();
     }
     front(rowA16, idxA, tbufX);
@@ -375,18 +508,19 @@ static cmm_status launch_mfma_t(const CompressArgs& a0, hipStream_t s) {
     set_error("compress (mfma): needs n_rows, n_cols <= 16383");
     return CMM_EUNSUPPORTED;
   }
-  const size_t pitch = ((size_t)a.n_rows + 1 + 7) / 8 * 8 + ((size_t)a.n_cols + 1 + 7) / 8 * 8;
+  const size_t pitch = ((size_t)a.n_rows + 1 + 64 + 7) / 8 * 8 + ((size_t)a.n_cols + 1 + 64 + 7) / 8 * 8;
   const size_t base = sizeof(IN) * (2 * ((size_t)1 << kLB) + pitch);
-  const size_t kMax = 160 * 1024;
+  const size_t kMax = 160 * 1024 - 256;   // the kernel's own counters take a few bytes more
   if (base > kMax) { set_error("compress (mfma): rows do not fit in LDS"); return CMM_EUNSUPPORTED; }
+  const bool desc = base + kDescLds <= kMax;
   int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
-  const int64_t want = a.n_rows + a.n_cols;
+  const int64_t want = desc ? kDescLds / 8 : a.n_rows + a.n_cols;
   if (cap > want) cap = want;
   a.ex_cap = cap;
   const size_t lds = base + sizeof(uint2) * (size_t)cap;
   a.dma = (a.n_rows % 8 == 0) && (a.n_cols % 8 == 0) && (a.ldb % 8 == 0) &&
           ((uintptr_t)a.At % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
-  auto kern = compress_mfma_kernel<IN>;
+  auto kern = desc ? compress_mfma_kernel<IN, true> : compress_mfma_kernel<IN, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return hip_check(e, "compress (mfma): set LDS size");
