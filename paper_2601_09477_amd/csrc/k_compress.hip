@@ -373,9 +373,21 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_batched_kernel(
 
 // SINGLE: one row buffer shared by the two operands (A staged, fixed up and
 // gathered before B), for rows too long to stage both at once.
-template <typename T, bool SINGLE>
+// DESC: collision fix-ups from per-thread descriptors (rows then carry 64
+// spare elements after the zero pad); otherwise by walking the plan's chain
+// lists.  Separate instances, because the chain-walking code, even when not
+// executed, slows the loop it sits in.
+constexpr int kSlots16 = 2;   // descriptor slots per thread and operand (512 threads)
+
+template <typename T, bool DESC>
+__host__ __device__ constexpr int64_t pitch16(int64_t n) {
+  return row_pitch<T>(DESC ? n + 64 : n);
+}
+
+template <typename T, bool SINGLE, bool DESC>
 __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, int t, uint32_t uhi,
                                                 int64_t k0, int64_t k1, unsigned char* smem) {
+  static_assert(!(SINGLE && DESC), "descriptors need both rows staged");
   constexpr int LB = 13;
   constexpr int E = 16;
   constexpr int NT = 512;
@@ -385,9 +397,9 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   T* rowA = xbuf + XLEN;
   const int64_t pitch1 = SINGLE ? (row_pitch<T>(a.n_rows) > row_pitch<T>(a.n_cols)
                                        ? row_pitch<T>(a.n_rows) : row_pitch<T>(a.n_cols))
-                                : row_pitch<T>(a.n_rows);
+                                : pitch16<T, DESC>(a.n_rows);
   T* rowB = SINGLE ? rowA : rowA + pitch1;
-  uint2* exl = reinterpret_cast<uint2*>(rowB + (SINGLE ? 0 : row_pitch<T>(a.n_cols)) +
+  uint2* exl = reinterpret_cast<uint2*>(rowB + (SINGLE ? 0 : pitch16<T, DESC>(a.n_cols)) +
                                         (SINGLE ? pitch1 : 0));
   if (!SINGLE && threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
 
@@ -425,10 +437,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
   const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
   const uint2* gB = a.planB.pairs + (size_t)t * a.n_cols;
-  // (float32 only: the float64 variant has no registers to spare for them)
-  const bool use_desc = sizeof(T) == 4 && !SINGLE && nchA <= 2 * NT && nchB <= 2 * NT &&
-                        4 * NT <= a.ex_cap;
-  if (ex_lds && !use_desc) {
+  if (!DESC && ex_lds) {
     for (int q = threadIdx.x; q < cntA; q += NT) exl[q] = gA[q];
     for (int q = threadIdx.x; q < cntB; q += NT) exl[cntA + q] = gB[q];
     int32_t* csl = reinterpret_cast<int32_t*>(exl + cntA + cntB);
@@ -441,67 +450,126 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   const uint2* lexB = exl + cntA;
   const int32_t* lcsA = reinterpret_cast<const int32_t*>(exl + cntA + cntB);
   const int32_t* lcsB = lcsA + nchA + 1;
-  // Collision descriptors (the usual case: at most 2 NT chains per operand).
-  // Thread tid owns chains tid and tid + NT of each operand; its descriptor
-  // (8 bytes, in LDS, built once per work unit) holds the chain's target
-  // (the bucket's first row), its next two rows and their signs relative to
-  // the target, as row indices, with the zero pad index n for absent rows
-  // and the target of an absent chain.  Longer chains keep their remaining
-  // rows in the plan's list.  A fix-up per k is then one descriptor load,
-  // three independent row loads and a store, with no branches.
-  uint2* dsc = exl;   // [operand][slot][NT]; replaces the LDS lists
-  auto build_desc = [&](int op, const int32_t* gc, const uint2* gp, int nch, uint32_t pad) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int c = (int)threadIdx.x + j * NT;
-      uint32_t tgt = pad, m1 = pad, m2 = pad, flags = 0;
-      if (c < nch) {
-        const int beg = gc[c], end = gc[c + 1];
-        const uint2 x0 = gp[beg];
-        tgt = x0.x >> 16;
-        m1 = x0.x & 0xFFFFu;
-        flags = (x0.y >> 31) ^ (__popc(uhi & (x0.y & kBucketMask)) & 1u);
-        if (end - beg >= 2) {
-          const uint2 x1 = gp[beg + 1];
-          m2 = x1.x & 0xFFFFu;
-          flags |= ((x1.y >> 31) ^ (__popc(uhi & (x1.y & kBucketMask)) & 1u)) << 1;
-        }
-        if (end - beg > 2) flags |= 4u;
-      }
-      dsc[(op * 2 + j) * NT + threadIdx.x] = make_uint2(tgt | (m1 << 16), m2 | (flags << 16));
-    }
+  // Collision descriptors.  Thread tid owns chains tid + j NT (j < kSlots16);
+  // a descriptor (three words in LDS, built once per work unit) holds the
+  // chain's target and its next five rows as 15-bit row indices with their
+  // signs relative to the target (absent rows: the zero pad index n; an
+  // absent chain targets the lane's spare element after the pad):
+  //   w0 = target | m1 << 15 | s1 << 30 | more << 31
+  //   w1 = m2 | m3 << 15 | s2 << 30 | s3 << 31
+  //   w2 = m4 | m5 << 15 | s4 << 30 | s5 << 31
+  // A chain with more rows (a bucket of seven or more) and chains beyond
+  // the slots are finished from the plan's lists.
+  uint32_t* dsc = reinterpret_cast<uint32_t*>(exl);   // [word][operand][slot][NT]
+  auto dref = [&](int word, int op, int j) -> uint32_t& {
+    return dsc[((word * 2 + op) * kSlots16 + j) * NT + threadIdx.x];
   };
-  if (use_desc) {
-    build_desc(0, gcA, gA, nchA, (uint32_t)a.n_rows);
-    build_desc(1, gcB, gB, nchB, (uint32_t)a.n_cols);
-  }
-  // one operand's fix-ups from its descriptors (rows of k staged)
-  auto fix_desc = [&](T* row, int op, const int32_t* gc, const uint2* gp) {
-    uint2 q[2];
-    T v[2][3];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) q[j] = dsc[(op * 2 + j) * NT + threadIdx.x];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      v[j][0] = row[q[j].x & 0xFFFFu];
-      v[j][1] = row[q[j].x >> 16];
-      v[j][2] = row[q[j].y & 0xFFFFu];
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const uint32_t f = q[j].y >> 16;
-      T acc_ = v[j][0] + flip_sign(v[j][1], f << 31);
-      acc_ = acc_ + flip_sign(v[j][2], (f >> 1) << 31);
-      if (f & 4u) {   // rows beyond the third (rare)
+  if constexpr (DESC) {
+    for (int op = 0; op < 2; ++op) {
+      const int32_t* gc = op ? gcB : gcA;
+      const uint2* gp = op ? gB : gA;
+      const int nch = op ? nchB : nchA;
+      const uint32_t pad = (uint32_t)(op ? a.n_cols : a.n_rows);
+      for (int j = 0; j < kSlots16; ++j) {
         const int c = (int)threadIdx.x + j * NT;
-        const int beg = gc[c], end = gc[c + 1];
-        for (int r = beg + 2; r < end; ++r) {
-          const uint2 y = gp[r];
-          const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
-          acc_ = acc_ + flip_sign(row[y.x & 0xFFFFu], neg << 31);
+        uint32_t m[6] = {pad + 1u + (threadIdx.x & 63u), pad, pad, pad, pad, pad};
+        uint32_t sg[6] = {0, 0, 0, 0, 0, 0};
+        uint32_t more = 0;
+        if (c < nch) {
+          const int beg = gc[c], end = gc[c + 1];
+          m[0] = gp[beg].x >> 16;
+          for (int r = 0; r < 5 && beg + r < end; ++r) {
+            const uint2 y = gp[beg + r];
+            m[r + 1] = y.x & 0xFFFFu;
+            sg[r + 1] = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+          }
+          more = end - beg > 5 ? 1u : 0u;
+        }
+        dref(0, op, j) = m[0] | (m[1] << 15) | (sg[1] << 30) | (more << 31);
+        dref(1, op, j) = m[2] | (m[3] << 15) | (sg[2] << 30) | (sg[3] << 31);
+        dref(2, op, j) = m[4] | (m[5] << 15) | (sg[4] << 30) | (sg[5] << 31);
+      }
+    }
+  }
+  // Fix-ups of both operands from their descriptors, straight-line: every
+  // slot loads its six values, sums them in rank order and stores once.
+  auto fix_desc = [&]() {
+    // float64: one operand after the other (registers); float32: both at once.
+    // A slot with more rows stores its partial sum (in the row's own type,
+    // so no extra rounding) and the rare pass continues from it.
+    constexpr int OPS = sizeof(T) == 8 ? 1 : 2;
+    bool rare = false;
+#pragma unroll
+    for (int o0 = 0; o0 < 2; o0 += OPS) {
+      uint32_t q[OPS][kSlots16][3];
+      T v[OPS][kSlots16][6];
+#pragma unroll
+      for (int oo = 0; oo < OPS; ++oo)
+#pragma unroll
+        for (int j = 0; j < kSlots16; ++j)
+#pragma unroll
+          for (int wd = 0; wd < 3; ++wd) q[oo][j][wd] = dref(wd, o0 + oo, j);
+#pragma unroll
+      for (int oo = 0; oo < OPS; ++oo) {
+        const T* row = (o0 + oo) ? rowB : rowA;
+#pragma unroll
+        for (int j = 0; j < kSlots16; ++j)
+#pragma unroll
+          for (int r = 0; r < 6; ++r)
+            v[oo][j][r] = row[(q[oo][j][r >> 1] >> (15 * (r & 1))) & 0x7FFFu];
+      }
+#pragma unroll
+      for (int oo = 0; oo < OPS; ++oo) {
+        T* row = (o0 + oo) ? rowB : rowA;
+#pragma unroll
+        for (int j = 0; j < kSlots16; ++j) {
+          T acc_ = v[oo][j][0];
+#pragma unroll
+          for (int r = 1; r < 6; ++r) {
+            // sign of member r: w0 bit 30 for r = 1, else bit 30 + (r & 1) of word r / 2
+            const uint32_t word = q[oo][j][r >> 1];
+            const uint32_t neg = (r == 1) ? (word >> 30) & 1u : (word >> (30 + (r & 1))) & 1u;
+            acc_ = acc_ + flip_sign(v[oo][j][r], neg << 31);
+          }
+          rare = rare || (q[oo][j][0] >> 31) != 0u;
+          row[q[oo][j][0] & 0x7FFFu] = acc_;
         }
       }
-      row[q[j].x & 0xFFFFu] = acc_;
+    }
+    const bool extra = nchA > kSlots16 * NT || nchB > kSlots16 * NT;
+    if (rare || extra) {
+#pragma unroll
+      for (int op = 0; op < 2; ++op) {
+        T* row = op ? rowB : rowA;
+        const int32_t* gc = op ? gcB : gcA;
+        const uint2* gp = op ? gB : gA;
+        for (int j = 0; j < kSlots16; ++j) {
+          const uint32_t w0 = dref(0, op, j);
+          if (!(w0 >> 31)) continue;
+          T acc_ = row[w0 & 0x7FFFu];
+          const int c = (int)threadIdx.x + j * NT;
+          const int beg = gc[c], end = gc[c + 1];
+          for (int r = beg + 5; r < end; ++r) {
+            const uint2 y = gp[r];
+            const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+            acc_ = acc_ + flip_sign(row[y.x & 0xFFFFu], neg << 31);
+          }
+          row[w0 & 0x7FFFu] = acc_;
+        }
+        // chains beyond the slots (disjoint targets)
+        const int nch = op ? nchB : nchA;
+        for (int c = kSlots16 * NT + (int)threadIdx.x; c < nch; c += NT) {
+          const int beg = gc[c], end = gc[c + 1];
+          const uint32_t tgt = gp[beg].x >> 16;
+          T acc_ = row[tgt];
+          for (int r = beg; r < end; ++r) {
+            const uint2 y = gp[r];
+            const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+            acc_ = acc_ + flip_sign(row[y.x & 0xFFFFu], neg << 31);
+          }
+          row[tgt] = acc_;
+        }
+      }
     }
   };
   // transpose addresses: thread part (padded) + register part
@@ -529,9 +597,8 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
     if (!SINGLE) stage_row<T, NT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
   };
   auto fixups = [&]() {
-    if (use_desc) {
-      fix_desc(rowA, 0, gcA, gA);
-      fix_desc(rowB, 1, gcB, gB);
+    if constexpr (DESC) {
+      fix_desc();
       return;
     }
     { if (ex_lds) fix_chains<T, NT>(rowA, lexA, lcsA, nchA, uhi); else fix_chains<T, NT>(rowA, gA, gcA, nchA, uhi); }
@@ -592,11 +659,13 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
     __syncthreads();   // Y transposed and the rows of k + 1 have landed
 #pragma unroll
     for (int e = 0; e < E; ++e) Y[e] = xbuf[rd_t + rd_e(e)];
-    // the collision fix-ups of k + 1 run while other waves do pass 2 of k
-    if (more) fixups();
+    // the chain-walking fix-ups of k + 1 run while other waves do pass 2 of
+    // k; the descriptor fix-ups after it, when X and Y are no longer live
+    if (!DESC && more) fixups();
     pass2_16(Y, sgn8);
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = fma(X[e], Y[e], acc[e]);
+    if (DESC && more) fixups();
     if (more) {
       __syncthreads();
       gather();
@@ -621,7 +690,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
 template <typename T>
 constexpr int waves16() { return 2; }
 
-template <typename T, bool SINGLE>
+template <typename T, bool SINGLE, bool DESC>
 __global__ __launch_bounds__(512, waves16<T>()) void compress16_kernel(CompressArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int LB = 13;
@@ -638,7 +707,7 @@ __global__ __launch_bounds__(512, waves16<T>()) void compress16_kernel(CompressA
   const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
   const int64_t k0 = (int64_t)g * k_per;
   const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
-  compress16_unit<T, SINGLE>(a, g, t, uhi, k0, k1, smem);
+  compress16_unit<T, SINGLE, DESC>(a, g, t, uhi, k0, k1, smem);
 }
 
 // The persistent batched form with the 16-element layout (b_lo = 2^13).
@@ -681,7 +750,7 @@ __global__ __launch_bounds__(512, waves16<T>()) void compress16_batched_kernel(
     const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
     const int64_t k0 = (int64_t)bi.group * k_per;
     const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
-    compress16_unit<T, false>(a, (int)bi.group, t, uhi, k0, k1, smem);
+    compress16_unit<T, false, false>(a, (int)bi.group, t, uhi, k0, k1, smem);
   }
 }
 
@@ -751,9 +820,17 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   constexpr int LB = 13;
   const int64_t blocks = ((int64_t)a.d << (a.log2b - LB)) * a.groups;
   const size_t xlen = ((size_t)1 << LB) + ((size_t)1 << (LB - 6)) + 16;
-  size_t base = sizeof(T) * (xlen + (size_t)row_pitch<T>(a.n_rows) +
-                             (size_t)row_pitch<T>(a.n_cols));
   const size_t kMax = 160 * 1024;
+  // descriptor fix-ups when both rows (with their spare elements) and the
+  // descriptors fit; else chain lists, with one time-shared row buffer when
+  // two rows do not fit
+  const size_t desc_lds = sizeof(uint32_t) * 3 * 2 * kSlots16 * 512;
+  const size_t base_desc = sizeof(T) * (xlen + (size_t)pitch16<T, true>(a.n_rows) +
+                                        (size_t)pitch16<T, true>(a.n_cols));
+  const bool desc = base_desc + desc_lds <= kMax && a.n_rows + 64 < 32768 &&
+                    a.n_cols + 64 < 32768;
+  size_t base = desc ? base_desc
+                     : sizeof(T) * (xlen + (size_t)row_pitch<T>(a.n_rows) + (size_t)row_pitch<T>(a.n_cols));
   bool single = false;
   if (base > kMax) {
     const size_t p1 = (size_t)(row_pitch<T>(a.n_rows) > row_pitch<T>(a.n_cols)
@@ -763,13 +840,15 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   }
   if (base > kMax) { set_error("compress: rows do not fit in LDS"); return CMM_EUNSUPPORTED; }
   int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
-  if (cap > a.n_rows + a.n_cols) cap = a.n_rows + a.n_cols;
+  const int64_t want = desc ? (int64_t)(desc_lds / sizeof(uint2)) : a.n_rows + a.n_cols;
+  if (cap > want) cap = want;
   a.ex_cap = cap;
   const size_t lds = base + sizeof(uint2) * (size_t)cap;
   constexpr int V = 16 / sizeof(T);
   a.dma = (a.n_rows % V == 0) && (a.n_cols % V == 0) && (a.ldb % V == 0) &&
           ((uintptr_t)a.At % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
-  auto kern = single ? compress16_kernel<T, true> : compress16_kernel<T, false>;
+  auto kern = single ? compress16_kernel<T, true, false>
+                     : (desc ? compress16_kernel<T, false, true> : compress16_kernel<T, false, false>);
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return hip_check(e, "compress: set LDS size");
