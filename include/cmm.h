@@ -68,6 +68,37 @@ typedef enum { CMM_MEDIAN = 0, CMM_MEAN = 1 } cmm_estimator;
 cmm_status cmm_hash(const uint64_t* keys, int d, int64_t n_rows, int64_t n_cols, int log2b,
                     uint32_t* tab1, uint32_t* tab2, void* stream);
 
+/* Alternative hash families.  Section 4.2 reports results for the
+ * multiply-add-shift family only and names a simpler and a more complex one
+ * that it does not define; this library reads them as:
+ *   CMM_HASH_MULTIPLY_ADD_SHIFT  the Section 4.2 family (same as cmm_hash);
+ *   CMM_HASH_MULTIPLY_SHIFT      h(x) = floor(((a x) mod 2^64) / 2^(64 - log2b))
+ *                                with the low bit of a set (Dietzfelbinger et
+ *                                al.; universal, not 2-wise independent: x = 0
+ *                                is always bucket 0, sign +1);
+ *   CMM_HASH_TABULATION          simple tabulation (Patrascu and Thorup):
+ *                                h(x) = T0[x_0] ^ T1[x_1] ^ T2[x_2] ^ T3[x_3]
+ *                                over the bytes of x (x_0 least significant),
+ *                                log2b top bits of the 64-bit word; the sign
+ *                                is the top bit of the sign function's word.
+ * keys (device):
+ *   multiply families  uint64[d][4][2], (a, c) for h1, h2, s1, s2 (c unused
+ *                      by multiply-shift);
+ *   tabulation         uint64[d][4][4][256]: for h1, h2, s1, s2 the tables
+ *                      T0..T3 of 256 words each.
+ * Tables as for cmm_hash (bucket | sign << 31); they feed every entry point
+ * that takes tab1 / tab2 with keys NULL.  Bit-exact.  An unknown kind is
+ * CMM_EINVAL. */
+typedef enum {
+  CMM_HASH_MULTIPLY_ADD_SHIFT = 0,
+  CMM_HASH_MULTIPLY_SHIFT = 1,
+  CMM_HASH_TABULATION = 2
+} cmm_hash_kind;
+
+cmm_status cmm_hash_family(cmm_hash_kind kind, const uint64_t* keys, int d, int64_t n_rows,
+                           int64_t n_cols, int log2b, uint32_t* tab1, uint32_t* tab2,
+                           void* stream);
+
 /* ---------------------------------------------------------------- sketch */
 /* Algorithm 1, the count-sketch loops of Compress, for kc consecutive values
  * of the inner index starting at k0:
@@ -136,6 +167,38 @@ cmm_status cmm_extract_heavy(const double* p, const uint32_t* tab1, const uint32
                              double threshold, int64_t* out_rows, int64_t* out_cols,
                              void* out_vals, cmm_dtype out_dtype, int64_t capacity,
                              int64_t* count, void* stream);
+
+/* The d single-repetition estimates at a list of entries, before the median
+ * or mean of Decompress (Algorithm 1):
+ *   out[t][q] = s1_t(rows[q]) s2_t(cols[q]) p[t][h1_t(rows[q]) xor h2_t(cols[q])]
+ * Each is unbiased with variance at most ||A B||_F^2 / b over the hash draw
+ * (Section 3.1); the variance experiment of Section 5.3 samples them with
+ * one independent draw per repetition.  rows, cols: device int64[count];
+ * out: device out_dtype[d][count] (CMM_F64 or CMM_F32); NaN for an index
+ * outside [0, n_rows) x [0, n_cols).  Any d in [1, 65535]. */
+cmm_status cmm_extract_reps(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                            int64_t n_rows, int64_t n_cols, int log2b, const int64_t* rows,
+                            const int64_t* cols, int64_t count, void* out, cmm_dtype out_dtype,
+                            void* stream);
+
+/* ------------------------------------------------------ evaluation counters */
+/* The correctness counters of Section 5.4 for one estimate: with B the set
+ * of big entries (big_rows / big_cols, device int64[n_big], distinct; an
+ * entry outside the matrix is skipped) and S every other entry of the
+ * n_rows x n_cols grid,
+ *   counts[0] = #{(i,j) in B : |C_hat[i][j]| >= threshold}
+ *   counts[1] = #{(i,j) in S : |C_hat[i][j]| <= threshold}
+ *   counts[2] = #{(i,j) in B : |C_hat[i][j] - C[i][j]| <= tolerance}
+ *   counts[3] = #{(i,j) in S : |C_hat[i][j] - C[i][j]| <= tolerance}
+ * (the paper uses threshold 0.5 and tolerance 0.1).  C_hat: device
+ * C_hat_dtype (CMM_F64 or CMM_F32), leading dimension ldh; C: the exact
+ * product, device float64, leading dimension ldc.  counts: device int64[4],
+ * overwritten.  A NaN estimate satisfies no condition.  Exact integers. */
+cmm_status cmm_correctness_counts(const void* C_hat, cmm_dtype C_hat_dtype, int64_t ldh,
+                                  const double* C, int64_t ldc, int64_t n_rows, int64_t n_cols,
+                                  const int64_t* big_rows, const int64_t* big_cols, int64_t n_big,
+                                  double threshold, double tolerance, int64_t* counts,
+                                  void* stream);
 
 /* ------------------------------------------------------------- end to end */
 /* One compressed product C_hat ~ A B (Algorithm 1 Compress + dense

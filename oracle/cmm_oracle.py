@@ -56,6 +56,61 @@ def hash_tables(keys: np.ndarray, n_rows: int, n_cols: int, log2b: int):
     return tab1, tab2
 
 
+# Section 4.2 also names a simpler and a more complex family that the paper
+# tried without reporting results.  Their definitions are not given there;
+# the two below are the standard ones (readings, see the package docs).
+def multiply_shift(a: int, x: np.ndarray, out_bits: int) -> np.ndarray:
+    """The simpler family, read as multiply-shift (Dietzfelbinger, Hagerup,
+    Katajainen, Penttonen 1997): the Section 4.2 family without the additive
+    word, h_a(x) = floor(((a x) mod 2^64) / 2^(64 - out_bits)) with a odd
+    (the low bit of the drawn word is set).  Universal, not 2-wise
+    independent: x = 0 always lands in bucket 0 with sign +1."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        v = np.uint64(int(a) | 1) * x
+    return (v >> np.uint64(64 - out_bits)).astype(np.uint64)
+
+
+def tabulation(T: np.ndarray, x: np.ndarray, out_bits: int) -> np.ndarray:
+    """The more complex family, simple tabulation (Patrascu and Thorup 2012):
+    the 32-bit key x is cut into the bytes x_0 (least significant) .. x_3 and
+    h(x) = T[0][x_0] xor T[1][x_1] xor T[2][x_2] xor T[3][x_3] over tables of
+    random 64-bit words; the out_bits top bits of h(x) are the hash value."""
+    x = np.asarray(x, dtype=np.uint64)
+    T = np.asarray(T, dtype=np.uint64)
+    v = np.zeros(x.shape, dtype=np.uint64)
+    for q in range(4):
+        v ^= T[q][((x >> np.uint64(8 * q)) & np.uint64(0xFF)).astype(np.int64)]
+    return (v >> np.uint64(64 - out_bits)).astype(np.uint64)
+
+
+def hash_tables_family(family: str, keys: np.ndarray, n_rows: int, n_cols: int, log2b: int):
+    """hash_tables for a named family: "multiply_add_shift" (Section 4.2;
+    keys uint64[d][4][2]), "multiply_shift" (keys uint64[d][4][2], the second
+    word of each pair unused) or "tabulation" (keys uint64[d][4][4][256]: for
+    h1, h2, s1, s2 the four byte tables).  Same table layout as hash_tables."""
+    if family == "multiply_add_shift":
+        return hash_tables(keys, n_rows, n_cols, log2b)
+    keys = np.asarray(keys, dtype=np.uint64)
+    d = keys.shape[0]
+    xr = np.arange(n_rows, dtype=np.uint64)
+    xc = np.arange(n_cols, dtype=np.uint64)
+    tab1 = np.zeros((d, n_rows), dtype=np.uint32)
+    tab2 = np.zeros((d, n_cols), dtype=np.uint32)
+    for t in range(d):
+        if family == "multiply_shift":
+            f = [lambda x, bits, k=keys[t][q]: multiply_shift(int(k[0]), x, bits) for q in range(4)]
+        elif family == "tabulation":
+            f = [lambda x, bits, k=keys[t][q]: tabulation(k, x, bits) for q in range(4)]
+        else:
+            raise ValueError(f"unknown hash family {family!r}")
+        h1, h2 = f[0](xr, log2b), f[1](xc, log2b)
+        s1, s2 = f[2](xr, 1), f[3](xc, 1)
+        tab1[t] = (h1 | (s1 << np.uint64(31))).astype(np.uint32)
+        tab2[t] = (h2 | (s2 << np.uint64(31))).astype(np.uint32)
+    return tab1, tab2
+
+
 def bucket(tab: np.ndarray) -> np.ndarray:
     """Bucket index of a table entry."""
     return (np.asarray(tab) & np.uint32(0x7FFFFFFF)).astype(np.int64)
@@ -249,6 +304,39 @@ def extract_entries(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, rows, col
         x[t] = sign(tab1[t][r]) * sign(tab2[t][c]) * p[t][bucket(tab1[t][r]) ^ bucket(tab2[t][c])]
     out[ok] = np.median(x, axis=0) if estimator == "median" else x.mean(axis=0)
     return out
+
+
+def extract_reps(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, rows, cols) -> np.ndarray:
+    """The d single-repetition values of Algorithm 1's Decompress at a list
+    of entries, before the median: out[t][q] = s1_t s2_t p[t][h1_t xor h2_t]
+    at (rows[q], cols[q]); NaN for an index outside the tables."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    d = p.shape[0]
+    out = np.full((d, len(rows)), np.nan)
+    ok = (rows >= 0) & (rows < tab1.shape[1]) & (cols >= 0) & (cols < tab2.shape[1])
+    r, c = rows[ok], cols[ok]
+    for t in range(d):
+        out[t, ok] = sign(tab1[t][r]) * sign(tab2[t][c]) * p[t][bucket(tab1[t][r]) ^ bucket(tab2[t][c])]
+    return out
+
+
+def correctness_counts(C_hat: np.ndarray, C: np.ndarray, big_rows, big_cols,
+                       threshold: float = 0.5, tolerance: float = 0.1) -> np.ndarray:
+    """Section 5.4: with B the big entries and S all others,
+    [#B with |c~| >= thr, #S with |c~| <= thr, #B with |c~ - c| <= tol,
+     #S with |c~ - c| <= tol] as int64."""
+    C_hat = np.asarray(C_hat, dtype=np.float64)
+    big = np.zeros(C_hat.shape, dtype=bool)
+    big[np.asarray(big_rows, dtype=np.int64), np.asarray(big_cols, dtype=np.int64)] = True
+    small = ~big
+    mag = np.abs(C_hat)
+    err = np.abs(C_hat - C)
+    with np.errstate(invalid="ignore"):
+        return np.array([np.count_nonzero(big & (mag >= threshold)),
+                         np.count_nonzero(small & (mag <= threshold)),
+                         np.count_nonzero(big & (err <= tolerance)),
+                         np.count_nonzero(small & (err <= tolerance))], dtype=np.int64)
 
 
 def estimate(A: np.ndarray, B: np.ndarray, keys: np.ndarray, log2b: int,

@@ -26,9 +26,13 @@ LIB_PATH = os.path.join(HERE, "libcmm.so")
 CMM_OK, CMM_EINVAL, CMM_ENOMEM, CMM_EHIP, CMM_EUNSUPPORTED = range(5)
 CMM_F64, CMM_F32, CMM_BF16, CMM_F16 = range(4)
 CMM_MEDIAN, CMM_MEAN = range(2)
+CMM_HASH_MULTIPLY_ADD_SHIFT, CMM_HASH_MULTIPLY_SHIFT, CMM_HASH_TABULATION = range(3)
+HASH_FAMILIES = {"multiply_add_shift": CMM_HASH_MULTIPLY_ADD_SHIFT,
+                 "multiply_shift": CMM_HASH_MULTIPLY_SHIFT, "tabulation": CMM_HASH_TABULATION}
 
-EXPORTED = ["cmm_hash", "cmm_sketch", "cmm_fwht", "cmm_accumulate", "cmm_extract",
-            "cmm_extract_entries", "cmm_extract_heavy",
+EXPORTED = ["cmm_hash", "cmm_hash_family", "cmm_sketch", "cmm_fwht", "cmm_accumulate", "cmm_extract",
+            "cmm_extract_entries", "cmm_extract_heavy", "cmm_extract_reps",
+            "cmm_correctness_counts",
             "cmm_workspace_size", "cmm_estimate", "cmm_backward_workspace_size",
             "cmm_estimate_backward", "cmm_batch_create", "cmm_batch_destroy",
             "cmm_batch_workspace_size", "cmm_batch_autotune", "cmm_batch_set_config",
@@ -76,6 +80,7 @@ def lib() -> ctypes.CDLL:
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     sig = {
         "cmm_hash": [vp, i32, i64, i64, i32, vp, vp, vp],
+        "cmm_hash_family": [i32, vp, i32, i64, i64, i32, vp, vp, vp],
         "cmm_sketch": [i32, vp, i32, i64, i64, i64, vp, i32, i32, i64, i64, vp, vp],
         "cmm_fwht": [vp, i32, i64, i32, dbl, vp],
         "cmm_accumulate": [vp, vp, i32, i32, i64, i32, vp, vp],
@@ -83,6 +88,8 @@ def lib() -> ctypes.CDLL:
         "cmm_extract_entries": [vp, vp, vp, i32, i64, i64, i32, i32, vp, vp, i64, vp, i32, vp],
         "cmm_extract_heavy": [vp, vp, vp, i32, i64, i64, i32, i32, dbl, vp, vp, vp, i32, i64, vp,
                               vp],
+        "cmm_extract_reps": [vp, vp, vp, i32, i64, i64, i32, vp, vp, i64, vp, i32, vp],
+        "cmm_correctness_counts": [vp, i32, i64, vp, i64, i64, i64, vp, vp, i64, dbl, dbl, vp, vp],
         "cmm_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
         "cmm_estimate": [ctypes.POINTER(Problem), vp, ctypes.c_size_t, vp],
         "cmm_backward_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
@@ -191,6 +198,26 @@ def cmm_extract_entries(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, rows
         _ptr(cols), rows.numel(), _ptr(out), _dtype_code(out), _stream(stream)))
 
 
+def cmm_extract_reps(p, tab1, tab2, d, n_rows, n_cols, log2b, rows, cols, out,
+                     stream=None) -> None:
+    """out[t][q] = the repetition-t estimate at (rows[q], cols[q]); out is a
+    [d][count] float64 or float32 device tensor."""
+    _check("cmm_extract_reps", lib().cmm_extract_reps(
+        _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, _ptr(rows), _ptr(cols),
+        rows.numel(), _ptr(out), _dtype_code(out), _stream(stream)))
+
+
+def cmm_correctness_counts(C_hat, C, big_rows, big_cols, counts, threshold=0.5, tolerance=0.1,
+                           stream=None) -> None:
+    """Section 5.4 counters into counts (int64 device tensor of 4):
+    [big >= thr, small <= thr, big within tol, small within tol]."""
+    n_rows, n_cols = C_hat.shape
+    _check("cmm_correctness_counts", lib().cmm_correctness_counts(
+        _ptr(C_hat), _dtype_code(C_hat), C_hat.stride(0), _ptr(C), C.stride(0), n_rows, n_cols,
+        _ptr(big_rows), _ptr(big_cols), big_rows.numel(), threshold, tolerance, _ptr(counts),
+        _stream(stream)))
+
+
 def cmm_extract_heavy(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, threshold, out_rows,
                       out_cols, out_vals, count, stream=None) -> None:
     """Entries with |C_hat| >= threshold into the lists (capacity = their length);
@@ -264,6 +291,26 @@ def cmm_profile_query(kernel: str):
 
 # ------------------------------------------------------------ high level
 _COMPUTE = {"f64": CMM_F64, "f32": CMM_F32, "bf16": CMM_BF16, "f16": CMM_F16}
+
+
+def cmm_hash_family(kind, keys, d, n_rows, n_cols, log2b, tab1, tab2, stream=None) -> None:
+    """kind CMM_HASH_*; keys int64 [d][4][2] (multiply families) or [d][4][4][256]
+    (tabulation), uint64 bits; tables as for cmm_hash."""
+    _check("cmm_hash_family", lib().cmm_hash_family(kind, _ptr(keys), d, n_rows, n_cols, log2b,
+                                                    _ptr(tab1), _ptr(tab2), _stream(stream)))
+
+
+def family_tables(family: str, keys: np.ndarray, n_rows: int, n_cols: int, log2b: int,
+                  device="cuda"):
+    """Hash tables (tab1, tab2) on the device for a named family
+    ("multiply_add_shift", "multiply_shift", "tabulation")."""
+    torch = _torch()
+    kd = keys_tensor(keys, device)
+    d = kd.shape[0]
+    tab1 = torch.empty((d, n_rows), dtype=torch.int32, device=device)
+    tab2 = torch.empty((d, n_cols), dtype=torch.int32, device=device)
+    cmm_hash_family(HASH_FAMILIES[family], kd, d, n_rows, n_cols, log2b, tab1, tab2)
+    return tab1, tab2
 
 
 def keys_tensor(keys: np.ndarray, device="cuda"):

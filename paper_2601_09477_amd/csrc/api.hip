@@ -582,6 +582,25 @@ cmm_status cmm_hash(const uint64_t* keys, int d, int64_t n_rows, int64_t n_cols,
   return launch_hash(keys, d, n_rows, n_cols, log2b, tab1, tab2, as_stream(stream));
 }
 
+cmm_status cmm_hash_family(cmm_hash_kind kind, const uint64_t* keys, int d, int64_t n_rows,
+                           int64_t n_cols, int log2b, uint32_t* tab1, uint32_t* tab2,
+                           void* stream) {
+  if (kind != CMM_HASH_MULTIPLY_ADD_SHIFT && kind != CMM_HASH_MULTIPLY_SHIFT &&
+      kind != CMM_HASH_TABULATION)
+    return invalid("cmm_hash_family: unknown hash family");
+  cmm_status s;
+  if ((s = check_d(d, "cmm_hash_family")) != CMM_OK) return s;
+  if ((s = check_log2b(log2b, "cmm_hash_family")) != CMM_OK) return s;
+  if (n_rows < 0 || n_cols < 0) return invalid("cmm_hash_family: negative size");
+  if (n_rows > kMaxHashDomain || n_cols > kMaxHashDomain)
+    return invalid("cmm_hash_family: sizes must be <= 2^32 (hash domain)");
+  if (n_rows == 0 && n_cols == 0) return CMM_OK;
+  if (!keys) return invalid("cmm_hash_family: keys is null");
+  if ((n_rows > 0 && !tab1) || (n_cols > 0 && !tab2))
+    return invalid("cmm_hash_family: table is null");
+  return launch_hash_family(kind, keys, d, n_rows, n_cols, log2b, tab1, tab2, as_stream(stream));
+}
+
 cmm_status cmm_sketch(int side, const void* M, cmm_dtype dtype, int64_t rows, int64_t cols,
                       int64_t ld, const uint32_t* tab, int d, int log2b, int64_t k0, int64_t kc,
                       void* out, void* stream) {
@@ -704,6 +723,41 @@ cmm_status cmm_extract_heavy(const double* p, const uint32_t* tab1, const uint32
   return launch_extract_heavy(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, threshold,
                               out_rows, out_cols, out_vals, out_dtype, capacity, count,
                               as_stream(stream));
+}
+
+cmm_status cmm_extract_reps(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                            int64_t n_rows, int64_t n_cols, int log2b, const int64_t* rows,
+                            const int64_t* cols, int64_t count, void* out, cmm_dtype out_dtype,
+                            void* stream) {
+  // the estimator plays no part: MEAN lets every d through the shared checks
+  cmm_status s = check_decompress(p, tab1, tab2, d, n_rows, n_cols, log2b, CMM_MEAN, out_dtype,
+                                  "cmm_extract_reps");
+  if (s != CMM_OK) return s;
+  if (count < 0) return invalid("cmm_extract_reps: negative count");
+  if (count == 0) return CMM_OK;
+  if (!rows || !cols || !out) return invalid("cmm_extract_reps: null pointer");
+  return launch_extract_reps(p, tab1, tab2, d, n_rows, n_cols, log2b, rows, cols, count, out,
+                             out_dtype, as_stream(stream));
+}
+
+cmm_status cmm_correctness_counts(const void* C_hat, cmm_dtype C_hat_dtype, int64_t ldh,
+                                  const double* C, int64_t ldc, int64_t n_rows, int64_t n_cols,
+                                  const int64_t* big_rows, const int64_t* big_cols, int64_t n_big,
+                                  double threshold, double tolerance, int64_t* counts,
+                                  void* stream) {
+  const char* fn = "cmm_correctness_counts";
+  if (!is_f64_or_f32(C_hat_dtype))
+    return invalid(std::string(fn) + ": C_hat_dtype must be CMM_F64 or CMM_F32");
+  if (n_rows < 0 || n_cols < 0 || n_big < 0) return invalid(std::string(fn) + ": negative size");
+  if (n_rows > 0 && n_cols > 0 && (ldh < n_cols || ldc < n_cols))
+    return invalid(std::string(fn) + ": leading dimension < n_cols");
+  if (!(threshold >= 0.0) || !(tolerance >= 0.0))
+    return invalid(std::string(fn) + ": threshold and tolerance must be >= 0 (not NaN)");
+  if (!counts) return invalid(std::string(fn) + ": counts is null");
+  if (n_rows > 0 && n_cols > 0 && (!C_hat || !C)) return invalid(std::string(fn) + ": null matrix");
+  if (n_big > 0 && (!big_rows || !big_cols)) return invalid(std::string(fn) + ": null big list");
+  return launch_correctness(C_hat, C_hat_dtype, ldh, C, ldc, n_rows, n_cols, big_rows, big_cols,
+                            n_big, threshold, tolerance, counts, as_stream(stream));
 }
 
 cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes) {

@@ -60,6 +60,9 @@ class ProfScope {
 // Every launcher only enqueues work; arguments were validated by the caller.
 cmm_status launch_hash(const uint64_t* keys, int d, int64_t n_rows, int64_t n_cols, int log2b,
                        uint32_t* tab1, uint32_t* tab2, hipStream_t s);
+cmm_status launch_hash_family(cmm_hash_kind kind, const uint64_t* keys, int d, int64_t n_rows,
+                              int64_t n_cols, int log2b, uint32_t* tab1, uint32_t* tab2,
+                              hipStream_t s);
 
 cmm_status launch_sketch(int side, const void* M, cmm_dtype dt, int64_t rows, int64_t cols,
                          int64_t ld, const uint32_t* tab, int d, int log2b, int64_t k0,
@@ -84,6 +87,14 @@ cmm_status launch_extract_heavy(const double* p, const uint32_t* tab1, const uin
                                 double threshold, int64_t* rows, int64_t* cols, void* vals,
                                 cmm_dtype out_dt, int64_t capacity, int64_t* count,
                                 hipStream_t s);
+cmm_status launch_extract_reps(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                               int64_t n_rows, int64_t n_cols, int log2b, const int64_t* rows,
+                               const int64_t* cols, int64_t count, void* out, cmm_dtype out_dt,
+                               hipStream_t s);
+cmm_status launch_correctness(const void* C_hat, cmm_dtype dt, int64_t ldh, const double* C,
+                              int64_t ldc, int64_t n_rows, int64_t n_cols, const int64_t* rows,
+                              const int64_t* cols, int64_t n_big, double thr, double tol,
+                              int64_t* counts, hipStream_t s);
 
 // Fill n doubles with zero (a kernel, not hipMemsetAsync, so that the
 // sequence stays valid under stream capture).

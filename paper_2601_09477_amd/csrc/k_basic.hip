@@ -5,13 +5,17 @@ namespace cmm {
 namespace {
 
 // Section 4.2: v = (a x + c) mod 2^64 (unsigned 64-bit wrap), bucket = the
-// log2b top bits of v; the sign hash keeps the single top bit.
+// log2b top bits of v; the sign hash keeps the single top bit.  With ADD
+// false this is multiply-shift: the additive word is dropped and the
+// multiplier made odd.
+template <bool ADD>
 __global__ void hash_kernel(const uint64_t* __restrict__ keys, int64_t n_rows, int64_t n_cols,
                             int log2b, uint32_t* __restrict__ tab1, uint32_t* __restrict__ tab2) {
   const int t = blockIdx.y;
   const uint64_t* k = keys + 8 * (size_t)t;
-  const uint64_t a1 = k[0], c1 = k[1], a2 = k[2], c2 = k[3];
-  const uint64_t as1 = k[4], cs1 = k[5], as2 = k[6], cs2 = k[7];
+  const uint64_t odd = ADD ? 0 : 1;
+  const uint64_t a1 = k[0] | odd, c1 = ADD ? k[1] : 0, a2 = k[2] | odd, c2 = ADD ? k[3] : 0;
+  const uint64_t as1 = k[4] | odd, cs1 = ADD ? k[5] : 0, as2 = k[6] | odd, cs2 = ADD ? k[7] : 0;
   const int shift = 64 - log2b;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t n = n_rows > n_cols ? n_rows : n_cols;
@@ -27,6 +31,36 @@ __global__ void hash_kernel(const uint64_t* __restrict__ keys, int64_t n_rows, i
       const uint32_t s = (uint32_t)((as2 * ux + cs2) >> 63);
       tab2[(size_t)t * n_cols + x] = h | (s << 31);
     }
+  }
+}
+
+// Simple tabulation (Patrascu and Thorup): the 32-bit index is cut into
+// four bytes and the hash is the xor of one random 64-bit word per byte,
+// from the byte's own table; bucket = the log2b top bits, sign = the top
+// bit of the sign function.  The 16 tables of repetition t (h1, h2, s1, s2
+// x 4 bytes x 256 words = 32 KB) are staged in LDS once per block.
+__global__ __launch_bounds__(256) void hash_tabulation_kernel(
+    const uint64_t* __restrict__ keys, int64_t n_rows, int64_t n_cols, int log2b,
+    uint32_t* __restrict__ tab1, uint32_t* __restrict__ tab2) {
+  __shared__ uint64_t T[4 * 4 * 256];
+  const int t = blockIdx.y;
+  const uint64_t* k = keys + (size_t)t * (4 * 4 * 256);
+  for (int q = threadIdx.x; q < 4 * 4 * 256; q += blockDim.x) T[q] = k[q];
+  __syncthreads();
+  auto h = [&](int f, uint32_t x) -> uint64_t {
+    const uint64_t* Tf = T + f * 1024;
+    return Tf[x & 0xFF] ^ Tf[256 + ((x >> 8) & 0xFF)] ^ Tf[512 + ((x >> 16) & 0xFF)] ^
+           Tf[768 + (x >> 24)];
+  };
+  const int shift = 64 - log2b;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t n = n_rows > n_cols ? n_rows : n_cols;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+    const uint32_t ux = (uint32_t)x;
+    if (x < n_rows)
+      tab1[(size_t)t * n_rows + x] = (uint32_t)(h(0, ux) >> shift) | ((uint32_t)(h(2, ux) >> 63) << 31);
+    if (x < n_cols)
+      tab2[(size_t)t * n_cols + x] = (uint32_t)(h(1, ux) >> shift) | ((uint32_t)(h(3, ux) >> 63) << 31);
   }
 }
 
@@ -81,7 +115,28 @@ cmm_status launch_hash(const uint64_t* keys, int d, int64_t n_rows, int64_t n_co
   ProfScope prof_("hash", s);
   const int64_t n = n_rows > n_cols ? n_rows : n_cols;
   dim3 grid(grid_for((size_t)n, 256, 4096), d);
-  hipLaunchKernelGGL(hash_kernel, grid, dim3(256), 0, s, keys, n_rows, n_cols, log2b, tab1, tab2);
+  hipLaunchKernelGGL(hash_kernel<true>, grid, dim3(256), 0, s, keys, n_rows, n_cols, log2b, tab1,
+                     tab2);
+  return hip_check(hipGetLastError(), "hash kernel launch");
+}
+
+cmm_status launch_hash_family(cmm_hash_kind kind, const uint64_t* keys, int d, int64_t n_rows,
+                              int64_t n_cols, int log2b, uint32_t* tab1, uint32_t* tab2,
+                              hipStream_t s) {
+  if (kind == CMM_HASH_MULTIPLY_ADD_SHIFT)
+    return launch_hash(keys, d, n_rows, n_cols, log2b, tab1, tab2, s);
+  ProfScope prof_("hash", s);
+  const int64_t n = n_rows > n_cols ? n_rows : n_cols;
+  if (kind == CMM_HASH_MULTIPLY_SHIFT) {
+    dim3 grid(grid_for((size_t)n, 256, 4096), d);
+    hipLaunchKernelGGL(hash_kernel<false>, grid, dim3(256), 0, s, keys, n_rows, n_cols, log2b,
+                       tab1, tab2);
+  } else {
+    // each block stages 32 KB of tables: give it a few thousand indices
+    dim3 grid(grid_for((size_t)n, 256 * 8, 1024), d);
+    hipLaunchKernelGGL(hash_tabulation_kernel, grid, dim3(256), 0, s, keys, n_rows, n_cols, log2b,
+                       tab1, tab2);
+  }
   return hip_check(hipGetLastError(), "hash kernel launch");
 }
 

@@ -69,7 +69,8 @@ __global__ __launch_bounds__(kCols) void extract_kernel(
   }
 }
 
-// Generic d (up to kMaxD): candidates in a local array, insertion sort.
+// Generic d: the median (d up to kMaxD) keeps the candidates in a local
+// array, insertion sorted; the mean only sums them.
 constexpr int kMaxD = 63;
 template <typename OutT>
 __global__ __launch_bounds__(kCols) void extract_generic_kernel(
@@ -89,9 +90,11 @@ __global__ __launch_bounds__(kCols) void extract_generic_kernel(
       const double x = p[(size_t)t * b + (e & (uint32_t)(b - 1))];
       const double y = (e & kSignBit) ? -x : x;
       s += y;
-      int q = t;
-      while (q > 0 && v[q - 1] > y) { v[q] = v[q - 1]; --q; }
-      v[q] = y;
+      if (!mean) {   // the median keeps d <= kMaxD candidates; the mean any d
+        int q = t;
+        while (q > 0 && v[q - 1] > y) { v[q] = v[q - 1]; --q; }
+        v[q] = y;
+      }
     }
     C[i * ldc + j] = (OutT)(mean ? s / d : v[d / 2]);
   }
@@ -208,9 +211,11 @@ __global__ __launch_bounds__(kCols) void heavy_generic_kernel(
         const double x = p[(size_t)t * b + (e & (uint32_t)(b - 1))];
         const double y = (e & kSignBit) ? -x : x;
         s += y;
-        int q = t;
-        while (q > 0 && v[q - 1] > y) { v[q] = v[q - 1]; --q; }
-        v[q] = y;
+        if (!mean) {
+          int q = t;
+          while (q > 0 && v[q - 1] > y) { v[q] = v[q - 1]; --q; }
+          v[q] = y;
+        }
       }
       o = mean ? s / d : v[d / 2];
     }
@@ -229,6 +234,92 @@ __global__ __launch_bounds__(kCols) void heavy_generic_kernel(
       }
     }
   }
+}
+
+// Per-repetition estimates at a list of entries: out[t][q] = s1 s2 p_t[h1 ^ h2]
+// for (rows[q], cols[q]); NaN where the index is outside the tables.
+// grid.y walks repetitions in slabs of 65535.
+template <typename OutT>
+__global__ __launch_bounds__(256) void extract_reps_kernel(
+    const double* __restrict__ p, const uint32_t* __restrict__ tab1,
+    const uint32_t* __restrict__ tab2, int d, int64_t n_rows, int64_t n_cols, int log2b,
+    const int64_t* __restrict__ rows, const int64_t* __restrict__ cols, int64_t count,
+    OutT* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= count) return;
+  const int64_t i = rows[q], j = cols[q];
+  const bool ok = i >= 0 && i < n_rows && j >= 0 && j < n_cols;
+  const int64_t b = (int64_t)1 << log2b;
+  for (int t = blockIdx.y; t < d; t += gridDim.y) {
+    double y = __builtin_nan("");
+    if (ok) {
+      const uint32_t e = tab1[(size_t)t * n_rows + i] ^ tab2[(size_t)t * n_cols + j];
+      const double x = p[(size_t)t * b + (e & (uint32_t)(b - 1))];
+      y = (e & kSignBit) ? -x : x;
+    }
+    out[(size_t)t * count + q] = (OutT)y;
+  }
+}
+
+// Correctness counters of the evaluation protocol over the dense grid:
+// c[1] += #{|C_hat| <= thr}, c[3] += #{|C_hat - C| <= tol} (every entry;
+// the big entries are taken out again by correctness_big_kernel).  Counts
+// per wave by ballot, one atomic add per wave and counter (integer adds:
+// the totals do not depend on the order).
+template <typename InT>
+__global__ __launch_bounds__(256) void correctness_dense_kernel(
+    const InT* __restrict__ C_hat, int64_t ldh, const double* __restrict__ C, int64_t ldc,
+    int64_t n_rows, int64_t n_cols, double thr, double tol, unsigned long long* __restrict__ c) {
+  const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  const bool jok = j < n_cols;
+  unsigned long long le = 0, close = 0;
+  for (int64_t i = blockIdx.x; i < n_rows; i += gridDim.x) {
+    bool a = false, bcl = false;
+    if (jok) {
+      const double h = (double)C_hat[i * ldh + j];
+      a = fabs(h) <= thr;
+      bcl = fabs(h - C[i * ldc + j]) <= tol;
+    }
+    le += __popcll(__ballot(a));
+    close += __popcll(__ballot(bcl));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (le) atomicAdd(c + 1, le);
+    if (close) atomicAdd(c + 3, close);
+  }
+}
+
+// The big entries (distinct): c[0] += #{|C_hat| >= thr}, c[2] += #{|C_hat - C|
+// <= tol}, and their share of the dense counts is subtracted from c[1], c[3]
+// (two's-complement adds on the unsigned counters).  An entry outside the
+// matrix is skipped.
+template <typename InT>
+__global__ __launch_bounds__(256) void correctness_big_kernel(
+    const InT* __restrict__ C_hat, int64_t ldh, const double* __restrict__ C, int64_t ldc,
+    int64_t n_rows, int64_t n_cols, const int64_t* __restrict__ rows,
+    const int64_t* __restrict__ cols, int64_t n_big, double thr, double tol,
+    unsigned long long* __restrict__ c) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool ge = false, le = false, close = false;
+  const int64_t i = q < n_big ? rows[q] : -1, j = q < n_big ? cols[q] : -1;
+  if (i >= 0 && i < n_rows && j >= 0 && j < n_cols) {
+    const double h = (double)C_hat[i * ldh + j];
+    ge = fabs(h) >= thr;
+    le = fabs(h) <= thr;
+    close = fabs(h - C[i * ldc + j]) <= tol;
+  }
+  const unsigned long long nge = __popcll(__ballot(ge)), nle = __popcll(__ballot(le)),
+                           ncl = __popcll(__ballot(close));
+  if ((threadIdx.x & 63) == 0) {
+    if (nge) atomicAdd(c + 0, nge);
+    if (ncl) atomicAdd(c + 2, ncl);
+    if (nle) atomicAdd(c + 1, 0ull - nle);
+    if (ncl) atomicAdd(c + 3, 0ull - ncl);
+  }
+}
+
+__global__ void zero_counters_kernel(unsigned long long* c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
 }
 
 __global__ void zero_counter_kernel(unsigned long long* c) { *c = 0ull; }
@@ -344,6 +435,68 @@ cmm_status launch_extract_heavy(const double* p, const uint32_t* tab1, const uin
                              static_cast<double*>(vals), capacity, c, s);
   return heavy_run<float>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, threshold, rows, cols,
                           static_cast<float*>(vals), capacity, c, s);
+}
+
+cmm_status launch_extract_reps(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                               int64_t n_rows, int64_t n_cols, int log2b, const int64_t* rows,
+                               const int64_t* cols, int64_t count, void* out, cmm_dtype out_dt,
+                               hipStream_t s) {
+  ProfScope prof_("extract_reps", s);
+  const int64_t blocks = (count + 255) / 256;
+  if (blocks > 0x7FFFFFFF) {
+    set_error("cmm_extract_reps: count too large");
+    return CMM_EUNSUPPORTED;
+  }
+  dim3 grid((unsigned)blocks, (unsigned)(d < 65535 ? d : 65535));
+  if (out_dt == CMM_F64)
+    hipLaunchKernelGGL(extract_reps_kernel<double>, grid, dim3(256), 0, s, p, tab1, tab2, d, n_rows,
+                       n_cols, log2b, rows, cols, count, static_cast<double*>(out));
+  else
+    hipLaunchKernelGGL(extract_reps_kernel<float>, grid, dim3(256), 0, s, p, tab1, tab2, d, n_rows,
+                       n_cols, log2b, rows, cols, count, static_cast<float*>(out));
+  return hip_check(hipGetLastError(), "extract_reps kernel launch");
+}
+
+template <typename InT>
+static cmm_status correctness_run(const InT* C_hat, int64_t ldh, const double* C, int64_t ldc,
+                                  int64_t n_rows, int64_t n_cols, const int64_t* rows,
+                                  const int64_t* cols, int64_t n_big, double thr, double tol,
+                                  unsigned long long* c, hipStream_t s) {
+  const int64_t gy = (n_cols + 255) / 256;
+  if (gy > 65535 || (n_big + 255) / 256 > 0x7FFFFFFF) {
+    set_error("cmm_correctness_counts: size not supported");
+    return CMM_EUNSUPPORTED;
+  }
+  if (n_rows > 0 && n_cols > 0) {
+    const int64_t gx = n_rows < 2048 ? n_rows : 2048;
+    hipLaunchKernelGGL(correctness_dense_kernel<InT>, dim3((unsigned)gx, (unsigned)gy), dim3(256),
+                       0, s, C_hat, ldh, C, ldc, n_rows, n_cols, thr, tol, c);
+    cmm_status st = hip_check(hipGetLastError(), "correctness kernel launch");
+    if (st != CMM_OK) return st;
+  }
+  if (n_big > 0) {
+    hipLaunchKernelGGL(correctness_big_kernel<InT>, dim3((unsigned)((n_big + 255) / 256)),
+                       dim3(256), 0, s, C_hat, ldh, C, ldc, n_rows, n_cols, rows, cols, n_big, thr,
+                       tol, c);
+    return hip_check(hipGetLastError(), "correctness kernel launch");
+  }
+  return CMM_OK;
+}
+
+cmm_status launch_correctness(const void* C_hat, cmm_dtype dt, int64_t ldh, const double* C,
+                              int64_t ldc, int64_t n_rows, int64_t n_cols, const int64_t* rows,
+                              const int64_t* cols, int64_t n_big, double thr, double tol,
+                              int64_t* counts, hipStream_t s) {
+  ProfScope prof_("correctness", s);
+  unsigned long long* c = reinterpret_cast<unsigned long long*>(counts);
+  hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, s, c, 4);
+  cmm_status st = hip_check(hipGetLastError(), "correctness counter reset");
+  if (st != CMM_OK) return st;
+  if (dt == CMM_F64)
+    return correctness_run<double>(static_cast<const double*>(C_hat), ldh, C, ldc, n_rows, n_cols,
+                                   rows, cols, n_big, thr, tol, c, s);
+  return correctness_run<float>(static_cast<const float*>(C_hat), ldh, C, ldc, n_rows, n_cols,
+                                rows, cols, n_big, thr, tol, c, s);
 }
 
 }  // namespace cmm

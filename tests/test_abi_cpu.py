@@ -54,6 +54,11 @@ def test_problem_struct_layout_matches_header():
     lambda L: L.cmm_hash(None, 3, 4, 4, 31, None, None, None),         # log2b too large
     lambda L: L.cmm_hash(None, 3, 4, 4, 8, None, None, None),          # null keys
     lambda L: L.cmm_hash(1, 3, 1 << 33, 4, 8, 1, 1, None),              # beyond hash domain
+    lambda L: L.cmm_hash_family(3, 1, 3, 4, 4, 8, 1, 1, None),          # unknown family
+    lambda L: L.cmm_hash_family(-1, 1, 3, 4, 4, 8, 1, 1, None),         # unknown family
+    lambda L: L.cmm_hash_family(2, None, 3, 4, 4, 8, 1, 1, None),       # null keys
+    lambda L: L.cmm_hash_family(1, 1, 0, 4, 4, 8, 1, 1, None),          # d = 0
+    lambda L: L.cmm_hash_family(2, 1, 3, 4, 4, 8, 1, None, None),       # null tab2
     lambda L: L.cmm_sketch(2, 1, 0, 4, 4, 4, 1, 1, 8, 0, 1, 1, None),   # bad side
     lambda L: L.cmm_sketch(0, 1, 2, 4, 4, 4, 1, 1, 8, 0, 1, 1, None),   # bf16 not a sketch type
     lambda L: L.cmm_sketch(0, 1, 0, 4, 4, 3, 1, 1, 8, 0, 1, 1, None),   # ld < cols
@@ -72,6 +77,17 @@ def test_problem_struct_layout_matches_header():
     lambda L: L.cmm_extract_heavy(1, 1, 1, 3, 8, 8, 8, 0, 1.0, 1, 1, 1, 0, 4, None, None),  # count
     lambda L: L.cmm_extract_heavy(1, 1, 1, 3, 8, 8, 8, 0, 1.0, None, 1, 1, 0, 4, 1, None),  # list
     lambda L: L.cmm_extract_heavy(1, 1, 1, 3, 8, 8, 8, 0, 1.0, 1, 1, 1, 2, 4, 1, None),  # bf16 out
+    lambda L: L.cmm_extract_reps(1, 1, 1, 0, 8, 8, 8, 1, 1, 4, 1, 0, None),       # d = 0
+    lambda L: L.cmm_extract_reps(1, 1, 1, 4, 8, 8, 8, None, 1, 4, 1, 0, None),    # rows null
+    lambda L: L.cmm_extract_reps(1, 1, 1, 4, 8, 8, 8, 1, 1, -2, 1, 0, None),      # count < 0
+    lambda L: L.cmm_extract_reps(1, 1, 1, 4, 8, 8, 8, 1, 1, 4, 1, 3, None),       # f16 out
+    lambda L: L.cmm_correctness_counts(1, 2, 8, 1, 8, 8, 8, 1, 1, 1, 0.5, 0.1, 1, None),  # bf16
+    lambda L: L.cmm_correctness_counts(1, 0, 7, 1, 8, 8, 8, 1, 1, 1, 0.5, 0.1, 1, None),  # ldh
+    lambda L: L.cmm_correctness_counts(1, 0, 8, 1, 8, 8, 8, 1, 1, 1, -1.0, 0.1, 1, None),  # thr
+    lambda L: L.cmm_correctness_counts(1, 0, 8, 1, 8, 8, 8, 1, 1, 1, 0.5, float("nan"), 1,
+                                       None),                                       # tol NaN
+    lambda L: L.cmm_correctness_counts(1, 0, 8, 1, 8, 8, 8, 1, 1, 1, 0.5, 0.1, None, None),  # counts
+    lambda L: L.cmm_correctness_counts(1, 0, 8, 1, 8, 8, 8, None, 1, 1, 0.5, 0.1, 1, None),  # big
 ])
 def test_invalid_arguments_rejected_on_host(call):
     L = _lib_or_skip()

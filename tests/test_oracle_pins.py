@@ -9,7 +9,8 @@ import pytest
 import scipy.linalg
 
 import oracle as O
-from workloads import draw_keys, exact_sparse_256, hadamard_sparse, small_random
+from workloads import (draw_keys, draw_tabulation_keys, exact_sparse_256, hadamard_sparse,
+                       small_random)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -95,6 +96,112 @@ def test_hash_uniformity_chi_square():
     assert chi2 < 255 + 6 * np.sqrt(2 * 255)   # mean dof, +6 sd
     signs = O.sign(t1[0])
     assert abs(signs.mean()) < 0.02
+
+
+# ------------------------------------------------- alternative hash families
+@pytest.mark.parametrize("m", [1, 5, 13, 16, 31])
+def test_multiply_shift_special_cases(m):
+    x = np.arange(0, 70000, 13, dtype=np.uint64)
+    # a = 2^(64-m) + 1 (odd): a x = x 2^(64-m) + x, whose top m bits are x mod 2^m
+    assert np.array_equal(O.multiply_shift((1 << (64 - m)) + 1, x, m), x % (1 << m))
+    # the drawn word's low bit is forced to one: 2^(64-m) behaves as 2^(64-m) + 1
+    assert np.array_equal(O.multiply_shift(1 << (64 - m), x, m), x % (1 << m))
+    # no additive term: x = 0 always hashes to 0
+    assert O.multiply_shift(0x9E3779B97F4A7C15, np.zeros(1, np.uint64), m)[0] == 0
+    # a = 2^64 - 1: (-x mod 2^64) >> (64 - m) = 2^m - 1 for 1 <= x < 2^(64-m)
+    assert np.all(O.multiply_shift((1 << 64) - 1, x[1:], m) == (1 << m) - 1)
+
+
+@pytest.mark.slow
+def test_multiply_shift_universal():
+    # Dietzfelbinger et al.: two distinct keys collide with probability at
+    # most 2 / b over the odd multipliers
+    log2b, draws = 6, 4000
+    keys = draw_keys(draws, 777)
+    hits = np.zeros(3)
+    pairs = [(1, 2), (3, 1000), (12345, 54321)]
+    for s in range(draws):
+        h = O.multiply_shift(int(keys[s, 0, 0]), np.array([1, 2, 3, 1000, 12345, 54321], np.uint64),
+                             log2b)
+        hits += [h[0] == h[1], h[2] == h[3], h[4] == h[5]]
+    rate = hits / draws
+    bound = 2 / (1 << log2b)
+    assert np.all(rate <= bound + 4 * np.sqrt(bound * (1 - bound) / draws)), rate
+
+
+def test_tabulation_byte_order_closed_form():
+    # T[q][v] = v << (56 - 8 q) puts byte q of x into bits [56 - 8q, 64 - 8q):
+    # the 32 top bits of h(x) are x with its bytes reversed
+    T = np.array([[v << (56 - 8 * q) for v in range(256)] for q in range(4)], dtype=np.uint64)
+    x = np.array([0, 1, 0xFF, 0x100, 0x12345678, 0xDEADBEEF, 0xFFFFFFFF], dtype=np.uint64)
+    bswap = [int.from_bytes(int(v).to_bytes(4, "little"), "big") for v in x]
+    assert O.tabulation(T, x, 32).tolist() == bswap
+    # with one output bit the hash is bit 63 of the word: bit 7 of byte 0 of x
+    assert O.tabulation(T, x, 1).tolist() == [(int(v) >> 7) & 1 for v in x]
+
+
+def test_tabulation_xor_structure():
+    # h is an xor of per-byte table words: for keys that differ crosswise in
+    # two byte positions (a rectangle), the four full 64-bit hashes xor to 0,
+    # while a key pair that differs in one byte changes h by the xor of the
+    # two table words of that byte
+    T = draw_tabulation_keys(1, 31)[0, 0]
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        base = int(rng.integers(0, 1 << 32))
+        q1, q2 = rng.choice(4, 2, replace=False)
+        v1, v2 = rng.integers(0, 256, 2)
+
+        def put(x, q, v):
+            return (x & ~(0xFF << (8 * q))) | (int(v) << (8 * q))
+        xs = np.array([base, put(base, q1, v1), put(base, q2, v2), put(put(base, q1, v1), q2, v2)],
+                      dtype=np.uint64)
+        h = O.tabulation(T, xs, 64)
+        assert h[0] ^ h[1] ^ h[2] ^ h[3] == 0
+        b0 = (base >> (8 * q1)) & 0xFF
+        assert h[0] ^ h[1] == T[q1][b0] ^ T[q1][int(v1)]
+
+
+def test_tabulation_uniform_and_pairwise():
+    log2b = 8
+    keys = draw_tabulation_keys(1, 4242)
+    t1, _ = O.hash_tables_family("tabulation", keys, 1 << 16, 1, log2b)
+    counts = np.bincount(O.bucket(t1[0]), minlength=1 << log2b)
+    expected = (1 << 16) / (1 << log2b)
+    chi2 = ((counts - expected) ** 2 / expected).sum()
+    assert chi2 < 255 + 6 * np.sqrt(2 * 255)
+    assert abs(O.sign(t1[0]).mean()) < 0.02
+    # collisions of a fixed pair of keys over independent tables: rate 1 / b
+    draws, b = 3000, 1 << 6
+    keys = draw_tabulation_keys(draws, 99)
+    hits = sum(O.tabulation(keys[s, 0], np.array([7, 70000], np.uint64), 6).tolist()[0] ==
+               O.tabulation(keys[s, 0], np.array([7, 70000], np.uint64), 6).tolist()[1]
+               for s in range(draws))
+    assert abs(hits / draws - 1 / b) < 4 * np.sqrt((1 / b) * (1 - 1 / b) / draws)
+
+
+def test_family_tables_layout():
+    # which drawn function feeds which field: zero bucket tables and a sign
+    # table that is all ones give bucket 0 and sign -1 for every index
+    keys = np.zeros((2, 4, 4, 256), dtype=np.uint64)
+    keys[:, 2] = np.uint64(1 << 63)          # s1: top bit set for every byte value
+    keys[:, 2, 1:] = 0                       # ... from byte 0 only (odd count of set words)
+    keys[1, 1, 0, :] = np.arange(256, dtype=np.uint64) << np.uint64(56)   # h2 of t = 1
+    t1, t2 = O.hash_tables_family("tabulation", keys, 40, 300, 8)
+    assert np.all(t1 == np.uint32(1 << 31))
+    assert np.all(t2[0] == 0)
+    assert np.array_equal(t2[1], (np.arange(300) & 0xFF).astype(np.uint32))
+    # the multiply-add-shift entry is the Section 4.2 table builder
+    k = draw_keys(3, 8)
+    for a, b in zip(O.hash_tables_family("multiply_add_shift", k, 50, 60, 11),
+                    O.hash_tables(k, 50, 60, 11)):
+        assert np.array_equal(a, b)
+    # multiply-shift reads the first word of each pair only
+    k2 = k.copy()
+    k2[:, :, 1] = 0
+    for a, b in zip(O.hash_tables_family("multiply_shift", k, 50, 60, 11),
+                    O.hash_tables_family("multiply_shift", k2, 50, 60, 11)):
+        assert np.array_equal(a, b)
 
 
 # ------------------------------------------------------------------ transform

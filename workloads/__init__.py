@@ -49,6 +49,33 @@ def draw_keys(d: int, key_seed: int) -> np.ndarray:
     return np.array(words, dtype=np.uint64).reshape(d, 4, 2)
 
 
+def splitmix64_array(seed: int, count: int) -> np.ndarray:
+    """splitmix64_stream as a uint64 array, computed without a Python loop:
+    output i mixes the state seed + (i + 1) * 0x9E3779B97F4A7C15 (mod 2^64)."""
+    i = np.arange(1, count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & MASK64) + i * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def draw_tabulation_keys(d: int, key_seed: int) -> np.ndarray:
+    """Simple-tabulation tables as uint64[d][4][4][256]: per repetition, for
+    h1, h2, s1, s2, four tables of 256 random words (one per key byte)."""
+    return splitmix64_array(key_seed, d * 4 * 4 * 256).reshape(d, 4, 4, 256)
+
+
+def draw_family_keys(family: str, d: int, key_seed: int) -> np.ndarray:
+    """Keys for a hash family: uint64[d][4][2] for the multiply families,
+    uint64[d][4][4][256] for simple tabulation."""
+    if family in ("multiply_add_shift", "multiply_shift"):
+        return draw_keys(d, key_seed)
+    if family == "tabulation":
+        return draw_tabulation_keys(d, key_seed)
+    raise ValueError(f"unknown hash family {family!r}")
+
+
 def sylvester(n: int) -> np.ndarray:
     """Sylvester-ordered +-1 Hadamard matrix of order n (power of two).
 
