@@ -328,6 +328,93 @@ def differentiation_form(steps: int, warmup: int) -> dict:
                                  "frac": adj_ops / avg_a / PEAK_F32_ADD}}
 
 
+def evaluation_protocol(n_var: int = 1024, draws: int = 1000, n_corr: int = 8192,
+                        instances: int = 10, c_d: float = 1.0, c_b: float = 16.0) -> dict:
+    """The paper's evaluation protocol on the GPU (Sections 5.2-5.4).
+
+    Variance experiment: per instance family, one instance at n = n_var and
+    `draws` independent hash draws (repetition t of one estimate is draw t),
+    the single-repetition estimates of the first big entry for several b:
+    sample mean and variance against Pagh's bound ||C||_F^2 / b; COVARIANCE
+    also under the other two hash families.  Correctness experiment: per
+    family `instances` instances at n = n_corr (each with its own hash draw),
+    d and b from Section 5.6 with (c_d, c_b), the four counters of Section
+    5.4 against the exact product (a float64 GEMM), reported as the columns
+    of the paper's correctness table.  Instances are generated on the GPU."""
+    import math
+
+    import torch
+
+    import paper_2601_09477_amd as cmm
+    from workloads import draw_family_keys, draw_keys
+    from workloads import instances as I
+    dev = torch.device("cuda:0")
+    t_start = time.perf_counter()
+    var_rows = []
+    for fam in I.FAMILIES:
+        w = I.instance(fam, n_var, 100, dev)
+        C = w.A @ w.B
+        i, j = int(w.big_rows[0]), int(w.big_cols[0])
+        cij = float(C[i, j])
+        fro2 = float((C * C).sum()) - cij * cij
+        ri = torch.tensor([i], dtype=torch.int64, device=dev)
+        ci = torch.tensor([j], dtype=torch.int64, device=dev)
+        hashes = ["multiply_add_shift"] + (["multiply_shift", "tabulation"]
+                                           if fam == "covariance" else [])
+        for h in hashes:
+            for log2b in (10, 12, 14, 16):
+                keys = draw_family_keys(h, draws, 31337 + log2b)
+                tab1, tab2 = cmm.family_tables(h, keys, n_var, n_var, log2b, dev)
+                res = cmm.estimate(w.A, w.B, draws, log2b, tab1=tab1, tab2=tab2,
+                                   estimator="mean", dense=False)
+                x = torch.empty((draws, 1), dtype=torch.float64, device=dev)
+                cmm.cmm_extract_reps(res.p, tab1, tab2, draws, n_var, n_var, log2b, ri, ci, x)
+                xs = x[:, 0].double()
+                var = float(xs.var(unbiased=True))
+                var_rows.append({"instance": fam, "hash": h, "log2b": log2b, "c": cij,
+                                 "mean": float(xs.mean()), "var": var,
+                                 "bound": fro2 / (1 << log2b),
+                                 "var_over_bound": var / (fro2 / (1 << log2b))})
+        del w, C
+    t_var = time.perf_counter() - t_start
+    print(f"[bench] variance experiment {t_var:.1f} s", file=sys.stderr, flush=True)
+
+    d, log2b = I.params(n_corr, c_d, c_b)
+    corr = {}
+    t1 = time.perf_counter()
+    for fam in I.FAMILIES:
+        fr = {"all_eps": 0.0, "big_eps": 0.0, "big_ge": 0.0, "small_le": 0.0}
+        est_ms = 0.0
+        for r in range(instances):
+            w = I.instance(fam, n_corr, 1000 + r, dev)
+            C = w.A @ w.B
+            keys = draw_keys(d, 5000 + 97 * r + I.FAMILIES.index(fam))
+            torch.cuda.synchronize()
+            e0 = time.perf_counter()
+            res = cmm.estimate(w.A, w.B, d, log2b, keys=keys)
+            torch.cuda.synchronize()
+            est_ms += (time.perf_counter() - e0) * 1e3
+            counts = torch.empty(4, dtype=torch.int64, device=dev)
+            cmm.cmm_correctness_counts(res.C_hat, C, w.big_rows.to(torch.int64),
+                                       w.big_cols.to(torch.int64), counts, 0.5, 0.1)
+            bge, sle, beps, seps = (int(v) for v in counts.cpu())
+            nb = int(w.big_rows.numel())
+            ns = n_corr * n_corr - nb
+            fr["all_eps"] += (beps + seps) / (n_corr * n_corr) / instances
+            fr["big_eps"] += beps / nb / instances
+            fr["big_ge"] += bge / nb / instances
+            fr["small_le"] += sle / ns / instances
+            del w, C, res
+        fr["ms_per_estimate"] = est_ms / instances
+        corr[fam] = fr
+        print(f"[bench] correctness {fam} done", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    return {"variance": {"n": n_var, "draws": draws, "rows": var_rows, "seconds": t_var},
+            "correctness": {"n": n_corr, "instances": instances, "d": d, "b": 1 << log2b,
+                            "c_d": c_d, "c_b": c_b, "threshold": 0.5, "tolerance": 0.1,
+                            "families": corr, "seconds": time.perf_counter() - t1}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +423,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form leg")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-eval", action="store_true",
+                    help="skip the evaluation protocol (variance and correctness experiments)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain elementwise copy of MIB MiB (read MIB, write "
                          "MIB): the reference dispatch for hardware byte counters")
@@ -389,6 +478,8 @@ def main() -> int:
         out["mfma_form"] = precision_form(max(3, args.steps // 4), 1)
         out["batched_form"] = batched_form(max(3, args.steps // 4), 1)
         out["differentiation_form"] = differentiation_form(max(3, args.steps // 2), 2)
+    if not args.no_eval and not args.no_forms:
+        out["evaluation"] = evaluation_protocol()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))
