@@ -306,6 +306,72 @@ def extract_entries(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, rows, col
     return out
 
 
+# ------------------------------------------------ Pagh's FFT form (Section 3.1)
+def cyclic_convolution(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Section 2: (x * y)[k] = sum over i + j = k (mod b) of x[i] y[j], by the
+    definition (O(b^2); for checks on small b)."""
+    b = len(x)
+    out = np.zeros(b)
+    for i in range(b):
+        for j in range(b):
+            out[(i + j) % b] += x[i] * y[j]
+    return out
+
+
+def compress_fft(A: np.ndarray, B: np.ndarray, tab1: np.ndarray, tab2: np.ndarray,
+                 log2b: int, k_chunk: int = 256) -> np.ndarray:
+    """Pagh's Compress (Section 3.1): per repetition, count-sketch column k
+    of A and row k of B, take their discrete Fourier transforms, add the
+    pointwise product; finally p[t] = inverse transform, which is the cyclic
+    convolution p_A * p_B summed over k.  The transform is numpy.fft (a
+    library step).  Returns p float64[d][b] (the real part)."""
+    d = tab1.shape[0]
+    n_inner = A.shape[1]
+    b = 1 << log2b
+    P = np.zeros((d, b), dtype=np.complex128)
+    for k0 in range(0, n_inner, k_chunk):
+        kc = min(k_chunk, n_inner - k0)
+        X = np.fft.fft(count_sketch(A, tab1, 0, k0, kc, log2b), axis=-1)
+        Y = np.fft.fft(count_sketch(B, tab2, 1, k0, kc, log2b), axis=-1)
+        P += (X * Y).sum(axis=1)
+    return np.fft.ifft(P, axis=-1).real
+
+
+def bucket_sums_cyclic(C: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, log2b: int,
+                       row_block: int = 512) -> np.ndarray:
+    """The plain definition Pagh's Compress reaches: p_t[x] = sum over
+    (i, j) with h1(i) + h2(j) = x (mod b) of s1(i) s2(j) C[i, j]
+    (Section 3.1: h(i, j) = h1(i) + h2(j) mod b, s(i, j) = s1(i) s2(j))."""
+    d = tab1.shape[0]
+    b = 1 << log2b
+    n_rows = C.shape[0]
+    p = np.zeros((d, b))
+    for t in range(d):
+        h1, s1 = bucket(tab1[t]), sign(tab1[t])
+        h2, s2 = bucket(tab2[t]), sign(tab2[t])
+        for r0 in range(0, n_rows, row_block):
+            r1 = min(n_rows, r0 + row_block)
+            idx = ((h1[r0:r1, None] + h2[None, :]) % b).ravel()
+            w = (s1[r0:r1, None] * s2[None, :] * C[r0:r1]).ravel()
+            p[t] += np.bincount(idx, weights=w, minlength=b)
+    return p
+
+
+def extract_cyclic(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray,
+                   estimator: str = "median") -> np.ndarray:
+    """Pagh's Decompress: Median_t s1_t(i) s2_t(j) p[t][(h1_t(i) + h2_t(j)) mod b]
+    (or the mean) for every (i, j)."""
+    d, b = p.shape
+    if estimator == "median" and d % 2 == 0:
+        raise ValueError("median estimator needs an odd number of repetitions")
+    x = np.empty((d, tab1.shape[1], tab2.shape[1]))
+    for t in range(d):
+        h1, s1 = bucket(tab1[t]), sign(tab1[t])
+        h2, s2 = bucket(tab2[t]), sign(tab2[t])
+        x[t] = s1[:, None] * s2[None, :] * p[t][(h1[:, None] + h2[None, :]) % b]
+    return np.median(x, axis=0) if estimator == "median" else x.mean(axis=0)
+
+
 def extract_reps(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, rows, cols) -> np.ndarray:
     """The d single-repetition values of Algorithm 1's Decompress at a list
     of entries, before the median: out[t][q] = s1_t s2_t p[t][h1_t xor h2_t]
