@@ -327,6 +327,59 @@ def differentiation_form(steps: int, warmup: int) -> dict:
                                  "frac": adj_ops / avg_a / PEAK_F32_ADD}}
 
 
+def fft_form(steps: int, warmup: int, seed: int = 0) -> dict:
+    """Pagh's FFT form (Section 3.1) on the headline workload (planted +-1,
+    n = 4096, b = 2^16, d = 9): the same timed region as the headline
+    (hash + compress + inverse + dense extract) through cmm_estimate_fft.
+    The paper compares the two transforms on one machine (its SU3 column);
+    fwht_speedup is this form's time over the FWHT form's."""
+    import torch
+
+    import paper_2601_09477_amd as cmm
+    from workloads import planted_4096
+    from workloads.metrics import planted_recall
+    w = planted_4096(seed)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    B = torch.from_numpy(w.B).to(dev)
+    keys = cmm.keys_tensor(w.keys, dev)
+    d, log2b, n = w.d, w.log2b, w.n
+    tab1 = torch.empty((d, n), dtype=torch.int32, device=dev)
+    tab2 = torch.empty((d, n), dtype=torch.int32, device=dev)
+    p = torch.empty((d, 1 << log2b), dtype=torch.float64, device=dev)
+    C_hat = torch.empty((n, n), dtype=torch.float64, device=dev)
+    pr = cmm.make_problem(A, B, d, log2b, keys=keys, tab1=tab1, tab2=tab2, p=p, C_hat=C_hat,
+                          compute="f64", estimator="median")
+    nbytes = cmm.cmm_fft_workspace_size(pr)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        cmm.cmm_estimate_fft(pr, ws, nbytes, stream)
+    torch.cuda.synchronize()
+    cmm.cmm_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cmm.cmm_estimate_fft(pr, ws, nbytes, stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    kern = {k: cmm.cmm_profile_query(k) for k in
+            ("hash", "sketch", "fft", "accumulate", "compress", "extract")}
+    cmm.cmm_profile_enable(False)
+    rec = planted_recall(C_hat.cpu().numpy(), w.rows, w.cols, w.tau)
+    b = 1 << log2b
+    # complex transforms: one per (t, k) of length b plus d inverses, at
+    # 5 b log2 b flops each (the usual count for a radix-2 transform)
+    flops = 5.0 * b * log2b * (d * n + d)
+    fft_ms = kern["fft"][0] / steps
+    return {"workload": "planted +-1, n=4096, b=2^16, d=9 (the headline), h = h1 + h2 mod b",
+            "ms_per_step": ms, "value": 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
+            "unit": "TFLOP/s-equivalent (2n^3/s)",
+            "kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
+            "transform_rate_TFLOPs": flops / (fft_ms * 1e-3) / 1e12 if fft_ms > 0 else None,
+            "recall": {"planted": rec["planted"], "recalled": rec["recalled"]},
+            "workspace_bytes": nbytes}
+
+
 def evaluation_protocol(n_var: int = 1024, draws: int = 1000, n_corr: int = 8192,
                         instances: int = 10, c_d: float = 1.0, c_b: float = 16.0) -> dict:
     """The paper's evaluation protocol on the GPU (Sections 5.2-5.4).
@@ -477,6 +530,8 @@ def main() -> int:
         out["mfma_form"] = precision_form(max(3, args.steps // 4), 1)
         out["batched_form"] = batched_form(max(3, args.steps // 4), 1)
         out["differentiation_form"] = differentiation_form(max(3, args.steps // 2), 2)
+        out["fft_form"] = fft_form(max(2, args.steps // 10), 1, args.seed)
+        out["fft_form"]["fwht_speedup"] = out["fft_form"]["ms_per_step"] / ms_per_step
     if not args.no_eval and not args.no_forms:
         out["evaluation"] = evaluation_protocol()
     if not args.no_cpu:

@@ -200,6 +200,26 @@ cmm_status cmm_correctness_counts(const void* C_hat, cmm_dtype C_hat_dtype, int6
                                   double threshold, double tolerance, int64_t* counts,
                                   void* stream);
 
+/* ------------------------------------------------------ Pagh's FFT form */
+/* Section 3.1: Pagh's original Compress sketches with h(i, j) = h1(i) + h2(j)
+ * mod b and takes the cyclic convolution p_A * p_B through the discrete
+ * Fourier transform; the FWHT form of Section 3.2 replaces both.  This form
+ * is here to compare the two transforms on the same GPU.
+ *
+ * cmm_fft: batched complex float64 DFT of `batch` vectors of length
+ * 2^log2n (1 <= log2n <= 24), interleaved (re, im), natural order:
+ *   out[v][k] = scale * sum_n in[v][n] exp(-+ 2 pi i n k / 2^log2n)
+ * (minus for inverse = 0, plus for inverse = 1).  in and out are device
+ * buffers; they may be the same buffer only when log2n <= 12. */
+cmm_status cmm_fft(const void* in, void* out, int64_t batch, int log2n, int inverse, double scale,
+                   void* stream);
+
+/* Decompress for the FFT form: C_hat[i][j] = Median_t s1 s2 p[t][(h1_t(i) +
+ * h2_t(j)) mod b] (or the mean).  Arguments as for cmm_extract. */
+cmm_status cmm_extract_cyclic(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                              int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
+                              void* C_hat, cmm_dtype out_dtype, int64_t ldc, void* stream);
+
 /* ------------------------------------------------------------- end to end */
 /* One compressed product C_hat ~ A B (Algorithm 1 Compress + dense
  * Decompress).
@@ -241,6 +261,16 @@ typedef struct {
 cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes);
 cmm_status cmm_estimate(const cmm_problem* prob, void* workspace, size_t workspace_bytes,
                         void* stream);
+
+/* Pagh's FFT form end to end (Section 3.1): the same problem description,
+ * float64 only (compute and in_dtype CMM_F64, else CMM_EUNSUPPORTED); p
+ * receives the cyclic sketch and C_hat the cyclic Decompress.  Composed of
+ * count sketches, one complex transform per (t, k) of p_A + i p_B, the
+ * products accumulated in the transform domain, and one inverse transform
+ * per repetition.  Workspace from cmm_fft_workspace_size. */
+cmm_status cmm_fft_workspace_size(const cmm_problem* prob, size_t* bytes);
+cmm_status cmm_estimate_fft(const cmm_problem* prob, void* workspace, size_t workspace_bytes,
+                            void* stream);
 
 /* ---------------------------------------------------------- batched form */
 /* Many independent problems (Algorithm 1 each, uneven sizes) with all their
@@ -316,7 +346,8 @@ cmm_status cmm_estimate_backward(const cmm_problem* prob, const void* W, int64_t
  * cmm_profile_query returns the summed elapsed time and the number of
  * launches of one kernel ("hash", "transpose", "plan", "compress",
  * "reduce", "fwht", "extract", "sketch", "accumulate", "wscatter",
- * "adjoint", "adjoint_reduce", "extract_entries", "extract_heavy") since the last
+ * "adjoint", "adjoint_reduce", "extract_entries", "extract_heavy",
+ * "extract_reps", "correctness", "fft") since the last
  * cmm_profile_enable call.  Enabling or disabling discards the records.
  * query waits for the recorded events.  Off by default. */
 void cmm_profile_enable(int on);

@@ -32,7 +32,8 @@ HASH_FAMILIES = {"multiply_add_shift": CMM_HASH_MULTIPLY_ADD_SHIFT,
 
 EXPORTED = ["cmm_hash", "cmm_hash_family", "cmm_sketch", "cmm_fwht", "cmm_accumulate", "cmm_extract",
             "cmm_extract_entries", "cmm_extract_heavy", "cmm_extract_reps",
-            "cmm_correctness_counts",
+            "cmm_correctness_counts", "cmm_fft", "cmm_extract_cyclic", "cmm_fft_workspace_size",
+            "cmm_estimate_fft",
             "cmm_workspace_size", "cmm_estimate", "cmm_backward_workspace_size",
             "cmm_estimate_backward", "cmm_batch_create", "cmm_batch_destroy",
             "cmm_batch_workspace_size", "cmm_batch_autotune", "cmm_batch_set_config",
@@ -89,6 +90,10 @@ def lib() -> ctypes.CDLL:
         "cmm_extract_heavy": [vp, vp, vp, i32, i64, i64, i32, i32, dbl, vp, vp, vp, i32, i64, vp,
                               vp],
         "cmm_extract_reps": [vp, vp, vp, i32, i64, i64, i32, vp, vp, i64, vp, i32, vp],
+        "cmm_fft": [vp, vp, i64, i32, i32, dbl, vp],
+        "cmm_extract_cyclic": [vp, vp, vp, i32, i64, i64, i32, i32, vp, i32, i64, vp],
+        "cmm_fft_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
+        "cmm_estimate_fft": [ctypes.POINTER(Problem), vp, ctypes.c_size_t, vp],
         "cmm_correctness_counts": [vp, i32, i64, vp, i64, i64, i64, vp, vp, i64, dbl, dbl, vp, vp],
         "cmm_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
         "cmm_estimate": [ctypes.POINTER(Problem), vp, ctypes.c_size_t, vp],
@@ -259,6 +264,58 @@ def cmm_workspace_size(prob: Problem) -> int:
 def cmm_estimate(prob: Problem, workspace, workspace_bytes: int, stream=None) -> None:
     _check("cmm_estimate", lib().cmm_estimate(ctypes.byref(prob), _ptr(workspace),
                                               workspace_bytes, _stream(stream)))
+
+
+def cmm_fft_workspace_size(prob: Problem) -> int:
+    n = ctypes.c_size_t(0)
+    _check("cmm_fft_workspace_size",
+           lib().cmm_fft_workspace_size(ctypes.byref(prob), ctypes.byref(n)))
+    return n.value
+
+
+def cmm_estimate_fft(prob: Problem, workspace, workspace_bytes: int, stream=None) -> None:
+    _check("cmm_estimate_fft", lib().cmm_estimate_fft(ctypes.byref(prob), _ptr(workspace),
+                                                      workspace_bytes, _stream(stream)))
+
+
+def cmm_fft(x, out, inverse=False, scale=1.0, stream=None) -> None:
+    """Batched complex transform along the last axis of complex128 tensors
+    (length a power of two); out may be x when the length is <= 4096."""
+    n = x.shape[-1]
+    log2n = n.bit_length() - 1
+    batch = x.numel() // n if n else 0
+    _check("cmm_fft", lib().cmm_fft(_ptr(x), _ptr(out), batch, log2n, int(bool(inverse)),
+                                    float(scale), _stream(stream)))
+
+
+def cmm_extract_cyclic(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat,
+                       stream=None) -> None:
+    _check("cmm_extract_cyclic", lib().cmm_extract_cyclic(
+        _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, estimator, _ptr(C_hat),
+        _dtype_code(C_hat), C_hat.stride(0), _stream(stream)))
+
+
+def estimate_fft(A, B, d: int, log2b: int, *, keys=None, tab1=None, tab2=None,
+                 estimator: str = "median", dense: bool = True, workspace=None,
+                 stream=None) -> "Estimate":
+    """Pagh's FFT form of the compressed product (float64 only)."""
+    torch = _torch()
+    dev = A.device
+    n_rows, n_cols = A.shape[0], B.shape[1]
+    if keys is not None and not hasattr(keys, "data_ptr"):
+        keys = keys_tensor(keys, dev)
+    if keys is not None:
+        tab1 = torch.empty((d, n_rows), dtype=torch.int32, device=dev)
+        tab2 = torch.empty((d, n_cols), dtype=torch.int32, device=dev)
+    p = torch.empty((d, 1 << log2b), dtype=torch.float64, device=dev)
+    C_hat = torch.empty((n_rows, n_cols), dtype=torch.float64, device=dev) if dense else None
+    pr = make_problem(A, B, d, log2b, keys=keys, tab1=tab1, tab2=tab2, p=p, C_hat=C_hat,
+                      compute="f64", estimator=estimator)
+    nbytes = cmm_fft_workspace_size(pr)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    cmm_estimate_fft(pr, workspace, nbytes, stream)
+    return Estimate(C_hat, p, tab1, tab2)
 
 
 def cmm_backward_workspace_size(prob: Problem) -> int:

@@ -760,6 +760,142 @@ cmm_status cmm_correctness_counts(const void* C_hat, cmm_dtype C_hat_dtype, int6
                             n_big, threshold, tolerance, counts, as_stream(stream));
 }
 
+// ---------------------------------------------------- Pagh's FFT form
+namespace {
+
+struct FftPlan {
+  int64_t kc = 1;     // k-chunk of the staged path
+  size_t off_x = 0, off_y = 0, off_z = 0, off_z2 = 0, off_P = 0, off_Q = 0, off_p = 0;
+  size_t bytes = 0;
+};
+
+// Sketches X, Y (float64 [d][kc][b]), their packed complex sequence and its
+// transform ([d][kc][b] complex each), the transformed accumulator P and its
+// inverse ([d][b] complex each), and p when the caller passes none.  The
+// chunk keeps the per-chunk buffers near 1 GiB.
+FftPlan make_fft_plan(const cmm_problem* pr) {
+  FftPlan P;
+  const size_t d = (size_t)pr->d, b = (size_t)1 << pr->log2b;
+  const size_t per_k = 48 * d * b;
+  int64_t kc = (int64_t)((size_t)1 << 30) / (int64_t)per_k;
+  if (kc > pr->n_inner) kc = pr->n_inner;
+  if (kc < 1) kc = 1;
+  P.kc = kc;
+  size_t off = 0;
+  P.off_x = off; off = align_up(off + 8 * d * kc * b, 256);
+  P.off_y = off; off = align_up(off + 8 * d * kc * b, 256);
+  P.off_z = off; off = align_up(off + 16 * d * kc * b, 256);
+  P.off_z2 = off; off = align_up(off + 16 * d * kc * b, 256);
+  P.off_P = off; off = align_up(off + 16 * d * b, 256);
+  P.off_Q = off; off = align_up(off + 16 * d * b, 256);
+  P.off_p = off; off = align_up(off + 8 * d * b, 256);
+  P.bytes = off;
+  return P;
+}
+
+cmm_status validate_fft_problem(const cmm_problem* pr, const char* fn) {
+  cmm_status s = validate_problem(pr, fn);
+  if (s != CMM_OK) return s;
+  if (pr->compute != CMM_F64 || pr->in_dtype != CMM_F64) {
+    set_error(std::string(fn) + ": the FFT form runs in float64 only (compute and in_dtype CMM_F64)");
+    return CMM_EUNSUPPORTED;
+  }
+  if (pr->d > 63 && pr->estimator == CMM_MEDIAN && pr->C_hat) {
+    set_error(std::string(fn) + ": median over more than 63 repetitions is not implemented");
+    return CMM_EUNSUPPORTED;
+  }
+  return CMM_OK;
+}
+
+cmm_status run_estimate_fft(const cmm_problem* pr, char* ws, hipStream_t s) {
+  const FftPlan P = make_fft_plan(pr);
+  const int d = pr->d;
+  const int64_t b = (int64_t)1 << pr->log2b;
+  cmm_status st;
+  if (pr->keys) {
+    st = launch_hash(pr->keys, d, pr->n_rows, pr->n_cols, pr->log2b, pr->tab1, pr->tab2, s);
+    if (st != CMM_OK) return st;
+  }
+  double* p = pr->p ? pr->p : reinterpret_cast<double*>(ws + P.off_p);
+  if (pr->n_inner == 0 || pr->n_rows == 0 || pr->n_cols == 0) {
+    if ((st = launch_zero(p, (size_t)d * b, s)) != CMM_OK) return st;
+  } else {
+    double* X = reinterpret_cast<double*>(ws + P.off_x);
+    double* Y = reinterpret_cast<double*>(ws + P.off_y);
+    void* Z = ws + P.off_z;
+    void* Z2 = ws + P.off_z2;
+    void* Pacc = ws + P.off_P;
+    if ((st = launch_zero_complex(Pacc, (size_t)d * b, s)) != CMM_OK) return st;
+    for (int64_t k0 = 0; k0 < pr->n_inner; k0 += P.kc) {
+      const int64_t kc = (pr->n_inner - k0) < P.kc ? (pr->n_inner - k0) : P.kc;
+      if ((st = launch_sketch(0, pr->A, CMM_F64, pr->n_rows, pr->n_inner, pr->lda, pr->tab1, d,
+                              pr->log2b, k0, kc, X, s)) != CMM_OK) return st;
+      if ((st = launch_sketch(1, pr->B, CMM_F64, pr->n_inner, pr->n_cols, pr->ldb, pr->tab2, d,
+                              pr->log2b, k0, kc, Y, s)) != CMM_OK) return st;
+      if ((st = launch_pack(X, Y, Z, (size_t)d * kc * b, s)) != CMM_OK) return st;
+      if ((st = launch_fft(Z, Z2, (int64_t)d * kc, pr->log2b, 0, 1.0, s)) != CMM_OK) return st;
+      if ((st = launch_accumulate_cyclic(Z2, d, kc, pr->log2b, Pacc, s)) != CMM_OK) return st;
+    }
+    void* Q = ws + P.off_Q;
+    st = launch_fft(Pacc, Q, d, pr->log2b, 1, std::ldexp(1.0, -pr->log2b), s);
+    if (st != CMM_OK) return st;
+    if ((st = launch_real_part(Q, p, (size_t)d * b, s)) != CMM_OK) return st;
+  }
+  if (pr->C_hat && pr->n_rows > 0 && pr->n_cols > 0)
+    return launch_extract(p, pr->tab1, pr->tab2, d, pr->n_rows, pr->n_cols, pr->log2b,
+                          pr->estimator, pr->C_hat, pr->out_dtype, pr->ldc, s, true);
+  return CMM_OK;
+}
+
+}  // namespace
+
+cmm_status cmm_fft(const void* in, void* out, int64_t batch, int log2n, int inverse, double scale,
+                   void* stream) {
+  if (log2n < 1 || log2n > 24) return invalid("cmm_fft: log2n must be in [1, 24]");
+  if (batch < 0) return invalid("cmm_fft: negative batch");
+  if (inverse != 0 && inverse != 1) return invalid("cmm_fft: inverse must be 0 or 1");
+  if (!std::isfinite(scale)) return invalid("cmm_fft: scale must be finite");
+  if (batch == 0) return CMM_OK;
+  if (!in || !out) return invalid("cmm_fft: null pointer");
+  if (log2n > 12 && in == out) return invalid("cmm_fft: in and out must differ when log2n > 12");
+  return launch_fft(in, out, batch, log2n, inverse, scale, as_stream(stream));
+}
+
+cmm_status cmm_fft_workspace_size(const cmm_problem* prob, size_t* bytes) {
+  cmm_status s = validate_fft_problem(prob, "cmm_fft_workspace_size");
+  if (s != CMM_OK) return s;
+  if (!bytes) return invalid("cmm_fft_workspace_size: bytes is null");
+  *bytes = make_fft_plan(prob).bytes;
+  return CMM_OK;
+}
+
+cmm_status cmm_estimate_fft(const cmm_problem* prob, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+  cmm_status s = validate_fft_problem(prob, "cmm_estimate_fft");
+  if (s != CMM_OK) return s;
+  const FftPlan P = make_fft_plan(prob);
+  if (workspace_bytes < P.bytes) {
+    set_error("cmm_estimate_fft: workspace of " + std::to_string(workspace_bytes) +
+              " bytes, need " + std::to_string(P.bytes));
+    return CMM_ENOMEM;
+  }
+  if (!workspace) return invalid("cmm_estimate_fft: workspace is null");
+  return run_estimate_fft(prob, static_cast<char*>(workspace), as_stream(stream));
+}
+
+cmm_status cmm_extract_cyclic(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                              int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
+                              void* C_hat, cmm_dtype out_dtype, int64_t ldc, void* stream) {
+  cmm_status s = check_decompress(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, out_dtype,
+                                  "cmm_extract_cyclic");
+  if (s != CMM_OK) return s;
+  if (ldc < n_cols) return invalid("cmm_extract_cyclic: ldc < n_cols");
+  if (n_rows == 0 || n_cols == 0) return CMM_OK;
+  if (!C_hat) return invalid("cmm_extract_cyclic: C_hat is null");
+  return launch_extract(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat, out_dtype, ldc,
+                        as_stream(stream), true);
+}
+
 cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes) {
   cmm_status s = validate_problem(prob, "cmm_workspace_size");
   if (s != CMM_OK) return s;

@@ -74,9 +74,21 @@ cmm_status launch_fwht(void* x, cmm_dtype dt, int64_t batch, int log2b, double s
 cmm_status launch_accumulate(const void* X, const void* Y, cmm_dtype dt, int d, int64_t kc,
                              int log2b, double* p_hat, hipStream_t s);
 
+// cyclic: Pagh's FFT form, buckets combined as (h1 + h2) mod b
 cmm_status launch_extract(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
                           int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator est,
-                          void* C_hat, cmm_dtype out_dt, int64_t ldc, hipStream_t s);
+                          void* C_hat, cmm_dtype out_dt, int64_t ldc, hipStream_t s,
+                          bool cyclic = false);
+
+// Pagh's FFT form: batched complex float64 transform (natural order; in and
+// out distinct when log2n > 12), its staged Compress helpers
+cmm_status launch_fft(const void* in, void* out, int64_t batch, int log2n, int inverse,
+                      double scale, hipStream_t s);
+cmm_status launch_pack(const double* X, const double* Y, void* Z, size_t n, hipStream_t s);
+cmm_status launch_accumulate_cyclic(const void* Z, int d, int64_t kc, int log2b, void* P,
+                                    hipStream_t s);
+cmm_status launch_zero_complex(void* x, size_t n, hipStream_t s);
+cmm_status launch_real_part(const void* Z, double* p, size_t n, hipStream_t s);
 
 cmm_status launch_extract_entries(const double* p, const uint32_t* tab1, const uint32_t* tab2,
                                   int d, int64_t n_rows, int64_t n_cols, int log2b,

@@ -14,6 +14,16 @@ namespace {
 constexpr int kCols = 256;
 constexpr int kRows = 8;
 
+// Entry of (i, j) from the two table entries: the bucket in the low bits
+// (the caller masks with b - 1), the sign product in bit 31.  The xor form
+// (Section 3.2) xors the buckets; Pagh's FFT form (Section 3.1) adds them
+// modulo b.
+template <bool CYC>
+__device__ __forceinline__ uint32_t combine(uint32_t a, uint32_t b) {
+  if (CYC) return ((a & 0x7FFFFFFFu) + (b & 0x7FFFFFFFu)) | ((a ^ b) & kSignBit);
+  return a ^ b;
+}
+
 // Compare-exchange network (odd-even transposition) leaving v sorted.
 template <int D>
 __device__ __forceinline__ void sort_net(double (&v)[D]) {
@@ -28,7 +38,7 @@ __device__ __forceinline__ void sort_net(double (&v)[D]) {
   }
 }
 
-template <typename OutT, int D>
+template <typename OutT, int D, bool CYC = false>
 __global__ __launch_bounds__(kCols) void extract_kernel(
     const double* __restrict__ p, const uint32_t* __restrict__ tab1,
     const uint32_t* __restrict__ tab2, int64_t n_rows, int64_t n_cols, int log2b, int mean,
@@ -46,7 +56,7 @@ __global__ __launch_bounds__(kCols) void extract_kernel(
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
       const int64_t i = i0 + r < n_rows ? i0 + r : n_rows - 1;
-      const uint32_t e = tab1[(size_t)t * n_rows + i] ^ e2;
+      const uint32_t e = combine<CYC>(tab1[(size_t)t * n_rows + i], e2);
       const double x = pt[e & bmask];
       v[r][t] = (e & kSignBit) ? -x : x;
     }
@@ -72,7 +82,7 @@ __global__ __launch_bounds__(kCols) void extract_kernel(
 // Generic d: the median (d up to kMaxD) keeps the candidates in a local
 // array, insertion sorted; the mean only sums them.
 constexpr int kMaxD = 63;
-template <typename OutT>
+template <typename OutT, bool CYC = false>
 __global__ __launch_bounds__(kCols) void extract_generic_kernel(
     const double* __restrict__ p, const uint32_t* __restrict__ tab1,
     const uint32_t* __restrict__ tab2, int d, int64_t n_rows, int64_t n_cols, int log2b,
@@ -86,7 +96,7 @@ __global__ __launch_bounds__(kCols) void extract_generic_kernel(
     double v[kMaxD];
     double s = 0.0;
     for (int t = 0; t < d; ++t) {
-      const uint32_t e = tab1[(size_t)t * n_rows + i] ^ tab2[(size_t)t * n_cols + j];
+      const uint32_t e = combine<CYC>(tab1[(size_t)t * n_rows + i], tab2[(size_t)t * n_cols + j]);
       const double x = p[(size_t)t * b + (e & (uint32_t)(b - 1))];
       const double y = (e & kSignBit) ? -x : x;
       s += y;
@@ -324,7 +334,7 @@ __global__ void zero_counters_kernel(unsigned long long* c, int n) {
 
 __global__ void zero_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
-template <typename OutT>
+template <typename OutT, bool CYC>
 cmm_status run(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
                int64_t n_rows, int64_t n_cols, int log2b, int mean, OutT* C, int64_t ldc,
                hipStream_t s) {
@@ -338,8 +348,8 @@ cmm_status run(const double* p, const uint32_t* tab1, const uint32_t* tab2, int 
   dim3 grid((unsigned)gx, (unsigned)gy);
 #define CMM_EXTRACT_CASE(DV)                                                                  \
   case DV:                                                                                    \
-    hipLaunchKernelGGL((extract_kernel<OutT, DV>), grid, dim3(kCols), 0, s, p, tab1, tab2,    \
-                       n_rows, n_cols, log2b, mean, C, ldc);                                  \
+    hipLaunchKernelGGL((extract_kernel<OutT, DV, CYC>), grid, dim3(kCols), 0, s, p, tab1,     \
+                       tab2, n_rows, n_cols, log2b, mean, C, ldc);                            \
     break;
   switch (d) {
     CMM_EXTRACT_CASE(1)
@@ -349,7 +359,7 @@ cmm_status run(const double* p, const uint32_t* tab1, const uint32_t* tab2, int 
     CMM_EXTRACT_CASE(9)
     CMM_EXTRACT_CASE(11)
     default:
-      hipLaunchKernelGGL(extract_generic_kernel<OutT>, grid, dim3(kCols), 0, s, p, tab1, tab2, d,
+      hipLaunchKernelGGL((extract_generic_kernel<OutT, CYC>), grid, dim3(kCols), 0, s, p, tab1, tab2, d,
                          n_rows, n_cols, log2b, mean, C, ldc);
   }
 #undef CMM_EXTRACT_CASE
@@ -360,12 +370,17 @@ cmm_status run(const double* p, const uint32_t* tab1, const uint32_t* tab2, int 
 
 cmm_status launch_extract(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
                           int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator est,
-                          void* C_hat, cmm_dtype out_dt, int64_t ldc, hipStream_t s) {
+                          void* C_hat, cmm_dtype out_dt, int64_t ldc, hipStream_t s, bool cyclic) {
   ProfScope prof_("extract", s);
   const int mean = est == CMM_MEAN;
+  if (cyclic) {
+    if (out_dt == CMM_F64)
+      return run<double, true>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, (double*)C_hat, ldc, s);
+    return run<float, true>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, (float*)C_hat, ldc, s);
+  }
   if (out_dt == CMM_F64)
-    return run<double>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, (double*)C_hat, ldc, s);
-  return run<float>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, (float*)C_hat, ldc, s);
+    return run<double, false>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, (double*)C_hat, ldc, s);
+  return run<float, false>(p, tab1, tab2, d, n_rows, n_cols, log2b, mean, (float*)C_hat, ldc, s);
 }
 
 cmm_status launch_extract_entries(const double* p, const uint32_t* tab1, const uint32_t* tab2,

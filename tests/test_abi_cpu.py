@@ -88,6 +88,15 @@ def test_problem_struct_layout_matches_header():
                                        None),                                       # tol NaN
     lambda L: L.cmm_correctness_counts(1, 0, 8, 1, 8, 8, 8, 1, 1, 1, 0.5, 0.1, None, None),  # counts
     lambda L: L.cmm_correctness_counts(1, 0, 8, 1, 8, 8, 8, None, 1, 1, 0.5, 0.1, 1, None),  # big
+    lambda L: L.cmm_fft(1, 2, 4, 0, 0, 1.0, None),                      # log2n = 0
+    lambda L: L.cmm_fft(1, 2, 4, 25, 0, 1.0, None),                     # log2n > 24
+    lambda L: L.cmm_fft(1, 2, 4, 8, 2, 1.0, None),                      # inverse not 0 / 1
+    lambda L: L.cmm_fft(1, 2, 4, 8, 0, float("inf"), None),             # scale not finite
+    lambda L: L.cmm_fft(1, 1, 4, 13, 0, 1.0, None),                     # in place above 2^12
+    lambda L: L.cmm_fft(None, 2, 4, 8, 0, 1.0, None),                   # null
+    lambda L: L.cmm_extract_cyclic(1, 1, 1, 4, 8, 8, 8, 0, 1, 0, 8, None),   # median, even d
+    lambda L: L.cmm_extract_cyclic(1, 1, 1, 3, 8, 8, 8, 0, 1, 0, 7, None),   # ldc < n_cols
+    lambda L: L.cmm_extract_cyclic(1, 1, 1, 3, 8, 8, 8, 0, None, 0, 8, None),  # C_hat null
 ])
 def test_invalid_arguments_rejected_on_host(call):
     L = _lib_or_skip()
@@ -128,6 +137,28 @@ def test_precision_form_limits(kw):
     n = ctypes.c_size_t(0)
     assert L.cmm_workspace_size(ctypes.byref(_problem(**kw)), ctypes.byref(n)) == cmm.CMM_EUNSUPPORTED
     assert b"precision form" in L.cmm_last_error()
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(compute=cmm.CMM_F32), cmm.CMM_EUNSUPPORTED),            # the FFT form is float64 only
+    (dict(in_dtype=cmm.CMM_F32, compute=cmm.CMM_F32), cmm.CMM_EUNSUPPORTED),
+    (dict(d=4), cmm.CMM_EINVAL),
+    (dict(tab1=None), cmm.CMM_EINVAL),
+])
+def test_fft_form_validation(kw, status):
+    L = _lib_or_skip()
+    n = ctypes.c_size_t(0)
+    pr = _problem(**kw)
+    assert L.cmm_fft_workspace_size(ctypes.byref(pr), ctypes.byref(n)) == status
+    assert L.cmm_estimate_fft(ctypes.byref(pr), 1, 1 << 40, None) == status
+
+
+def test_fft_form_short_workspace():
+    L = _lib_or_skip()
+    pr = _problem(n_rows=64, n_inner=32, n_cols=48, lda=32, ldb=48)
+    n = ctypes.c_size_t(0)
+    assert L.cmm_fft_workspace_size(ctypes.byref(pr), ctypes.byref(n)) == cmm.CMM_OK
+    assert L.cmm_estimate_fft(ctypes.byref(pr), 1, n.value - 1, None) == cmm.CMM_ENOMEM
 
 
 @pytest.mark.parametrize("kw,status", [
