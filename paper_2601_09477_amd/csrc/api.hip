@@ -764,28 +764,49 @@ cmm_status cmm_correctness_counts(const void* C_hat, cmm_dtype C_hat_dtype, int6
 namespace {
 
 struct FftPlan {
+  bool fused = false;
+  int groups = 1;     // k-ranges of the fused kernel
   int64_t kc = 1;     // k-chunk of the staged path
   size_t off_x = 0, off_y = 0, off_z = 0, off_z2 = 0, off_P = 0, off_Q = 0, off_p = 0;
+  size_t off_at = 0, off_planA = 0, off_planB = 0, off_part = 0;
   size_t bytes = 0;
 };
 
-// Sketches X, Y (float64 [d][kc][b]), their packed complex sequence and its
-// transform ([d][kc][b] complex each), the transformed accumulator P and its
-// inverse ([d][b] complex each), and p when the caller passes none.  The
-// chunk keeps the per-chunk buffers near 1 GiB.
+// Fused path: A^T, the bucket plans (b_lo = 2^12), complex partials
+// [groups][d][b]; staged path: sketches X, Y (float64 [d][kc][b]), their
+// packed complex sequence and its transform ([d][kc][b] complex each), the
+// chunk keeping these buffers near 1 GiB.  Both: the transformed
+// accumulator P and its inverse ([d][b] complex each), and p when the
+// caller passes none.
 FftPlan make_fft_plan(const cmm_problem* pr) {
   FftPlan P;
   const size_t d = (size_t)pr->d, b = (size_t)1 << pr->log2b;
-  const size_t per_k = 48 * d * b;
-  int64_t kc = (int64_t)((size_t)1 << 30) / (int64_t)per_k;
-  if (kc > pr->n_inner) kc = pr->n_inner;
-  if (kc < 1) kc = 1;
-  P.kc = kc;
   size_t off = 0;
-  P.off_x = off; off = align_up(off + 8 * d * kc * b, 256);
-  P.off_y = off; off = align_up(off + 8 * d * kc * b, 256);
-  P.off_z = off; off = align_up(off + 16 * d * kc * b, 256);
-  P.off_z2 = off; off = align_up(off + 16 * d * kc * b, 256);
+  P.fused = pr->n_inner > 0 && compress_fft_supported(pr->n_rows, pr->n_cols, pr->log2b) &&
+            plan_lds_bytes(pr->n_rows, 12) <= 160 * 1024 &&
+            plan_lds_bytes(pr->n_cols, 12) <= 160 * 1024;
+  if (P.fused) {
+    const int64_t units = (int64_t)d * (((int64_t)1 << (pr->log2b - 12)) / 2 + 1);
+    int64_t g = (2048 + units - 1) / units;
+    if (g > pr->n_inner) g = pr->n_inner;
+    if (g < 1) g = 1;
+    while (g > 1 && ((units * g) & 7) != 0 && g < pr->n_inner) ++g;
+    P.groups = (int)g;
+    P.off_at = off; off = align_up(off + 8 * (size_t)pr->n_rows * pr->n_inner, 256);
+    P.off_planA = off; off = align_up(off + plan_bytes(pr->d, pr->n_rows, 12), 256);
+    P.off_planB = off; off = align_up(off + plan_bytes(pr->d, pr->n_cols, 12), 256);
+    P.off_part = off; off = align_up(off + 16 * (size_t)P.groups * d * b, 256);
+  } else {
+    const size_t per_k = 48 * d * b;
+    int64_t kc = (int64_t)((size_t)1 << 30) / (int64_t)per_k;
+    if (kc > pr->n_inner) kc = pr->n_inner;
+    if (kc < 1) kc = 1;
+    P.kc = kc;
+    P.off_x = off; off = align_up(off + 8 * d * kc * b, 256);
+    P.off_y = off; off = align_up(off + 8 * d * kc * b, 256);
+    P.off_z = off; off = align_up(off + 16 * d * kc * b, 256);
+    P.off_z2 = off; off = align_up(off + 16 * d * kc * b, 256);
+  }
   P.off_P = off; off = align_up(off + 16 * d * b, 256);
   P.off_Q = off; off = align_up(off + 16 * d * b, 256);
   P.off_p = off; off = align_up(off + 8 * d * b, 256);
@@ -820,13 +841,41 @@ cmm_status run_estimate_fft(const cmm_problem* pr, char* ws, hipStream_t s) {
   if (pr->n_inner == 0 || pr->n_rows == 0 || pr->n_cols == 0) {
     if ((st = launch_zero(p, (size_t)d * b, s)) != CMM_OK) return st;
   } else {
+    void* Pacc = ws + P.off_P;
+    if (P.fused) {
+      void* At = ws + P.off_at;
+      st = launch_transpose(pr->A, pr->in_dtype, pr->n_rows, pr->n_inner, pr->lda, At, CMM_F64, s);
+      if (st != CMM_OK) return st;
+      CompressArgs a;
+      a.At = At;
+      a.B = pr->B;
+      a.ldb = pr->ldb;
+      a.n_rows = pr->n_rows;
+      a.n_cols = pr->n_cols;
+      a.n_inner = pr->n_inner;
+      a.tab1 = pr->tab1;
+      a.tab2 = pr->tab2;
+      a.planA = carve_plan(ws + P.off_planA, d, pr->n_rows, 12);
+      a.planB = carve_plan(ws + P.off_planB, d, pr->n_cols, 12);
+      a.d = d;
+      a.log2b = pr->log2b;
+      a.groups = P.groups;
+      a.partial = reinterpret_cast<double*>(ws + P.off_part);
+      a.ex_cap = 0;
+      a.dma = 0;
+      a.variant = 0;
+      if ((st = launch_plan(pr->tab1, d, pr->n_rows, 12, a.planA, s)) != CMM_OK) return st;
+      if ((st = launch_plan(pr->tab2, d, pr->n_cols, 12, a.planB, s)) != CMM_OK) return st;
+      if ((st = launch_compress_fft(a, s)) != CMM_OK) return st;
+      st = launch_reduce_fft_partials(a.partial, P.groups, d, pr->log2b, Pacc, s);
+      if (st != CMM_OK) return st;
+    }
     double* X = reinterpret_cast<double*>(ws + P.off_x);
     double* Y = reinterpret_cast<double*>(ws + P.off_y);
     void* Z = ws + P.off_z;
     void* Z2 = ws + P.off_z2;
-    void* Pacc = ws + P.off_P;
-    if ((st = launch_zero_complex(Pacc, (size_t)d * b, s)) != CMM_OK) return st;
-    for (int64_t k0 = 0; k0 < pr->n_inner; k0 += P.kc) {
+    if (!P.fused && (st = launch_zero_complex(Pacc, (size_t)d * b, s)) != CMM_OK) return st;
+    for (int64_t k0 = 0; !P.fused && k0 < pr->n_inner; k0 += P.kc) {
       const int64_t kc = (pr->n_inner - k0) < P.kc ? (pr->n_inner - k0) : P.kc;
       if ((st = launch_sketch(0, pr->A, CMM_F64, pr->n_rows, pr->n_inner, pr->lda, pr->tab1, d,
                               pr->log2b, k0, kc, X, s)) != CMM_OK) return st;

@@ -158,6 +158,14 @@ __host__ __device__ inline PlanView carve_plan(char* p, int d, int64_t n, int lb
 cmm_status launch_plan(const uint32_t* tab, int d, int64_t n, int lb, const PlanView& pv,
                        hipStream_t s);
 cmm_status launch_compress(const CompressArgs& a, cmm_dtype dt, int lb, hipStream_t s);
+// fused FFT-form Compress (b_lo = 2^12 complex, partials [groups][d][b]
+// complex), its LDS size and shape limits, and the reduction of its partials
+// into the full transformed accumulator
+size_t compress_fft_lds(int64_t n_rows, int64_t n_cols, int log2b);
+bool compress_fft_supported(int64_t n_rows, int64_t n_cols, int log2b);
+cmm_status launch_compress_fft(const CompressArgs& a, hipStream_t s);
+cmm_status launch_reduce_fft_partials(const void* part, int groups, int d, int log2b, void* P,
+                                      hipStream_t s);
 // LDS bytes of the fused kernel (b_lo = 2^lb, 32 elements per thread)
 // before the collision lists.
 size_t compress_lds_base(cmm_dtype dt, int lb, int64_t n_rows, int64_t n_cols);
