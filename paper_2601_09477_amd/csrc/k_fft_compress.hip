@@ -67,64 +67,71 @@ __device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, doub
 
 // V[m] = sum_x v[x] w8^(m x), w8 = exp(-2 pi i / 8), in place: pairs (x,
 // x + 4) first, the differences turned by w8^x, then two 4-point
-// transforms giving the even and the odd outputs.
+// transforms giving the even and the odd outputs.  Every step overwrites
+// its inputs, so only the 8 points and two temporaries are live.
 __device__ __forceinline__ void dft8(double2 (&v)[8]) {
   constexpr double r = 0.70710678118654752440;
-  double2 s0 = caddf(v[0], v[4]), s1 = caddf(v[1], v[5]), s2 = caddf(v[2], v[6]),
-          s3 = caddf(v[3], v[7]);
-  double2 d0 = csubf(v[0], v[4]), d1 = csubf(v[1], v[5]), d2 = csubf(v[2], v[6]),
-          d3 = csubf(v[3], v[7]);
-  d1 = make_double2((d1.x + d1.y) * r, (d1.y - d1.x) * r);     // (1 - i) / sqrt 2
-  d2 = make_double2(d2.y, -d2.x);                              // -i
-  d3 = make_double2((d3.y - d3.x) * r, -(d3.x + d3.y) * r);    // (-1 - i) / sqrt 2
-  dft4(s0, s1, s2, s3);
-  dft4(d0, d1, d2, d3);
-  v[0] = s0; v[2] = s1; v[4] = s2; v[6] = s3;
-  v[1] = d0; v[3] = d1; v[5] = d2; v[7] = d3;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double2 t = v[k];
+    v[k] = caddf(t, v[k + 4]);
+    v[k + 4] = csubf(t, v[k + 4]);
+  }
+  v[5] = make_double2((v[5].x + v[5].y) * r, (v[5].y - v[5].x) * r);     // (1 - i) / sqrt 2
+  v[6] = make_double2(v[6].y, -v[6].x);                                  // -i
+  v[7] = make_double2((v[7].y - v[7].x) * r, -(v[7].x + v[7].y) * r);    // (-1 - i) / sqrt 2
+  dft4(v[0], v[1], v[2], v[3]);   // -> V0, V2, V4, V6
+  dft4(v[4], v[5], v[6], v[7]);   // -> V1, V3, V5, V7
+  const double2 o1 = v[1], o2 = v[2], o3 = v[3], o4 = v[4], o5 = v[5], o6 = v[6];
+  v[1] = o4; v[2] = o1; v[3] = o5; v[4] = o2; v[5] = o6; v[6] = o3;
 }
 
-// v[m] *= w^m, m = 1..7
+// v[m] *= w^m, m = 1..7, the powers built one at a time
 __device__ __forceinline__ void twiddle8(double2 (&v)[8], double2 w) {
-  const double2 w2 = cmulf(w, w), w3 = cmulf(w2, w), w4 = cmulf(w2, w2);
-  const double2 w5 = cmulf(w4, w), w6 = cmulf(w3, w3), w7 = cmulf(w6, w);
-  v[1] = cmulf(v[1], w); v[2] = cmulf(v[2], w2); v[3] = cmulf(v[3], w3);
-  v[4] = cmulf(v[4], w4); v[5] = cmulf(v[5], w5); v[6] = cmulf(v[6], w6);
-  v[7] = cmulf(v[7], w7);
+  double2 p = w;
+#pragma unroll
+  for (int m = 1; m < 8; ++m) {
+    v[m] = cmulf(v[m], p);
+    if (m < 7) p = cmulf(p, w);
+  }
 }
 
 // 4096-point forward transform; thread tid enters with x[tid + 512 m] in
 // v[m] and leaves with X[a + 8 b1 + 64 c2 + 512 m] in v[m], where
 // a = tid >> 6, b1 = (tid >> 3) & 7, c2 = tid & 7.  Ends without a barrier:
 // the caller separates the last reads from the next use of xb.
-__device__ __forceinline__ void fft4096(double2 (&v)[8], double2* __restrict__ xb, double2 tw0,
-                                        double2 tw1, double2 tw2) {
+__device__ __forceinline__ void fft4096(double2 (&v)[8], double2* __restrict__ xb,
+                                        const double2* __restrict__ stw) {
+  // Padded positions xpad(i) = i + 8 (i >> 6).  Within each stage the 8
+  // points of a thread sit at one base plus fixed steps: m * 512 -> 576,
+  // 64 x -> 72, 8 x -> 8, x -> 1 (the low 6 bits never carry).
   const int tid = threadIdx.x;
+  const int a = tid >> 6, jp = tid & 63, b1 = (tid >> 3) & 7, jj = tid & 7;
   dft8(v);
-  twiddle8(v, tw0);
+  twiddle8(v, stw[tid]);
+  double2* p = xb + xpad(tid);
 #pragma unroll
-  for (int m = 0; m < 8; ++m) xb[xpad(m * 512 + tid)] = v[m];
+  for (int m = 0; m < 8; ++m) p[576 * m] = v[m];
   __syncthreads();
-  const int a = tid >> 6, jp = tid & 63;
-  int base = a * 512 + jp;
+  p = xb + xpad(a * 512 + jp);
 #pragma unroll
-  for (int x = 0; x < 8; ++x) v[x] = xb[xpad(base + 64 * x)];
+  for (int x = 0; x < 8; ++x) v[x] = p[72 * x];
   dft8(v);
-  twiddle8(v, tw1);
+  twiddle8(v, stw[512 + jp]);
 #pragma unroll
-  for (int m = 0; m < 8; ++m) xb[xpad(base + 64 * m)] = v[m];
+  for (int m = 0; m < 8; ++m) p[72 * m] = v[m];
   __syncthreads();
-  const int b1 = (tid >> 3) & 7, jj = tid & 7;
-  base = a * 512 + b1 * 64 + jj;
+  p = xb + xpad(a * 512 + b1 * 64 + jj);
 #pragma unroll
-  for (int x = 0; x < 8; ++x) v[x] = xb[xpad(base + 8 * x)];
+  for (int x = 0; x < 8; ++x) v[x] = p[8 * x];
   dft8(v);
-  twiddle8(v, tw2);
+  twiddle8(v, stw[576 + jj]);
 #pragma unroll
-  for (int m = 0; m < 8; ++m) xb[xpad(base + 8 * m)] = v[m];
+  for (int m = 0; m < 8; ++m) p[8 * m] = v[m];
   __syncthreads();
-  base = a * 512 + b1 * 64 + jj * 8;
+  p = xb + xpad(a * 512 + b1 * 64 + jj * 8);
 #pragma unroll
-  for (int x = 0; x < 8; ++x) v[x] = xb[xpad(base + x)];
+  for (int x = 0; x < 8; ++x) v[x] = p[x];
   dft8(v);
 }
 
@@ -186,6 +193,24 @@ __device__ __forceinline__ void merge_chains(double* __restrict__ row,
   }
 }
 
+// X[e] = w_e (row[re_e] + i row[im_e]) with w_e = cT dT^e s_e roots[q_e]
+__device__ __forceinline__ void gather_weighted(double2 (&X)[8], const double* __restrict__ row,
+                                                const uint32_t (&off)[8], const uint32_t (&qs)[4],
+                                                const double2* __restrict__ roots, double2 cT,
+                                                double2 dT) {
+  double2 tw = cT;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    uint32_t o = off[e];
+    asm volatile("" : "+v"(o));   // decode per use: keeps 8 registers, not 16
+    const uint32_t qe = (qs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+    double2 sg = roots[qe & 0x7FFFu];
+    if (qe & 0x8000u) sg = make_double2(-sg.x, -sg.y);
+    X[e] = cmulf(cmulf(tw, sg), make_double2(row[o & 0xFFFFu], row[o >> 16]));
+    if (e < 7) tw = cmulf(tw, dT);
+  }
+}
+
 __global__ __launch_bounds__(kFNT, 2) void compress_fft_kernel(CompressArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int bhi_bits = a.log2b - kFLB;
@@ -212,6 +237,7 @@ __global__ __launch_bounds__(kFNT, 2) void compress_fft_kernel(CompressArgs a) {
   uint32_t* recA = reinterpret_cast<uint32_t*>(row + row_pitch<double>(nmax));
   uint32_t* recB = recA + a.n_rows;
   double2* roots = reinterpret_cast<double2*>(recA + ((a.n_rows + a.n_cols + 3) & ~(int64_t)3));
+  double2* stw = roots + b_hi;   // w_4096^j (512), w_512^j (64), w_64^j (8)
   uint32_t* mapA = reinterpret_cast<uint32_t*>(xb);   // [b_lo], in the exchange buffer
   uint32_t* mapB = mapA + (1 << kFLB);
 
@@ -224,6 +250,9 @@ __global__ __launch_bounds__(kFNT, 2) void compress_fft_kernel(CompressArgs a) {
 
   // roots of unity of order b_hi, bucket maps, chain records
   for (uint32_t q = tid; q < b_hi; q += kFNT) roots[q] = fwd_root(q, b_hi);
+  stw[tid] = fwd_root((uint64_t)tid, 4096);
+  if (tid < 64) stw[512 + tid] = fwd_root((uint64_t)tid, 512);
+  if (tid < 8) stw[576 + tid] = fwd_root((uint64_t)tid, 64);
   for (int r = tid; r < (1 << kFLB); r += kFNT) {
     mapA[r] = (uint32_t)a.n_rows;
     mapB[r] = (uint32_t)a.n_cols;
@@ -232,36 +261,37 @@ __global__ __launch_bounds__(kFNT, 2) void compress_fft_kernel(CompressArgs a) {
   build_records(oA, uhi, b_hi - 1, recA, mapA);
   build_records(oB, uhi, b_hi - 1, recB, mapB);
   __syncthreads();
-  // gather slots and fold weights of the thread's buckets tid + 512 e
-  uint32_t offA[8], offB[8];
-  double2 wA[8], wB[8];
+  // gather slots of the thread's buckets r = tid + 512 e, and their fold
+  // weights w_b^(u_hi h(f)) s(f) of the first row f, split as
+  // w_b^(u_hi r) (= cT dT^e, shared by the operands) times s(f)
+  // w_{b_hi}^(u_hi hi(f)) (a root index and a sign, 16 bits per bucket)
+  uint32_t offA[8], offB[8], qA[4], qB[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) { qA[e] = 0; qB[e] = 0; }
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int r = tid + 512 * e;
     const int32_t fa = oA.first[r], fb = oB.first[r];
     offA[e] = (uint32_t)(fa >= 0 ? fa : a.n_rows) | (mapA[r] << 16);
     offB[e] = (uint32_t)(fb >= 0 ? fb : a.n_cols) | (mapB[r] << 16);
-    wA[e] = make_double2(0.0, 0.0);
-    wB[e] = make_double2(0.0, 0.0);
     if (fa >= 0) {
       const uint32_t ef = oA.tab[fa];
-      const double2 w = fwd_root((uint64_t)uhi * (ef & kBucketMask), b);
-      wA[e] = (ef & kSignBit) ? make_double2(-w.x, -w.y) : w;
+      const uint32_t q = (uhi * ((ef & kBucketMask) >> kFLB)) & (b_hi - 1);
+      qA[e >> 1] |= (q | ((ef & kSignBit) >> 16)) << (16 * (e & 1));
     }
     if (fb >= 0) {
       const uint32_t ef = oB.tab[fb];
-      const double2 w = fwd_root((uint64_t)uhi * (ef & kBucketMask), b);
-      wB[e] = (ef & kSignBit) ? make_double2(-w.x, -w.y) : w;
+      const uint32_t q = (uhi * ((ef & kBucketMask) >> kFLB)) & (b_hi - 1);
+      qB[e >> 1] |= (q | ((ef & kSignBit) >> 16)) << (16 * (e & 1));
     }
   }
+  const double2 cT = fwd_root((uint64_t)uhi * (uint64_t)tid, b);
+  const double2 dT = fwd_root((uint64_t)uhi * 512u, b);
   // this thread's chains for the in-place merges
   const int cA0 = (int)((int64_t)oA.nch * tid / kFNT), cA1 = (int)((int64_t)oA.nch * (tid + 1) / kFNT);
   const int cB0 = (int)((int64_t)oB.nch * tid / kFNT), cB1 = (int)((int64_t)oB.nch * (tid + 1) / kFNT);
   const int sA = cA0 < cA1 ? cA0 + oA.cs[cA0] : 0;
   const int sB = cB0 < cB1 ? cB0 + oB.cs[cB0] : 0;
-  const double2 tw0 = fwd_root((uint64_t)tid, 4096);
-  const double2 tw1 = fwd_root((uint64_t)(tid & 63), 512);
-  const double2 tw2 = fwd_root((uint64_t)(tid & 7), 64);
   __syncthreads();   // the maps are read; the exchange buffer is free
 
   const double* At = reinterpret_cast<const double*>(a.At);
@@ -279,26 +309,22 @@ __global__ __launch_bounds__(kFNT, 2) void compress_fft_kernel(CompressArgs a) {
     __syncthreads();   // A's row of k has landed
     merge_chains(row, recA, sA, cA1 - cA0, roots);
     __syncthreads();
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      X[e] = cmulf(wA[e], make_double2(row[offA[e] & 0xFFFFu], row[offA[e] >> 16]));
+    gather_weighted(X, row, offA, qA, roots, cT, dT);
     __syncthreads();   // the row buffer is free
     if (tid == 0) row[a.n_cols] = 0.0;
     stage_row<double, kFNT>(row, Bm + k * a.ldb, a.n_cols, dma);
-    fft4096(X, xb, tw0, tw1, tw2);
+    fft4096(X, xb, stw);
     if (dma) wait_dma();
     __syncthreads();   // B's row has landed; X's last exchange reads are done
     merge_chains(row, recB, sB, cB1 - cB0, roots);
     __syncthreads();
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      Y[e] = cmulf(wB[e], make_double2(row[offB[e] & 0xFFFFu], row[offB[e] >> 16]));
+    gather_weighted(Y, row, offB, qB, roots, cT, dT);
     __syncthreads();
     if (k + 1 < k1) {
       if (tid == 0) row[a.n_rows] = 0.0;
       stage_row<double, kFNT>(row, At + (k + 1) * a.n_rows, a.n_rows, dma);
     }
-    fft4096(Y, xb, tw0, tw1, tw2);
+    fft4096(Y, xb, stw);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       acc[e].x = fma(X[e].x, Y[e].x, fma(-X[e].y, Y[e].y, acc[e].x));
@@ -340,7 +366,7 @@ size_t compress_fft_lds(int64_t n_rows, int64_t n_cols, int log2b) {
   const int64_t nmax = n_rows > n_cols ? n_rows : n_cols;
   return sizeof(double2) * kXLen + sizeof(double) * (size_t)row_pitch<double>(nmax) +
          sizeof(uint32_t) * (size_t)((n_rows + n_cols + 3) & ~(int64_t)3) +
-         sizeof(double2) * ((size_t)1 << (log2b - kFLB));
+         sizeof(double2) * (((size_t)1 << (log2b - kFLB)) + 512 + 64 + 8);
 }
 
 bool compress_fft_supported(int64_t n_rows, int64_t n_cols, int log2b) {
