@@ -126,12 +126,15 @@ __device__ __forceinline__ void fft4096(double2 (&v)[8], double2* __restrict__ x
   for (int x = 0; x < 8; ++x) v[x] = p[8 * x];
   dft8(v);
   twiddle8(v, stw[576 + jj]);
+  // the last exchange stores point (m, jj) of a 64-point block at 8 m +
+  // (jj ^ m): the writes stay contiguous per m, and the reads below (8
+  // consecutive points per thread) fall into distinct banks across lanes
+  p = xb + xpad(a * 512 + b1 * 64);
 #pragma unroll
-  for (int m = 0; m < 8; ++m) p[8 * m] = v[m];
+  for (int m = 0; m < 8; ++m) p[8 * m + (jj ^ m)] = v[m];
   __syncthreads();
-  p = xb + xpad(a * 512 + b1 * 64 + jj * 8);
 #pragma unroll
-  for (int x = 0; x < 8; ++x) v[x] = p[x];
+  for (int x = 0; x < 8; ++x) v[x] = p[8 * jj + (x ^ jj)];
   dft8(v);
 }
 
