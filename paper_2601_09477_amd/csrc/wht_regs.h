@@ -257,15 +257,17 @@ __device__ __forceinline__ uint32_t pad16(uint32_t x) { return x + (x >> 6) + ((
 
 // Butterfly across lane bit 3: lanes with bit 3 clear keep a + b, lanes
 // with it set b' = a - b, where the partner value comes from lane xor 8
-// (row_ror:8 within 16-lane rows).
+// (row_ror:8 within 16-lane rows).  The rotation gives every lane a
+// source, so the move needs no prior value in its destination (mov_dpp;
+// update_dpp with an explicit old value costs one extra move per dword).
 __device__ __forceinline__ double dpp_xor8(double x) {
   const uint64_t u = (uint64_t)__double_as_longlong(x);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x128, 0xF, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x128, 0xF, 0xF, false);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x128, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x128, 0xF, 0xF, false);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 __device__ __forceinline__ float dpp_xor8(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x128, 0xF, 0xF, false));
 }
 
 template <int J, typename T>
