@@ -58,6 +58,7 @@ struct BatchLayout {
   std::vector<int64_t> off_p;       // workspace p per problem (-1: the caller's)
   size_t off_desc = 0, off_items = 0, off_queue = 0, desc_bytes = 0;
   size_t lds = 0;
+  bool desc = false;                // 16-element layout with descriptor fix-ups
   size_t bytes = 0;
 };
 
@@ -107,6 +108,20 @@ BatchLayout make_layout(const cmm_batch& b, const BatchConfig& c) {
     if (base > lds_cap) return L;
     const size_t want = base + sizeof(uint2) * (size_t)(p.n_rows + p.n_cols + (p.n_rows + p.n_cols + 8) / 2);
     lds = std::max(lds, std::min(want, lds_cap));
+  }
+  // descriptor fix-ups (faster than walking the chains) when every
+  // problem's rows, spare elements and descriptors fit the LDS share
+  if (c.radix == 16) {
+    bool desc = true;
+    size_t dl = 0;
+    for (int i = 0; i < n && desc; ++i) {
+      const cmm_problem& p = b.probs[i];
+      if (!active(p)) continue;
+      const size_t need = compress16_desc_lds(b.cdt, p.n_rows, p.n_cols);
+      desc = need <= lds_cap && p.n_rows + 64 < 32768 && p.n_cols + 64 < 32768;
+      dl = std::max(dl, need);
+    }
+    if (desc) { L.desc = true; lds = dl; }
   }
   L.lds = lds;
   // items
@@ -171,7 +186,7 @@ BatchLayout make_layout(const cmm_batch& b, const BatchConfig& c) {
     bp.partial = (int64_t)off; off = align_up(off + sizeof(double) * groups[i] * p.d * blen, 256);
     const size_t base = lds_base(b.cdt, c, p.n_rows, p.n_cols);
     int64_t cap = (int64_t)((lds - std::min(lds, base)) / sizeof(uint2));
-    bp.ex_cap = std::min<int64_t>(cap, p.n_rows + p.n_cols);
+    bp.ex_cap = L.desc ? 0 : std::min<int64_t>(cap, p.n_rows + p.n_cols);
     // 16-byte row copies: the workspace is 256-byte aligned, the caller's B is checked here
     const bool b_ok = bp.bc >= 0 || ((uintptr_t)p.B % 16 == 0);
     bp.dma = (p.n_rows % V == 0) && (p.n_cols % V == 0) && (bp.ldb % V == 0) && b_ok;
@@ -266,7 +281,7 @@ cmm_status compress_all(cmm_batch& b, const BatchConfig& c, char* ws, hipStream_
   return launch_compress_batched(ws, reinterpret_cast<const BatchPair*>(ws + L.off_desc),
                                  reinterpret_cast<const BatchItem*>(ws + L.off_items),
                                  (int)L.items.size(), reinterpret_cast<int*>(ws + L.off_queue),
-                                 b.cdt, c.lb, c.radix, wgs, L.lds, s);
+                                 b.cdt, c.lb, c.radix, L.desc, wgs, L.lds, s);
 }
 
 // Per-problem work after Compress: partial sums, inverse transform, extract.

@@ -171,6 +171,9 @@ cmm_status launch_reduce_fft_partials(const void* part, int groups, int d, int l
 size_t compress_lds_base(cmm_dtype dt, int lb, int64_t n_rows, int64_t n_cols);
 // The same for the 16-element layout (b_lo = 2^13, 512 threads).
 size_t compress16_lds_base(cmm_dtype dt, int64_t n_rows, int64_t n_cols);
+// LDS of the 16-element kernel with descriptor fix-ups (rows with their 64
+// spare elements, the descriptors); usable when n_rows, n_cols + 64 < 2^15
+size_t compress16_desc_lds(cmm_dtype dt, int64_t n_rows, int64_t n_cols);
 
 // ------------------------------------------------------------ batched form
 // One problem of a batch as the persistent kernel reads it: workspace
@@ -197,6 +200,7 @@ struct BatchItem {
 // to 2^13; 16: b_lo = 2^13).
 cmm_status launch_compress_batched(char* ws, const BatchPair* pairs, const BatchItem* items,
                                    int n_items, int* queue, cmm_dtype dt, int lb, int radix,
+                                   bool desc,
                                    int wgs, size_t lds, hipStream_t s);
 
 // Precision form: MFMA compress (b_lo = 2^14) on bf16 / fp16 rows.

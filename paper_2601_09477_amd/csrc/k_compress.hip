@@ -711,7 +711,7 @@ __global__ __launch_bounds__(512, waves16<T>()) void compress16_kernel(CompressA
 }
 
 // The persistent batched form with the 16-element layout (b_lo = 2^13).
-template <typename T>
+template <typename T, bool DESC>
 __global__ __launch_bounds__(512, waves16<T>()) void compress16_batched_kernel(
     char* __restrict__ ws, const BatchPair* __restrict__ pairs,
     const BatchItem* __restrict__ items, int n_items, int* __restrict__ queue) {
@@ -750,7 +750,7 @@ __global__ __launch_bounds__(512, waves16<T>()) void compress16_batched_kernel(
     const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
     const int64_t k0 = (int64_t)bi.group * k_per;
     const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
-    compress16_unit<T, false, false>(a, (int)bi.group, t, uhi, k0, k1, smem);
+    compress16_unit<T, false, DESC>(a, (int)bi.group, t, uhi, k0, k1, smem);
   }
 }
 
@@ -856,6 +856,16 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   return hip_check(hipGetLastError(), "compress kernel launch");
 }
 
+size_t compress16_desc_lds(cmm_dtype dt, int64_t n_rows, int64_t n_cols) {
+  const size_t xlen = ((size_t)1 << 13) + ((size_t)1 << 7) + 16;
+  const size_t desc = sizeof(uint32_t) * 3 * 2 * kSlots16 * 512;
+  if (dt == CMM_F64)
+    return sizeof(double) * (xlen + (size_t)pitch16<double, true>(n_rows) +
+                             (size_t)pitch16<double, true>(n_cols)) + desc;
+  return sizeof(float) * (xlen + (size_t)pitch16<float, true>(n_rows) +
+                          (size_t)pitch16<float, true>(n_cols)) + desc;
+}
+
 size_t compress16_lds_base(cmm_dtype dt, int64_t n_rows, int64_t n_cols) {
   const size_t xlen = ((size_t)1 << 13) + ((size_t)1 << 7) + 16;
   if (dt == CMM_F64)
@@ -886,9 +896,10 @@ static cmm_status launch_batched_t(char* ws, const BatchPair* pairs, const Batch
 
 template <typename T>
 static cmm_status launch_batched16_t(char* ws, const BatchPair* pairs, const BatchItem* items,
-                                     int n_items, int* queue, int wgs, size_t lds, hipStream_t s) {
+                                     int n_items, int* queue, bool desc, int wgs, size_t lds,
+                                     hipStream_t s) {
   ProfScope prof_("compress", s);
-  auto kern = compress16_batched_kernel<T>;
+  auto kern = desc ? compress16_batched_kernel<T, true> : compress16_batched_kernel<T, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return hip_check(e, "compress (batched): set LDS size");
@@ -898,14 +909,15 @@ static cmm_status launch_batched16_t(char* ws, const BatchPair* pairs, const Bat
 
 cmm_status launch_compress_batched(char* ws, const BatchPair* pairs, const BatchItem* items,
                                    int n_items, int* queue, cmm_dtype dt, int lb, int radix,
-                                   int wgs, size_t lds, hipStream_t s) {
+                                   bool desc, int wgs, size_t lds, hipStream_t s) {
   if (radix == 16) {
     if (lb != 13) {
       set_error("compress (batched): the 16-element layout needs b_lo = 2^13");
       return CMM_EUNSUPPORTED;
     }
-    if (dt == CMM_F64) return launch_batched16_t<double>(ws, pairs, items, n_items, queue, wgs, lds, s);
-    return launch_batched16_t<float>(ws, pairs, items, n_items, queue, wgs, lds, s);
+    if (dt == CMM_F64)
+      return launch_batched16_t<double>(ws, pairs, items, n_items, queue, desc, wgs, lds, s);
+    return launch_batched16_t<float>(ws, pairs, items, n_items, queue, desc, wgs, lds, s);
   }
   if (dt == CMM_F64) {
     switch (lb) {
