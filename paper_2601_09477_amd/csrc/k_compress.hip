@@ -637,15 +637,16 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   }
   for (int64_t k = k0; k < k1; ++k) {
     const bool more = k + 1 < k1;
-    __syncthreads();   // every gather of k is done: the row buffers can be refilled
-    if (more) {
-      if (SINGLE && threadIdx.x == 0) rowA[a.n_rows] = T(0);
-      load_k(k + 1);
-    }
     pass1_16(X);
 #pragma unroll
     for (int e = 0; e < E; ++e) xbuf[wr_t + wr_e(e)] = X[e];
     __syncthreads();
+    // every thread has passed its gathers of k (they fed pass 1): the row
+    // buffers can be refilled with k + 1
+    if (more) {
+      if (SINGLE && threadIdx.x == 0) rowA[a.n_rows] = T(0);
+      load_k(k + 1);
+    }
     // the transposed reads of X overlap pass 1 of Y
 #pragma unroll
     for (int e = 0; e < E; ++e) X[e] = xbuf[rd_t + rd_e(e)];
