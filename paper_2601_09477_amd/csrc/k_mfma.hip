@@ -222,67 +222,134 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   const uint2* lexB = exl + cntA;
   const int32_t* lcsA = reinterpret_cast<const int32_t*>(exl + cntA + cntB);
   const int32_t* lcsB = lcsA + nchA + 1;
-  // Collision descriptors.  Thread tid owns chains tid + j kNT (j < kSlots).
-  // A descriptor (three words in LDS, built once per work unit) holds the
-  // chain's target and its next five rows as 15-bit row indices with their
-  // signs relative to the target (absent rows: the zero pad index n; an
-  // absent chain targets the lane's spare element after the pad):
+  // Collision descriptors.  A descriptor (three words in LDS, built once per
+  // work unit) holds a chain's target and its next five rows as 15-bit row
+  // indices with their signs relative to the target (absent rows: the zero
+  // pad index n; an absent chain targets the lane's spare element after the
+  // pad):
   //   w0 = target | m1 << 15 | s1 << 30 | more << 31
   //   w1 = m2 | m3 << 15 | s2 << 30 | s3 << 31
-  //   w2 = m4 | m5 << 15 | s4 << 30 | s5 << 31
-  // A chain with more rows (a bucket of seven or more: about one in a
-  // million) and chains beyond the slots are finished from the plan's lists.
+  //   w2 = m4 | m5 << 15 | s4 << 30 | s5 << 31, or the chain's index when
+  //        it has more rows (more = 1; the rare pass adds rows 4 onwards)
+  // Slot position pos = tid + j kNT (j < kSlots) takes the chains in an
+  // order with the chains of three or more rows first (stable), so that the
+  // fix-up can read and add the rows past the first two only in the waves
+  // whose positions hold such chains (a wave-uniform test).  A chain with
+  // more than six rows (about one in a million buckets) and chains beyond
+  // the slots are finished from the plan's lists.
   uint32_t* dsc = reinterpret_cast<uint32_t*>(exl);   // [word][operand][slot][kNT]
+  auto dslot = [&](int word, int op, int pos) -> uint32_t& {
+    return dsc[((word * 2 + op) * kSlots + pos / kNT) * kNT + pos % kNT];
+  };
   auto dref = [&](int word, int op, int j) -> uint32_t& {
     return dsc[((word * 2 + op) * kSlots + j) * kNT + threadIdx.x];
   };
+  __shared__ int32_t s_scan[kNT / 64 + 1];
+  int nlong[2] = {0, 0};
+  // position of every chain (longer chains first) by a block-wide scan over
+  // contiguous runs of chains; identity order when the chains exceed the slots
   auto build_desc = [&](int op, const int32_t* gc, const uint2* gp, int nch, uint32_t pad) {
+    const bool ordered = nch <= kSlots * kNT;
+    const int per = (nch + kNT - 1) / kNT;
+    const int c0 = (int)threadIdx.x * per;
+    int mine = 0;
+    if (ordered)
+      for (int c = c0; c < c0 + per && c < nch; ++c) mine += (gc[c + 1] - gc[c] > 1) ? 1 : 0;
+    // exclusive scan of `mine` over the block
+    const uint32_t lane_ = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    int incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off);
+      if ((int)lane_ >= off) incl += y;
+    }
+    if (lane_ == 63u) s_scan[wv] = incl;
+    __syncthreads();
+    int wbase_ = 0, total = 0;
+    for (int q = 0; q < kNT / 64; ++q) {
+      const int x = s_scan[q];
+      if (q < (int)wv) wbase_ += x;
+      total += x;
+    }
+    __syncthreads();   // s_scan is reused by the next operand
+    nlong[op] = ordered ? total : 0;
+    int lpos = wbase_ + incl - mine;                 // next long position
+    int ppos = total + c0 - (wbase_ + incl - mine);  // next pair position
+    // empty slots first: absent chains
     for (int j = 0; j < kSlots; ++j) {
-      const int c = (int)threadIdx.x + j * kNT;
-      uint32_t m[6] = {pad + 1u + (threadIdx.x & 63u), pad, pad, pad, pad, pad};
-      uint32_t sg[6] = {0, 0, 0, 0, 0, 0};
-      uint32_t more = 0;
-      if (c < nch) {
-        const int beg = gc[c], end = gc[c + 1];
-        m[0] = gp[beg].x >> 16;
-        for (int r = 0; r < 5 && beg + r < end; ++r) {
-          const uint2 y = gp[beg + r];
-          m[r + 1] = y.x & 0xFFFFu;
-          sg[r + 1] = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
-        }
-        more = end - beg > 5 ? 1u : 0u;
+      const int pos = (int)threadIdx.x + j * kNT;
+      if (pos >= nch) {
+        dref(0, op, j) = (pad + 1u + (threadIdx.x & 63u)) | (pad << 15);
+        dref(1, op, j) = pad | (pad << 15);
+        dref(2, op, j) = pad | (pad << 15);
       }
-      dref(0, op, j) = m[0] | (m[1] << 15) | (sg[1] << 30) | (more << 31);
-      dref(1, op, j) = m[2] | (m[3] << 15) | (sg[2] << 30) | (sg[3] << 31);
-      dref(2, op, j) = m[4] | (m[5] << 15) | (sg[4] << 30) | (sg[5] << 31);
+    }
+    const int cb = ordered ? c0 : (int)threadIdx.x;
+    const int ce = ordered ? (c0 + per < nch ? c0 + per : nch) : nch;
+    for (int c = cb; c < ce; c += ordered ? 1 : kNT) {
+      const int beg = gc[c], end = gc[c + 1];
+      int pos = c;
+      if (ordered) pos = (end - beg > 1) ? lpos++ : ppos++;
+      if (pos >= kSlots * kNT) continue;
+      uint32_t m[6] = {gp[beg].x >> 16, pad, pad, pad, pad, pad};
+      uint32_t sg[6] = {0, 0, 0, 0, 0, 0};
+      for (int r = 0; r < 5 && beg + r < end; ++r) {
+        const uint2 y = gp[beg + r];
+        m[r + 1] = y.x & 0xFFFFu;
+        sg[r + 1] = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+      }
+      const uint32_t more = end - beg > 5 ? 1u : 0u;
+      dslot(0, op, pos) = m[0] | (m[1] << 15) | (sg[1] << 30) | (more << 31);
+      dslot(1, op, pos) = m[2] | (m[3] << 15) | (sg[2] << 30) | (sg[3] << 31);
+      dslot(2, op, pos) = more ? (uint32_t)c : m[4] | (m[5] << 15) | (sg[4] << 30) | (sg[5] << 31);
     }
   };
   if (DESC) {
     build_desc(0, gcA, gA, nchA, (uint32_t)a.n_rows);
     build_desc(1, gcB, gB, nchB, (uint32_t)a.n_cols);
   }
-  // Fix-ups of both operands from their descriptors, straight-line: every
-  // slot loads its six values, sums them (float32, rank order) and stores
-  // once; a slot with more rows stores to its lane's spare element and is
-  // finished, still rounded once, in the rare pass.
+  // Fix-ups of both operands from their descriptors: every slot adds its
+  // target and first row; the rows past those only in waves whose positions
+  // hold longer chains (all of them when the order is the identity).  The
+  // sum is in float32, in rank order, stored once; a slot with more rows
+  // stores to its lane's spare element and is finished, still rounded once,
+  // in the rare pass.
+  const int wave_pos = (int)(threadIdx.x & ~63u);
   auto fix_desc = [&](const int32_t* gcA_, const uint2* gpA_, const int32_t* gcB_, const uint2* gpB_) {
-    uint32_t q[2][kSlots][3];
-    float v[2][kSlots][6];
+    uint32_t q0[2][kSlots];
     float sum[2][kSlots];
 #pragma unroll
     for (int op = 0; op < 2; ++op)
 #pragma unroll
-      for (int j = 0; j < kSlots; ++j)
-#pragma unroll
-        for (int wd = 0; wd < 3; ++wd) q[op][j][wd] = dref(wd, op, j);
+      for (int j = 0; j < kSlots; ++j) q0[op][j] = dref(0, op, j);
 #pragma unroll
     for (int op = 0; op < 2; ++op) {
       const IN* row = op ? rowB : rowA;
+      const int nl = DESC ? nlong[op] : 0;
+      const int nch_op = op ? nchB : nchA;
+      const bool all_long = nch_op > kSlots * kNT;
 #pragma unroll
-      for (int j = 0; j < kSlots; ++j)
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-          v[op][j][r] = to_f(row[(q[op][j][r >> 1] >> (15 * (r & 1))) & 0x7FFFu]);
+      for (int j = 0; j < kSlots; ++j) {
+        const uint32_t w0 = q0[op][j];
+        const float v0 = to_f(row[w0 & 0x7FFFu]);
+        const float v1 = to_f(row[(w0 >> 15) & 0x7FFFu]);
+        float acc_ = v0 + (((w0 >> 30) & 1u) ? -v1 : v1);
+        if (all_long || wave_pos + j * kNT < nl) {   // wave-uniform
+          const uint32_t w1 = dref(1, op, j), w2 = dref(2, op, j);
+          const float v2 = to_f(row[w1 & 0x7FFFu]), v3 = to_f(row[(w1 >> 15) & 0x7FFFu]);
+          // w2 of a slot with more rows is a chain index (< n, so the reads
+          // stay in the row): its values are not added here
+          const bool mr = (w0 >> 31) != 0u;
+          float v4 = to_f(row[w2 & 0x7FFFu]), v5 = to_f(row[(w2 >> 15) & 0x7FFFu]);
+          v4 = mr ? 0.f : v4;
+          v5 = mr ? 0.f : v5;
+          acc_ = acc_ + (((w1 >> 30) & 1u) ? -v2 : v2);
+          acc_ = acc_ + (((w1 >> 31) & 1u) ? -v3 : v3);
+          acc_ = acc_ + ((!mr && ((w2 >> 30) & 1u)) ? -v4 : v4);
+          acc_ = acc_ + ((!mr && ((w2 >> 31) & 1u)) ? -v5 : v5);
+        }
+        sum[op][j] = acc_;
+      }
     }
     bool rare = false;
 #pragma unroll
@@ -291,18 +358,9 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
       const uint32_t spare = (uint32_t)(op ? a.n_cols : a.n_rows) + 1u + (threadIdx.x & 63u);
 #pragma unroll
       for (int j = 0; j < kSlots; ++j) {
-        float acc_ = v[op][j][0];
-#pragma unroll
-        for (int r = 1; r < 6; ++r) {
-          // sign of member r: w0 bit 30 for r = 1, else bit 30 + (r & 1) of word r / 2
-          const uint32_t word = q[op][j][r >> 1];
-          const uint32_t neg = (r == 1) ? (word >> 30) & 1u : (word >> (30 + (r & 1))) & 1u;
-          acc_ = acc_ + (neg ? -v[op][j][r] : v[op][j][r]);
-        }
-        sum[op][j] = acc_;
-        const bool more = (q[op][j][0] >> 31) != 0u;
+        const bool more = (q0[op][j] >> 31) != 0u;
         rare = rare || more;
-        row[more ? spare : (q[op][j][0] & 0x7FFFu)] = (IN)acc_;
+        row[more ? spare : (q0[op][j] & 0x7FFFu)] = (IN)sum[op][j];
       }
     }
     const bool extra = nchA > kSlots * kNT || nchB > kSlots * kNT;
@@ -313,19 +371,22 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
         const int32_t* gc = op ? gcB_ : gcA_;
         const uint2* gp = op ? gpB_ : gpA_;
         for (int j = 0; j < kSlots; ++j) {
-          if (!(q[op][j][0] >> 31)) continue;
+          if (!(q0[op][j] >> 31)) continue;
+          // a bucket of seven or more rows: the target and rows 1..3 are
+          // summed; the chain index is in w2
+          const uint32_t tgt = q0[op][j] & 0x7FFFu;
+          const int c = (int)dref(2, op, j);
           float acc_ = sum[op][j];
-          const int c = (int)threadIdx.x + j * kNT;
           const int beg = gc[c], end = gc[c + 1];
-          for (int r = beg + 5; r < end; ++r) {
+          for (int r = beg + 3; r < end; ++r) {
             const uint2 y = gp[r];
             const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
             const float w = to_f(row[y.x & 0xFFFFu]);
             acc_ = acc_ + (neg ? -w : w);
           }
-          row[q[op][j][0] & 0x7FFFu] = (IN)acc_;
+          row[tgt] = (IN)acc_;
         }
-        // chains beyond the slots (disjoint targets)
+        // chains beyond the slots (identity order; disjoint targets)
         const int nch = op ? nchB : nchA;
         for (int c = kSlots * kNT + (int)threadIdx.x; c < nch; c += kNT) {
           const int beg = gc[c], end = gc[c + 1];
@@ -371,18 +432,22 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   // tiles (independent MFMAs); result written (rounded) to the transpose buffer
   auto gather_tiles = [&](const unsigned char* rb, const uint32_t (&idx)[NS / 2],
                           vec (&av)[kTiles]) {
-    uint32_t raw[NS];
+    // the two 16-bit values of a slot pair go straight into the low and
+    // high halves of one register (d16 loads), then take their signs
+    typedef __attribute__((ext_vector_type(2))) uint16_t h2;
+    h2 raw[NS / 2];
 #pragma unroll
-    for (int e = 0; e < NS; ++e)
-      raw[e] = *reinterpret_cast<const uint16_t*>(rb + ((idx[e >> 1] >> ((e & 1) * 16)) & 0x7FFFu));
+    for (int q = 0; q < NS / 2; ++q) {
+      raw[q].x = *reinterpret_cast<const uint16_t*>(rb + (idx[q] & 0x7FFFu));
+      raw[q].y = *reinterpret_cast<const uint16_t*>(rb + ((idx[q] >> 16) & 0x7FFFu));
+    }
 #pragma unroll
     for (int c = 0; c < kTiles; ++c) {
       u2 pk;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int e = c * 4 + 2 * h;
-        const uint32_t word = raw[e] | (raw[e + 1] << 16);
-        pk[h] = word ^ (idx[e >> 1] & 0x80008000u);   // folded signs
+        const int q = c * 2 + h;
+        pk[h] = __builtin_bit_cast(uint32_t, raw[q]) ^ (idx[q] & 0x80008000u);   // folded signs
       }
       av[c] = __builtin_bit_cast(vec, pk);
     }
