@@ -452,15 +452,12 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
       av[c] = __builtin_bit_cast(vec, pk);
     }
   };
-  // passes 1-2 of one operand from its staged row; each phase runs over all
-  // tiles (independent MFMAs); the result is written, rounded, to the
+  // passes 1-2 of one operand from its gathered tiles; each phase runs over
+  // all tiles (independent MFMAs); the result is written, rounded, to the
   // transpose buffer
-  auto front = [&](const uint16_t* row16, const uint32_t (&idx)[NS / 2], IN* tb) {
-    const unsigned char* rb = reinterpret_cast<const unsigned char*>(row16);
-    vec av[kTiles];
+  auto front = [&](vec (&av)[kTiles], IN* tb) {
     const f32x4 z = {0.f, 0.f, 0.f, 0.f};
     f32x4 d[kTiles];
-    gather_tiles(rb, idx, av);
 #pragma unroll
     for (int c = 0; c < kTiles; ++c) d[c] = Mf<IN>::mma(av[c], h16, z);
 #pragma unroll
@@ -483,12 +480,14 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
       tb16[taddr((3u << 4) | ((uint32_t)c << 8))] = (uint16_t)(p23 >> 16);
     }
   };
-  // passes 3-4 from the transpose buffer into the final float32 layout
-  auto back = [&](const IN* tb, f32x4 (&out)[kTiles]) {
-    vec av[kTiles];
+  // the transposed tiles of one operand (8-byte reads)
+  auto load_back = [&](const IN* tb, vec (&av)[kTiles]) {
 #pragma unroll
     for (int c = 0; c < kTiles; ++c)
       av[c] = *reinterpret_cast<const vec*>(tb + rbase + taddr((uint32_t)c << 2));
+  };
+  // passes 3-4 into the final float32 layout
+  auto back = [&](vec (&av)[kTiles], f32x4 (&out)[kTiles]) {
     const f32x4 z = {0.f, 0.f, 0.f, 0.f};
     f32x4 d[kTiles];
 #pragma unroll
@@ -540,13 +539,25 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
       }
       __syncthreads();
     }
-    front(rowA16, idxA, tbufX);
-    front(rowB16, idxB, tbufY);
+    // both operands' gathers are issued before either's matrix passes, so
+    // the loads of one overlap the MFMAs of the other
+    {
+      vec avX[kTiles], avY[kTiles];
+      gather_tiles(reinterpret_cast<const unsigned char*>(rowA16), idxA, avX);
+      gather_tiles(reinterpret_cast<const unsigned char*>(rowB16), idxB, avY);
+      front(avX, tbufX);
+      front(avY, tbufY);
+    }
     __syncthreads();   // gathers done (rows free), transpose buffers written
     if (k + 1 < k1) load_k(k + 1);
     f32x4 X[kTiles], Y[kTiles];
-    back(tbufX, X);
-    back(tbufY, Y);
+    {
+      vec bvX[kTiles], bvY[kTiles];
+      load_back(tbufX, bvX);
+      load_back(tbufY, bvY);
+      back(bvX, X);
+      back(bvY, Y);
+    }
 #pragma unroll
     for (int c = 0; c < kTiles; ++c)
 #pragma unroll
