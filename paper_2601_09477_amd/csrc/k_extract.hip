@@ -14,6 +14,10 @@ namespace {
 constexpr int kCols = 256;
 constexpr int kRows = 8;
 
+// Rows of a tile whose d candidates are gathered together (all of them up to
+// d = 11; beyond, the tile is taken in two halves to stay within registers).
+__host__ __device__ constexpr int rows_per_round(int d) { return d <= 11 ? kRows : kRows / 2; }
+
 // Entry of (i, j) from the two table entries: the bucket in the low bits
 // (the caller masks with b - 1), the sign product in bit 31.  The xor form
 // (Section 3.2) xors the buckets; Pagh's FFT form (Section 3.1) adds them
@@ -48,34 +52,38 @@ __global__ __launch_bounds__(kCols) void extract_kernel(
   const int64_t b = (int64_t)1 << log2b;
   const uint32_t bmask = (uint32_t)(b - 1);
   const bool jok = j < n_cols;
-  double v[kRows][D];
+  constexpr int RG = rows_per_round(D);
 #pragma unroll
-  for (int t = 0; t < D; ++t) {
-    const uint32_t e2 = jok ? tab2[(size_t)t * n_cols + j] : 0u;
-    const double* pt = p + (size_t)t * b;
+  for (int g = 0; g < kRows; g += RG) {
+    double v[RG][D];
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-      const int64_t i = i0 + r < n_rows ? i0 + r : n_rows - 1;
-      const uint32_t e = combine<CYC>(tab1[(size_t)t * n_rows + i], e2);
-      const double x = pt[e & bmask];
-      v[r][t] = (e & kSignBit) ? -x : x;
+    for (int t = 0; t < D; ++t) {
+      const uint32_t e2 = jok ? tab2[(size_t)t * n_cols + j] : 0u;
+      const double* pt = p + (size_t)t * b;
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        const int64_t i = i0 + g + r < n_rows ? i0 + g + r : n_rows - 1;
+        const uint32_t e = combine<CYC>(tab1[(size_t)t * n_rows + i], e2);
+        const double x = pt[e & bmask];
+        v[r][t] = (e & kSignBit) ? -x : x;
+      }
     }
-  }
-  if (!jok) return;
+    if (!jok) return;
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) {
-    if (i0 + r >= n_rows) break;
-    double out;
-    if (mean) {
-      double s = 0.0;
+    for (int r = 0; r < RG; ++r) {
+      if (i0 + g + r >= n_rows) return;
+      double out;
+      if (mean) {
+        double s = 0.0;
 #pragma unroll
-      for (int t = 0; t < D; ++t) s += v[r][t];
-      out = s / D;
-    } else {
-      sort_net<D>(v[r]);
-      out = v[r][D / 2];
+        for (int t = 0; t < D; ++t) s += v[r][t];
+        out = s / D;
+      } else {
+        sort_net<D>(v[r]);
+        out = v[r][D / 2];
+      }
+      C[(i0 + g + r) * ldc + j] = (OutT)out;
     }
-    C[(i0 + r) * ldc + j] = (OutT)out;
   }
 }
 
@@ -158,43 +166,47 @@ __global__ __launch_bounds__(kCols) void heavy_kernel(
   const uint32_t bmask = (uint32_t)(b - 1);
   const bool jok = j < n_cols;
   const uint32_t lane = threadIdx.x & 63;
-  double v[kRows][D];
+  constexpr int RG = rows_per_round(D);
 #pragma unroll
-  for (int t = 0; t < D; ++t) {
-    const uint32_t e2 = jok ? tab2[(size_t)t * n_cols + j] : 0u;
-    const double* pt = p + (size_t)t * b;
+  for (int g = 0; g < kRows; g += RG) {
+    double v[RG][D];
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-      const int64_t i = i0 + r < n_rows ? i0 + r : n_rows - 1;
-      const uint32_t e = tab1[(size_t)t * n_rows + i] ^ e2;
-      const double x = pt[e & bmask];
-      v[r][t] = (e & kSignBit) ? -x : x;
+    for (int t = 0; t < D; ++t) {
+      const uint32_t e2 = jok ? tab2[(size_t)t * n_cols + j] : 0u;
+      const double* pt = p + (size_t)t * b;
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        const int64_t i = i0 + g + r < n_rows ? i0 + g + r : n_rows - 1;
+        const uint32_t e = tab1[(size_t)t * n_rows + i] ^ e2;
+        const double x = pt[e & bmask];
+        v[r][t] = (e & kSignBit) ? -x : x;
+      }
     }
-  }
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) {
-    double o;
-    if (mean) {
-      double s = 0.0;
+    for (int r = 0; r < RG; ++r) {
+      double o;
+      if (mean) {
+        double s = 0.0;
 #pragma unroll
-      for (int t = 0; t < D; ++t) s += v[r][t];
-      o = s / D;
-    } else {
-      sort_net<D>(v[r]);
-      o = v[r][D / 2];
-    }
-    const bool hit = jok && (i0 + r < n_rows) && fabs(o) >= thr;
-    const unsigned long long mask = __ballot(hit);   // every lane of the wave takes part
-    if (mask == 0ull) continue;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(mask));
-    base = __shfl(base, 0);
-    if (hit) {
-      const unsigned long long slot = base + __popcll(mask & ((1ull << lane) - 1ull));
-      if (slot < (unsigned long long)capacity) {
-        out_rows[slot] = i0 + r;
-        out_cols[slot] = j;
-        out_vals[slot] = (OutT)o;
+        for (int t = 0; t < D; ++t) s += v[r][t];
+        o = s / D;
+      } else {
+        sort_net<D>(v[r]);
+        o = v[r][D / 2];
+      }
+      const bool hit = jok && (i0 + g + r < n_rows) && fabs(o) >= thr;
+      const unsigned long long mask = __ballot(hit);   // every lane of the wave takes part
+      if (mask == 0ull) continue;
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+      base = __shfl(base, 0);
+      if (hit) {
+        const unsigned long long slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (slot < (unsigned long long)capacity) {
+          out_rows[slot] = i0 + g + r;
+          out_cols[slot] = j;
+          out_vals[slot] = (OutT)o;
+        }
       }
     }
   }
@@ -273,29 +285,42 @@ __global__ __launch_bounds__(256) void extract_reps_kernel(
 
 // Correctness counters of the evaluation protocol over the dense grid:
 // c[1] += #{|C_hat| <= thr}, c[3] += #{|C_hat - C| <= tol} (every entry;
-// the big entries are taken out again by correctness_big_kernel).  Counts
-// per wave by ballot, one atomic add per wave and counter (integer adds:
-// the totals do not depend on the order).
+// the big entries are taken out again by correctness_big_kernel).  A thread
+// counts its column over a strided set of rows; the block sums the threads'
+// counts and adds them with one atomic per counter (integer adds: the
+// totals do not depend on the order).  The grid is a few thousand blocks,
+// so the atomics on the two counters stay few.
 template <typename InT>
 __global__ __launch_bounds__(256) void correctness_dense_kernel(
     const InT* __restrict__ C_hat, int64_t ldh, const double* __restrict__ C, int64_t ldc,
     int64_t n_rows, int64_t n_cols, double thr, double tol, unsigned long long* __restrict__ c) {
+  __shared__ unsigned long long part[2][4];
   const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
-  const bool jok = j < n_cols;
-  unsigned long long le = 0, close = 0;
-  for (int64_t i = blockIdx.x; i < n_rows; i += gridDim.x) {
-    bool a = false, bcl = false;
-    if (jok) {
+  uint32_t le = 0, close = 0;
+  if (j < n_cols) {
+#pragma unroll 4
+    for (int64_t i = blockIdx.x; i < n_rows; i += gridDim.x) {
       const double h = (double)C_hat[i * ldh + j];
-      a = fabs(h) <= thr;
-      bcl = fabs(h - C[i * ldc + j]) <= tol;
+      le += fabs(h) <= thr ? 1u : 0u;
+      close += fabs(h - C[i * ldc + j]) <= tol ? 1u : 0u;
     }
-    le += __popcll(__ballot(a));
-    close += __popcll(__ballot(bcl));
   }
+  unsigned long long a = le, bcl = close;
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off);
+    bcl += __shfl_xor(bcl, off);
+  }
+  const int wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    if (le) atomicAdd(c + 1, le);
-    if (close) atomicAdd(c + 3, close);
+    part[0][wv] = a;
+    part[1][wv] = bcl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long sa = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+    const unsigned long long sc = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    if (sa) atomicAdd(c + 1, sa);
+    if (sc) atomicAdd(c + 3, sc);
   }
 }
 
@@ -358,6 +383,11 @@ cmm_status run(const double* p, const uint32_t* tab1, const uint32_t* tab2, int 
     CMM_EXTRACT_CASE(7)
     CMM_EXTRACT_CASE(9)
     CMM_EXTRACT_CASE(11)
+    CMM_EXTRACT_CASE(13)
+    CMM_EXTRACT_CASE(15)
+    CMM_EXTRACT_CASE(17)
+    CMM_EXTRACT_CASE(19)
+    CMM_EXTRACT_CASE(21)
     default:
       hipLaunchKernelGGL((extract_generic_kernel<OutT, CYC>), grid, dim3(kCols), 0, s, p, tab1, tab2, d,
                          n_rows, n_cols, log2b, mean, C, ldc);
@@ -426,6 +456,11 @@ static cmm_status heavy_run(const double* p, const uint32_t* tab1, const uint32_
     CMM_HEAVY_CASE(7)
     CMM_HEAVY_CASE(9)
     CMM_HEAVY_CASE(11)
+    CMM_HEAVY_CASE(13)
+    CMM_HEAVY_CASE(15)
+    CMM_HEAVY_CASE(17)
+    CMM_HEAVY_CASE(19)
+    CMM_HEAVY_CASE(21)
     default:
       hipLaunchKernelGGL(heavy_generic_kernel<OutT>, grid, dim3(kCols), 0, s, p, tab1, tab2, d,
                          n_rows, n_cols, log2b, mean, thr, rows, cols, vals, capacity, count);
@@ -483,7 +518,9 @@ static cmm_status correctness_run(const InT* C_hat, int64_t ldh, const double* C
     return CMM_EUNSUPPORTED;
   }
   if (n_rows > 0 && n_cols > 0) {
-    const int64_t gx = n_rows < 2048 ? n_rows : 2048;
+    // about 4096 blocks in all: each thread then covers n_rows / gx rows
+    const int64_t want = (4096 + gy - 1) / gy;
+    const int64_t gx = n_rows < want ? n_rows : want;
     hipLaunchKernelGGL(correctness_dense_kernel<InT>, dim3((unsigned)gx, (unsigned)gy), dim3(256),
                        0, s, C_hat, ldh, C, ldc, n_rows, n_cols, thr, tol, c);
     cmm_status st = hip_check(hipGetLastError(), "correctness kernel launch");

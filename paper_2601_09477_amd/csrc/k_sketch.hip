@@ -1,78 +1,170 @@
 // Standalone count sketch (Algorithm 1, the two sketch loops of Compress).
 //
-// One wavefront owns one output vector (t, kk) and accumulates it in an LDS
-// window of kWin buckets, sweeping the bucket range window by window.  Input
-// indices are consumed 64 at a time in ascending order; lanes of a group
-// that hit the same bucket are applied in lane order (rank rounds), so every
-// bucket receives its terms in ascending index order -- the result does not
-// depend on scheduling and equals a sequential left-to-right sum.
+// A work-group owns one repetition t, one window of W <= 1024 consecutive
+// buckets and a run of tiles of KT consecutive inner indices k.  It scans
+// the hash table of t once, keeps the indices that land in its window as a
+// list in LDS (ascending index order), and ranks equal buckets in that
+// order.  Each tile then accumulates its KT x W sketch values in LDS, rank
+// level by rank level (the terms of one bucket are added in ascending index
+// order, so the result equals a sequential left-to-right sum and does not
+// depend on scheduling), and streams them to HBM with coalesced stores.
+// The list is built once per work-group when the window's hits fit it
+// (always, unless b is small against n); otherwise it is rebuilt segment by
+// segment for every tile.
 #include "cmm_internal.h"
 
 namespace cmm {
 namespace {
 
-constexpr int kWaves = 4;
+constexpr int kSkThreads = 256;
+constexpr int kSkLogW = 10;       // at most 1024 buckets per window
+constexpr int kSkHC = 2048;       // hit-list capacity
+constexpr int kSkChunk = 1024;    // indices scanned per step (4 per thread)
+constexpr int kSkTarget = 4096;   // work-groups aimed for (the tiles are split to reach it)
+constexpr int32_t kSkNone = 0x7FFFFFFF;
 
 template <typename T>
-struct SketchWin { static constexpr int value = 4096; };       // 32 KB of f64 per wave
-template <>
-struct SketchWin<float> { static constexpr int value = 8192; };  // 32 KB of f32 per wave
+struct SkTile { static constexpr int value = sizeof(T) == 8 ? 4 : 8; };   // 32 KB of LDS
 
 template <typename T>
-__global__ __launch_bounds__(64 * kWaves) void sketch_kernel(
+__global__ __launch_bounds__(kSkThreads) void sketch_kernel(
     int side, const T* __restrict__ M, int64_t ld, const uint32_t* __restrict__ tab,
-    int64_t n_idx, int log2b, int64_t k0, int64_t kc, int d, T* __restrict__ out) {
-  constexpr int W = SketchWin<T>::value;
-  __shared__ T win[kWaves][W];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t col = (int64_t)blockIdx.x * kWaves + wv;   // t * kc + kk
-  if (col >= (int64_t)d * kc) return;                      // whole wave exits together
-  const int t = (int)(col / kc);
-  const int64_t kk = col - (int64_t)t * kc;
+    int64_t n_idx, int log2b, int log2w, int64_t nwin, int64_t tiles_per_group, int64_t k0,
+    int64_t kc, int d, T* __restrict__ out) {
+  constexpr int KT = SkTile<T>::value;
+  __shared__ T acc[KT << kSkLogW];           // [kk][bucket in window]
+  __shared__ uint32_t hidx[kSkHC];           // hit index
+  __shared__ uint32_t hkey[kSkHC];           // bucket in window | rank << 16 | sign bit
+  __shared__ int32_t tag[1 << kSkLogW];
+  __shared__ int32_t wsum[4][kSkThreads / 64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int64_t lin = blockIdx.x;
+  const int64_t w = lin % nwin;
+  const int t = (int)((lin / nwin) % d);
+  const int64_t grp = lin / (nwin * d);
+  const int W = 1 << log2w;
   const int64_t b = (int64_t)1 << log2b;
-  const int win_bits = log2b < 12 ? log2b : (sizeof(T) == 8 ? 12 : 13);
-  const int64_t wlen = (int64_t)1 << win_bits;
+  const uint32_t bmask = (uint32_t)(b - 1);
   const uint32_t* tb = tab + (size_t)t * n_idx;
-  T* dst = out + (size_t)col * b;
-  T* lds = win[wv];
+  const int64_t ntiles = (kc + KT - 1) / KT;
+  const int64_t kt0 = grp * tiles_per_group;
+  const int64_t kt1 = kt0 + tiles_per_group < ntiles ? kt0 + tiles_per_group : ntiles;
 
-  for (int64_t w0 = 0; w0 < b; w0 += wlen) {
-    for (int64_t x = lane; x < wlen; x += 64) lds[x] = T(0);
-    for (int64_t g0 = 0; g0 < n_idx; g0 += 64) {
-      const int64_t idx = g0 + lane;
-      uint32_t key = 0xFFFFFFFFu;   // lanes outside the window never match a bucket
-      T v = T(0);
-      if (idx < n_idx) {
-        const uint32_t e = tb[idx];
-        const int64_t x = (int64_t)(e & (uint32_t)(b - 1));
-        if (x >= w0 && x < w0 + wlen) {
-          key = (uint32_t)(x - w0);
-          const T m = side == 0 ? M[idx * ld + (k0 + kk)] : M[(k0 + kk) * ld + idx];
-          v = (e & kSignBit) ? -m : m;
+  for (int e = tid; e < (KT << log2w); e += kSkThreads) acc[e] = T(0);
+  for (int e = tid; e < W; e += kSkThreads) tag[e] = kSkNone;
+  __syncthreads();
+
+  // Hit list of the indices from pos on, in ascending order, until it could
+  // overflow; cnt is the list length (the same in every thread).  Returns the
+  // first index not scanned.
+  auto build = [&](int64_t pos, int& cnt) -> int64_t {
+    cnt = 0;
+    int64_t c0 = pos;
+    for (; c0 < n_idx && cnt + kSkChunk <= kSkHC; c0 += kSkChunk) {
+      uint32_t e[4];
+      bool hit[4];
+      unsigned long long m[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t idx = c0 + q * kSkThreads + tid;
+        e[q] = idx < n_idx ? tb[idx] : 0u;
+        hit[q] = idx < n_idx && (int64_t)((e[q] & bmask) >> log2w) == w;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        m[q] = __ballot(hit[q]);
+        if (lane == 0) wsum[q][wv] = __popcll(m[q]);
+      }
+      __syncthreads();
+      int base = cnt;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int off = base;
+        for (int v = 0; v < wv; ++v) off += wsum[q][v];
+        for (int v = 0; v < kSkThreads / 64; ++v) base += wsum[q][v];
+        if (hit[q]) {
+          const int h = off + __popcll(m[q] & ((1ull << lane) - 1ull));
+          hidx[h] = (uint32_t)(c0 + q * kSkThreads + tid);
+          hkey[h] = ((e[q] & bmask) & (uint32_t)(W - 1)) | (e[q] & kSignBit);
         }
       }
-      // rank = number of lower lanes with the same key
-      int rank = 0;
-      int any = 0;
-      for (int j = 0; j < 64; ++j) {
-        const uint32_t kj = (uint32_t)__builtin_amdgcn_readlane((int)key, j);
-        any |= (kj != 0xFFFFFFFFu);
-        rank += (j < lane && kj == key) ? 1 : 0;
-      }
-      if (!any) continue;
-      int maxr = rank;
-      for (int off = 32; off >= 1; off >>= 1) {
-        const int o = __shfl_xor(maxr, off);
-        maxr = o > maxr ? o : maxr;
-      }
-      for (int r = 0; r <= maxr; ++r) {
-        // LDS accesses of one wavefront complete in program order, so round
-        // r + 1 reads what round r wrote.
-        if (key != 0xFFFFFFFFu && rank == r) lds[key] = lds[key] + v;
-      }
+      cnt = base;
+      __syncthreads();   // wsum read everywhere before the next step writes it
     }
-    for (int64_t x = lane; x < wlen; x += 64) dst[w0 + x] = lds[x];
+    return c0 < n_idx ? c0 : n_idx;
+  };
+
+  // Ranks the list: the rank of an entry is the number of earlier entries
+  // with the same bucket.  Round r gives rank r to the first unranked entry
+  // of every bucket.  Returns the number of ranks.
+  auto rank_list = [&](int cnt) -> int {
+    if (cnt == 0) return 0;
+    uint32_t pend = 0;   // bit s: entry tid + s * kSkThreads is unranked
+    for (int s = 0; tid + s * kSkThreads < cnt; ++s) pend |= 1u << s;
+    for (int round = 0;; ++round) {
+      for (int s = 0; tid + s * kSkThreads < cnt; ++s)
+        if ((pend >> s) & 1u) {
+          const int h = tid + s * kSkThreads;
+          atomicMin(&tag[hkey[h] & 0xFFFFu], h);
+        }
+      __syncthreads();
+      uint32_t won = 0;
+      for (int s = 0; tid + s * kSkThreads < cnt; ++s)
+        if ((pend >> s) & 1u) {
+          const int h = tid + s * kSkThreads;
+          if (tag[hkey[h] & 0xFFFFu] == h) won |= 1u << s;
+        }
+      __syncthreads();   // every thread read its tags before they are reset
+      for (int s = 0; tid + s * kSkThreads < cnt; ++s)
+        if ((won >> s) & 1u) {
+          const int h = tid + s * kSkThreads;
+          tag[hkey[h] & 0xFFFFu] = kSkNone;
+          hkey[h] |= (uint32_t)round << 16;
+        }
+      pend &= ~won;
+      if (!__syncthreads_or(pend != 0u)) return round + 1;
+    }
+  };
+
+  const int64_t kdim = side == 0 ? 1 : ld;   // stride of M along k
+  const int64_t idim = side == 0 ? ld : 1;   // stride of M along the sketched index
+  bool single = false;
+  int cnt = 0, levels = 0;
+  for (int64_t kt = kt0; kt < kt1; ++kt) {
+    const int64_t kb = kt * KT;
+    int64_t pos = 0;
+    do {
+      if (!single) {
+        const int64_t next = build(pos, cnt);
+        levels = rank_list(cnt);
+        single = pos == 0 && next >= n_idx;
+        pos = next;
+      } else {
+        pos = n_idx;
+      }
+      for (int r = 0; r < levels; ++r) {
+        for (int e = tid; e < cnt * KT; e += kSkThreads) {
+          const int h = e / KT;
+          const int kk = e - h * KT;
+          const uint32_t hk = hkey[h];
+          if ((int)((hk >> 16) & 0x7FFFu) != r || kb + kk >= kc) continue;
+          const T m = M[(int64_t)hidx[h] * idim + (k0 + kb + kk) * kdim];
+          acc[(kk << log2w) + (hk & 0xFFFFu)] += (hk & kSignBit) ? -m : m;
+        }
+        __syncthreads();
+      }
+    } while (pos < n_idx);
+    // stream the tile out and clear it for the next one
+    for (int e = tid; e < (KT << log2w); e += kSkThreads) {
+      const int kk = e >> log2w;
+      const int x = e & (W - 1);
+      const T v = acc[e];
+      acc[e] = T(0);
+      if (kb + kk < kc) out[((size_t)t * kc + kb + kk) * b + w * W + x] = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -83,15 +175,25 @@ cmm_status launch_sketch(int side, const void* M, cmm_dtype dt, int64_t rows, in
                          int64_t kc, void* out, hipStream_t s) {
   ProfScope prof_("sketch", s);
   const int64_t n_idx = side == 0 ? rows : cols;
-  const int64_t ncol = (int64_t)d * kc;
-  const int64_t blocks = (ncol + kWaves - 1) / kWaves;
-  if (blocks > 0x7FFFFFFF) return invalid("cmm_sketch: d * kc too large");
+  const int log2w = log2b < kSkLogW ? log2b : kSkLogW;
+  const int64_t nwin = (int64_t)1 << (log2b - log2w);
+  const int kt = dt == CMM_F64 ? SkTile<double>::value : SkTile<float>::value;
+  const int64_t ntiles = (kc + kt - 1) / kt;
+  const int64_t base = (int64_t)d * nwin;
+  int64_t groups = (kSkTarget + base - 1) / base;
+  if (groups > ntiles) groups = ntiles;
+  const int64_t per = (ntiles + groups - 1) / groups;
+  groups = (ntiles + per - 1) / per;
+  const int64_t blocks = base * groups;
+  if (blocks > 0x7FFFFFFF) return invalid("cmm_sketch: d * 2^log2b too large");
   if (dt == CMM_F64)
-    hipLaunchKernelGGL(sketch_kernel<double>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s,
-                       side, (const double*)M, ld, tab, n_idx, log2b, k0, kc, d, (double*)out);
+    hipLaunchKernelGGL(sketch_kernel<double>, dim3((unsigned)blocks), dim3(kSkThreads), 0, s,
+                       side, (const double*)M, ld, tab, n_idx, log2b, log2w, nwin, per, k0, kc,
+                       d, (double*)out);
   else
-    hipLaunchKernelGGL(sketch_kernel<float>, dim3((unsigned)blocks), dim3(64 * kWaves), 0, s,
-                       side, (const float*)M, ld, tab, n_idx, log2b, k0, kc, d, (float*)out);
+    hipLaunchKernelGGL(sketch_kernel<float>, dim3((unsigned)blocks), dim3(kSkThreads), 0, s,
+                       side, (const float*)M, ld, tab, n_idx, log2b, log2w, nwin, per, k0, kc,
+                       d, (float*)out);
   return hip_check(hipGetLastError(), "sketch kernel launch");
 }
 

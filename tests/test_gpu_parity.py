@@ -41,7 +41,10 @@ def test_hash_bit_exact(d, n_rows, n_cols, log2b):
 # --------------------------------------------------------------- sketch
 @pytest.mark.parametrize("side", [0, 1])
 @pytest.mark.parametrize("rows,cols,log2b,k0,kc", [
-    (37, 19, 5, 0, 19), (300, 129, 14, 7, 100), (130, 260, 13, 250, 10), (64, 64, 3, 0, 64)])
+    (37, 19, 5, 0, 19), (300, 129, 14, 7, 100), (130, 260, 13, 250, 10), (64, 64, 3, 0, 64),
+    # more hits per window than one hit list holds (segments), and one
+    # window of two buckets (long rank chains)
+    (5000, 40, 4, 3, 30), (3000, 9, 1, 0, 9)])
 def test_sketch_f64_bit_exact(side, rows, cols, log2b, k0, kc):
     if side == 1:
         rows, cols = cols, rows   # B is n_inner x n_cols
@@ -117,7 +120,7 @@ def test_accumulate_bit_exact():
 
 
 # -------------------------------------------------------------- extract
-@pytest.mark.parametrize("d", [1, 3, 5, 7, 9, 11, 13])
+@pytest.mark.parametrize("d", [1, 3, 5, 7, 9, 11, 13, 15, 17, 21, 23])
 @pytest.mark.parametrize("estimator", ["median", "mean"])
 def test_extract_bit_exact(d, estimator):
     announce(f"extract d={d} {estimator}")
