@@ -8,7 +8,9 @@ Default workload: n = 4096, b = 2^16, d = 9, float64, +-1 entries with
 4096 planted pairs A[i] = 4 B[:, j] (synthetic).  The metric is the
 DGEMM-equivalent rate 2 n^3 / t, reported with heavy-hitter recall; the
 fused compress kernel is reported against the FP64 VALU add roofline, and
-the CPU oracle is timed on the host beside it.  Beside it: the precision
+the CPU oracle is timed on the host beside it.  The C-ABI steps are also
+timed one call at a time (the unfused pipeline) against the HBM roofline.
+Beside it: the precision
 form (bf16 / fp16 on MFMA, n = 8192), the batched form (64 uneven pairs in
 one persistent launch, autotuned, graph replays) and the differentiation
 form (forward + adjoint at n = 2048).
@@ -162,6 +164,77 @@ def heavy_hitter_extract(w, p, steps: int) -> dict:
     ms, n = cmm.cmm_profile_query("extract_heavy")
     cmm.cmm_profile_enable(False)
     return {"threshold": w.tau, "hits": int(count.item()), "ms": ms / max(1, n)}
+
+
+HBM_PEAK_GBS = 8000.0
+
+
+def unfused_steps(w, steps: int, warmup: int, kc: int = 64) -> dict:
+    """The C-ABI steps one call at a time on the headline workload: hash,
+    the sketches of A and B for one chunk of kc values of k, their forward
+    transforms, the accumulate, the inverse transform and the dense extract.
+    Each is reported against the HBM roofline with its algorithmic bytes
+    (every input read once, every output written once), and the chunk's
+    sketch + transform + accumulate time is scaled to all n values of k to
+    set the unfused Compress beside the fused kernel."""
+    import torch
+
+    import paper_2601_09477_amd as cmm
+    n, d, log2b = w.n, w.d, w.log2b
+    b = 1 << log2b
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    B = torch.from_numpy(w.B).to(dev)
+    keys = cmm.keys_tensor(w.keys, dev)
+    tab1 = torch.empty((d, n), dtype=torch.int32, device=dev)
+    tab2 = torch.empty_like(tab1)
+    X = torch.empty((d, kc, b), dtype=torch.float64, device=dev)
+    Y = torch.empty_like(X)
+    p_hat = torch.zeros((d, b), dtype=torch.float64, device=dev)
+    C_hat = torch.empty((n, n), dtype=torch.float64, device=dev)
+
+    def step():
+        cmm.cmm_hash(keys, d, n, n, log2b, tab1, tab2)
+        cmm.cmm_sketch(0, A, n, n, n, tab1, d, log2b, 0, kc, X)
+        cmm.cmm_sketch(1, B, n, n, n, tab2, d, log2b, 0, kc, Y)
+        cmm.cmm_fwht(X, d * kc, log2b)
+        cmm.cmm_fwht(Y, d * kc, log2b)
+        cmm.cmm_accumulate(X, Y, d, kc, log2b, p_hat)
+        cmm.cmm_fwht(p_hat, d, log2b, 2.0 ** -log2b)
+        cmm.cmm_extract(p_hat, tab1, tab2, d, n, n, log2b, cmm.CMM_MEDIAN, C_hat)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    cmm.cmm_profile_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = {k: cmm.cmm_profile_query(k)[0] / steps
+          for k in ("hash", "sketch", "fwht", "accumulate", "extract")}
+    cmm.cmm_profile_enable(False)
+    vec = d * kc * b * 8                      # one operand's chunk of sketches
+    algo = {"hash": 2 * d * n * 4,
+            "sketch": 2 * (n * kc * 8 + vec),
+            "fwht": 2 * 2 * vec + 2 * d * b * 8,
+            "accumulate": 2 * vec + 2 * d * b * 8,
+            "extract": n * n * 8 + d * b * 8 + 2 * d * n * 4}
+    # a transform of length 2^log2b >= 4096 makes 1 + ceil((log2b - 12) / 4)
+    # passes through HBM (12 bits, then 4 at a time)
+    passes = 1 + (max(0, log2b - 12) + 3) // 4
+    rows = {}
+    for k, t in ms.items():
+        gbs = algo[k] / (t * 1e-3) / 1e9
+        rows[k] = {"ms": t, "algorithmic_bytes": algo[k], "GB_per_s": gbs,
+                   "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    rows["fwht"]["passes"] = passes
+    rows["fwht"]["pass_GB_per_s"] = passes * rows["fwht"]["GB_per_s"]
+    rows["fwht"]["pass_frac_of_hbm_peak"] = passes * rows["fwht"]["frac_of_hbm_peak"]
+    chunk = ms["sketch"] + ms["fwht"] + ms["accumulate"]
+    return {"workload": f"planted +-1, n={n}, b=2^{log2b}, d={d}; one chunk of kc={kc} values of k",
+            "kernels": rows,
+            "note": "fwht = two forward transforms of d*kc vectors and the inverse of d vectors",
+            "unfused_compress_ms_all_k": chunk * n / kc}
 
 
 def precision_form(steps: int, warmup: int) -> dict:
@@ -503,6 +576,7 @@ def main() -> int:
     ms_per_step, kern, C_hat, p = run_estimate(w, "f64", args.steps, args.warmup)
     rec = planted_recall(C_hat.cpu().numpy(), w.rows, w.cols, w.tau)
     heavy = heavy_hitter_extract(w, p, args.steps)
+    unfused = unfused_steps(w, max(3, args.steps // 2), 1)
     ms_comp, n_comp = kern["compress"]
     avg_comp = ms_comp / max(1, n_comp) * 1e-3
     ops = compress_ops(n, d, log2b)
@@ -521,6 +595,7 @@ def main() -> int:
                    "tau": w.tau},
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
         "heavy_hitter_extract": heavy,
+        "unfused_steps": unfused,
         "roofline": {"kernel": "compress (fused sketch + WHT + accumulate)", "bound": "alu",
                      "achieved": achieved / 1e12, "peak": PEAK_F64_ADD / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_F64_ADD,

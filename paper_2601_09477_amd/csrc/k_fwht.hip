@@ -1,12 +1,17 @@
 // Standalone in-place Walsh-Hadamard transform of batched vectors in HBM
 // (Section 3.2: +-1 butterflies only, natural order, in place).
 //
-// The log2b index bits are processed in passes through HBM.  A pass owns a
-// bit range [s, s + P) and moves tiles of 2^P x W elements (W consecutive
-// low indices, so every global access is a run of W contiguous elements)
-// through LDS; inside the tile the P bits are done as radix-16 (or smaller)
-// butterflies in registers, one LDS round trip per 4 bits.  The final pass
-// applies the power-of-two scale.
+// The log2b index bits are processed in passes through HBM; the final pass
+// applies the power-of-two scale.  For b >= 4096:
+//  * the low 12 bits in one pass over tiles of 4096 contiguous elements: the
+//    top 4 tile bits as radix-16 in registers straight from global memory
+//    (coalesced), the middle 4 and the low 4 through LDS, then vector stores;
+//  * every further 4 bits (or fewer) in a register-only pass: a thread owns
+//    one column of 2^P elements at stride 2^s, and consecutive threads own
+//    consecutive columns, so every access is coalesced.
+// Shorter vectors take the general pass: a bit range [s, s + P) over tiles of
+// 2^P x W elements (W consecutive low indices) moved through LDS, one LDS
+// round trip per 4 bits.
 #include "cmm_internal.h"
 
 namespace cmm {
@@ -104,7 +109,117 @@ __global__ __launch_bounds__(kThreads) void fwht_pass_kernel(T* __restrict__ x, 
 }
 
 template <typename T>
+__device__ __forceinline__ void radix16(T (&v)[16]) {
+#pragma unroll
+  for (int h = 1; h < 16; h <<= 1) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if ((i & h) == 0) {
+        const T a = v[i], c = v[i + h];
+        v[i] = a + c;
+        v[i + h] = a - c;
+      }
+    }
+  }
+}
+
+template <typename T> struct Pair;
+template <> struct Pair<double> { typedef double2 type; };
+template <> struct Pair<float> { typedef float2 type; };
+
+// Low 12 bits of vectors of length >= 4096: one work-group per tile of 4096
+// contiguous elements (element e of the tile at x[tile * 4096 + e]).
+// VEC: x is aligned to two elements, so the stores go out in pairs.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(kThreads) void fwht_low12_kernel(T* __restrict__ x, T scale,
+                                                              int apply_scale) {
+  __shared__ T lds[(1 << kTileBits) + (1 << (kTileBits - 4))];
+  T* xt = x + ((int64_t)blockIdx.x << kTileBits);
+  const int tid = threadIdx.x;
+  T v[16];
+  // bits 8..11: element tid + 256 r
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = xt[tid + (r << 8)];
+  radix16(v);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) lds[pad(tid + (r << 8))] = v[r];
+  __syncthreads();
+  // bits 4..7: element (tid & 15) | r << 4 | (tid >> 4) << 8
+  const int b1 = (tid & 15) | ((tid >> 4) << 8);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = lds[pad(b1 + (r << 4))];
+  radix16(v);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) lds[pad(b1 + (r << 4))] = v[r];
+  __syncthreads();
+  // bits 0..3: the 16 consecutive elements 16 tid + r
+  const int b2 = tid << 4;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = lds[pad(b2 + r)];
+  radix16(v);
+  if (apply_scale) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = v[r] * scale;
+  }
+  if (VEC) {
+    typedef typename Pair<T>::type T2;
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) {
+      T2 q;
+      q.x = v[r];
+      q.y = v[r + 1];
+      *reinterpret_cast<T2*>(xt + b2 + r) = q;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) xt[b2 + r] = v[r];
+  }
+}
+
+// Bits [s, s + P), P <= 4, s >= 12: column c (of batch * b / 2^P) holds the
+// elements ((c >> s) << (s + P)) + (c & (2^s - 1)) + m 2^s, m < 2^P.
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void fwht_cols_kernel(T* __restrict__ x, int64_t ncols,
+                                                             int s, T scale, int apply_scale) {
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= ncols) return;
+  T* xc = x + (((c >> s) << (s + P)) + (c & (((int64_t)1 << s) - 1)));
+  T v[16];
+#pragma unroll
+  for (int m = 0; m < (1 << P); ++m) v[m] = xc[(int64_t)m << s];
+  wht_regs<T, (1 << P)>(v);
+#pragma unroll
+  for (int m = 0; m < (1 << P); ++m) xc[(int64_t)m << s] = apply_scale ? v[m] * scale : v[m];
+}
+
+template <typename T>
 cmm_status run(T* x, int64_t batch, int log2b, double scale, hipStream_t st) {
+  if (log2b >= kTileBits) {
+    if (batch > ((int64_t)0x7FFFFFFF >> (log2b - kTileBits)))
+      return invalid("cmm_fwht: batch too large");
+    const int64_t tiles = batch << (log2b - kTileBits);
+    const bool vec = (reinterpret_cast<uintptr_t>(x) % (2 * sizeof(T))) == 0;
+    auto low = vec ? fwht_low12_kernel<T, true> : fwht_low12_kernel<T, false>;
+    hipLaunchKernelGGL(low, dim3((unsigned)tiles), dim3(kThreads), 0, st, x, (T)scale,
+                       log2b == kTileBits && scale != 1.0);
+    cmm_status r = hip_check(hipGetLastError(), "fwht pass launch");
+    for (int s = kTileBits; r == CMM_OK && s < log2b;) {
+      const int P = log2b - s < 4 ? log2b - s : 4;
+      const int64_t ncols = (batch << log2b) >> P;
+      const int64_t blocks = (ncols + kThreads - 1) / kThreads;
+      if (blocks > 0x7FFFFFFF) return invalid("cmm_fwht: batch too large");
+      const int last = s + P >= log2b && scale != 1.0;
+      switch (P) {
+        case 1: hipLaunchKernelGGL((fwht_cols_kernel<T, 1>), dim3((unsigned)blocks), dim3(kThreads), 0, st, x, ncols, s, (T)scale, last); break;
+        case 2: hipLaunchKernelGGL((fwht_cols_kernel<T, 2>), dim3((unsigned)blocks), dim3(kThreads), 0, st, x, ncols, s, (T)scale, last); break;
+        case 3: hipLaunchKernelGGL((fwht_cols_kernel<T, 3>), dim3((unsigned)blocks), dim3(kThreads), 0, st, x, ncols, s, (T)scale, last); break;
+        default: hipLaunchKernelGGL((fwht_cols_kernel<T, 4>), dim3((unsigned)blocks), dim3(kThreads), 0, st, x, ncols, s, (T)scale, last); break;
+      }
+      r = hip_check(hipGetLastError(), "fwht pass launch");
+      s += P;
+    }
+    return r;
+  }
   int s = 0;
   while (s < log2b) {
     int P, logW;

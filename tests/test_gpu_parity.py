@@ -78,8 +78,8 @@ def test_sketch_f32_close():
 
 
 # ----------------------------------------------------------------- fwht
-@pytest.mark.parametrize("log2b,batch", [(1, 3), (4, 1), (7, 5), (12, 2), (13, 3), (16, 2),
-                                         (18, 1), (20, 1)])
+@pytest.mark.parametrize("log2b,batch", [(1, 3), (4, 1), (7, 5), (12, 2), (13, 3), (14, 3),
+                                         (15, 2), (16, 2), (17, 2), (18, 1), (20, 1)])
 def test_fwht_integer_exact_and_inverse(log2b, batch):
     announce(f"fwht log2b={log2b} batch={batch}")
     rng = np.random.default_rng(log2b)
@@ -89,6 +89,27 @@ def test_fwht_integer_exact_and_inverse(log2b, batch):
     assert np.array_equal(host(g), O.wht(x))
     cmm.cmm_fwht(g, batch, log2b, 2.0 ** -log2b)
     assert np.array_equal(host(g), x)
+
+
+@pytest.mark.parametrize("log2b", [12, 13, 16])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fwht_unaligned_integer_exact(log2b, dtype):
+    """Vectors starting one element past an aligned address (the pass stores
+    elements one by one there), float64 and float32 (integer data: exact)."""
+    announce(f"fwht unaligned log2b={log2b} {dtype}")
+    t = torch()
+    rng = np.random.default_rng(40 + log2b)
+    batch = 3
+    x = rng.integers(-100, 100, size=(batch, 1 << log2b))
+    tdt = t.float64 if dtype == "f64" else t.float32
+    buf = t.zeros(batch * (1 << log2b) + 1, dtype=tdt, device="cuda")
+    g = buf[1:]
+    g.copy_(t.from_numpy(x.reshape(-1)).to(tdt))
+    cmm.cmm_fwht(g, batch, log2b, 1.0)
+    assert np.array_equal(g.cpu().double().numpy().reshape(batch, -1), O.wht(x.astype(np.float64)))
+    assert float(buf[0]) == 0.0
+    cmm.cmm_fwht(g, batch, log2b, 2.0 ** -log2b)
+    assert np.array_equal(g.cpu().double().numpy().reshape(batch, -1), x.astype(np.float64))
 
 
 @pytest.mark.parametrize("log2b", [9, 16])
@@ -105,15 +126,36 @@ def test_fwht_real_close(log2b):
 
 
 # ----------------------------------------------------------- accumulate
-def test_accumulate_bit_exact():
-    announce("accumulate")
+@pytest.mark.parametrize("log2b,kc,dtype,offset", [
+    (10, 17, "f64", 0), (1, 9, "f64", 0), (12, 8, "f32", 0), (10, 17, "f64", 1),
+    (11, 5, "f32", 1)])
+def test_accumulate_bit_exact(log2b, kc, dtype, offset):
+    """Pair loads on aligned operands, element loads one element past an
+    aligned address; float32 operands widen exactly; p_hat starts nonzero
+    (the sums are added into it)."""
+    announce(f"accumulate log2b={log2b} kc={kc} {dtype} offset={offset}")
     t = torch()
-    rng = np.random.default_rng(3)
-    X = rng.standard_normal((3, 17, 1 << 10))
-    Y = rng.standard_normal((3, 17, 1 << 10))
-    p = t.zeros((3, 1 << 10), dtype=t.float64, device="cuda")
-    cmm.cmm_accumulate(dev(X), dev(Y), 3, 17, 10, p)
-    got, want = host(p), O.accumulate(X, Y)
+    rng = np.random.default_rng(3 + log2b)
+    d, b = 3, 1 << log2b
+    ndt = np.float64 if dtype == "f64" else np.float32
+    X = rng.standard_normal((d, kc, b)).astype(ndt)
+    Y = rng.standard_normal((d, kc, b)).astype(ndt)
+    p0 = rng.standard_normal((d, b))
+    tdt = t.float64 if dtype == "f64" else t.float32
+    bx = t.zeros(d * kc * b + offset, dtype=tdt, device="cuda")
+    by = t.zeros(d * kc * b + offset, dtype=tdt, device="cuda")
+    bp = t.zeros(d * b + offset, dtype=t.float64, device="cuda")
+    gx, gy, p = bx[offset:], by[offset:], bp[offset:]
+    gx.copy_(t.from_numpy(X.reshape(-1)))
+    gy.copy_(t.from_numpy(Y.reshape(-1)))
+    p.copy_(t.from_numpy(p0.reshape(-1)))
+    cmm.cmm_accumulate(gx, gy, d, kc, log2b, p)
+    got = p.cpu().numpy().reshape(d, b)
+    # the starting p_hat enters the oracle as a first term p0 * 1 (exact), so
+    # the oracle's ascending sum is the same sequence of rounded adds
+    Xd = np.concatenate([p0[:, None, :], X.astype(np.float64)], axis=1)
+    Yd = np.concatenate([np.ones((d, 1, b)), Y.astype(np.float64)], axis=1)
+    want = O.accumulate(Xd, Yd)
     diff = np.abs(got - want)
     print("accumulate max diff", diff.max(), "count", np.count_nonzero(diff), flush=True)
     assert np.array_equal(got, want)
