@@ -37,8 +37,8 @@ std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> g_prof;
 void prof_clear_locked() {
   for (auto& kv : g_prof)
     for (auto& ev : kv.second) {
-      hipEventDestroy(ev.first);
-      hipEventDestroy(ev.second);
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
     }
   g_prof.clear();
 }
@@ -47,14 +47,21 @@ void prof_clear_locked() {
 ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), stream_(s) {
   if (!g_prof_on.load(std::memory_order_relaxed)) return;
   if (hipEventCreate(&start_) != hipSuccess) { start_ = nullptr; return; }
-  hipEventRecord(start_, stream_);
+  if (hipEventRecord(start_, stream_) != hipSuccess) {
+    (void)hipEventDestroy(start_);
+    start_ = nullptr;
+  }
 }
 
 ProfScope::~ProfScope() {
   if (!start_) return;
   hipEvent_t stop = nullptr;
-  if (hipEventCreate(&stop) != hipSuccess) { hipEventDestroy(start_); return; }
-  hipEventRecord(stop, stream_);
+  if (hipEventCreate(&stop) != hipSuccess) { (void)hipEventDestroy(start_); return; }
+  if (hipEventRecord(stop, stream_) != hipSuccess) {
+    (void)hipEventDestroy(start_);
+    (void)hipEventDestroy(stop);
+    return;
+  }
   std::lock_guard<std::mutex> g(g_prof_mu);
   g_prof[name_].emplace_back(start_, stop);
 }
@@ -760,7 +767,10 @@ cmm_status cmm_correctness_counts(const void* C_hat, cmm_dtype C_hat_dtype, int6
                             n_big, threshold, tolerance, counts, as_stream(stream));
 }
 
+}  // extern "C"
+
 // ---------------------------------------------------- Pagh's FFT form
+namespace cmm {
 namespace {
 
 struct FftPlan {
@@ -897,6 +907,9 @@ cmm_status run_estimate_fft(const cmm_problem* pr, char* ws, hipStream_t s) {
 }
 
 }  // namespace
+}  // namespace cmm
+
+extern "C" {
 
 cmm_status cmm_fft(const void* in, void* out, int64_t batch, int log2n, int inverse, double scale,
                    void* stream) {
