@@ -20,7 +20,7 @@ constexpr int kSkThreads = 256;
 constexpr int kSkLogW = 10;       // at most 1024 buckets per window
 constexpr int kSkHC = 2048;       // hit-list capacity
 constexpr int kSkChunk = 1024;    // indices scanned per step (4 per thread)
-constexpr int kSkTarget = 4096;   // work-groups aimed for (the tiles are split to reach it)
+constexpr int kSkTarget = 2048;   // work-groups aimed for (the tiles are split to reach it)
 constexpr int32_t kSkNone = 0x7FFFFFFF;
 
 template <typename T>
