@@ -460,80 +460,129 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   //   w2 = m4 | m5 << 15 | s4 << 30 | s5 << 31
   // A chain with more rows (a bucket of seven or more) and chains beyond
   // the slots are finished from the plan's lists.
+  //
+  // Slot positions: chain c sits at position p (thread p mod NT, slot
+  // p / NT).  When the chains fit the slots they are placed with the chains
+  // of three or more rows first (a block scan), so only the waves whose
+  // positions hold such chains read words 1 and 2, and waves past the last
+  // chain skip a slot (both tests are wave-uniform); otherwise position c
+  // holds chain c.  A chain with more than six rows keeps its index in
+  // word 2, adds only its first four rows here and is finished in the rare
+  // pass.
   uint32_t* dsc = reinterpret_cast<uint32_t*>(exl);   // [word][operand][slot][NT]
   auto dref = [&](int word, int op, int j) -> uint32_t& {
     return dsc[((word * 2 + op) * kSlots16 + j) * NT + threadIdx.x];
   };
+  auto dslot = [&](int word, int op, int pos) -> uint32_t& {
+    return dsc[((word * 2 + op) * kSlots16 + pos / NT) * NT + pos % NT];
+  };
+  int nlong[2] = {0, 0};
   if constexpr (DESC) {
+    // the transpose buffer is idle until the k loop: scan scratch
+    int32_t* s_scan = reinterpret_cast<int32_t*>(xbuf);
+    __syncthreads();   // a previous work unit's last transposed reads are done
     for (int op = 0; op < 2; ++op) {
       const int32_t* gc = op ? gcB : gcA;
       const uint2* gp = op ? gB : gA;
       const int nch = op ? nchB : nchA;
       const uint32_t pad = (uint32_t)(op ? a.n_cols : a.n_rows);
-      for (int j = 0; j < kSlots16; ++j) {
-        const int c = (int)threadIdx.x + j * NT;
-        uint32_t m[6] = {pad + 1u + (threadIdx.x & 63u), pad, pad, pad, pad, pad};
-        uint32_t sg[6] = {0, 0, 0, 0, 0, 0};
-        uint32_t more = 0;
-        if (c < nch) {
-          const int beg = gc[c], end = gc[c + 1];
-          m[0] = gp[beg].x >> 16;
-          for (int r = 0; r < 5 && beg + r < end; ++r) {
-            const uint2 y = gp[beg + r];
-            m[r + 1] = y.x & 0xFFFFu;
-            sg[r + 1] = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
-          }
-          more = end - beg > 5 ? 1u : 0u;
+      const bool ordered = nch <= kSlots16 * NT;
+      const int per = (nch + NT - 1) / NT;
+      const int c0 = (int)threadIdx.x * per;
+      int mine = 0;
+      if (ordered)
+        for (int c = c0; c < c0 + per && c < nch; ++c) mine += (gc[c + 1] - gc[c] > 1) ? 1 : 0;
+      int incl = mine;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off);
+        if ((int)lane >= off) incl += y;
+      }
+      if (lane == 63u) s_scan[w] = incl;
+      __syncthreads();
+      int wbase = 0, total = 0;
+      for (int q = 0; q < NT / 64; ++q) {
+        const int x = s_scan[q];
+        if (q < (int)w) wbase += x;
+        total += x;
+      }
+      __syncthreads();   // s_scan is reused by the next operand
+      nlong[op] = ordered ? total : 0;
+      int lpos = wbase + incl - mine;                 // next position of a longer chain
+      int ppos = total + c0 - (wbase + incl - mine);  // next position of a two-row chain
+      for (int j = 0; j < kSlots16; ++j) {            // absent chains
+        if ((int)threadIdx.x + j * NT >= nch) {
+          dref(0, op, j) = (pad + 1u + (threadIdx.x & 63u)) | (pad << 15);
+          dref(1, op, j) = pad | (pad << 15);
+          dref(2, op, j) = pad | (pad << 15);
         }
-        dref(0, op, j) = m[0] | (m[1] << 15) | (sg[1] << 30) | (more << 31);
-        dref(1, op, j) = m[2] | (m[3] << 15) | (sg[2] << 30) | (sg[3] << 31);
-        dref(2, op, j) = m[4] | (m[5] << 15) | (sg[4] << 30) | (sg[5] << 31);
+      }
+      const int cb = ordered ? c0 : (int)threadIdx.x;
+      const int ce = ordered ? (c0 + per < nch ? c0 + per : nch) : nch;
+      for (int c = cb; c < ce; c += ordered ? 1 : NT) {
+        const int beg = gc[c], end = gc[c + 1];
+        int pos = c;
+        if (ordered) pos = (end - beg > 1) ? lpos++ : ppos++;
+        if (pos >= kSlots16 * NT) continue;
+        uint32_t m[6] = {gp[beg].x >> 16, pad, pad, pad, pad, pad};
+        uint32_t sg[6] = {0, 0, 0, 0, 0, 0};
+        for (int r = 0; r < 5 && beg + r < end; ++r) {
+          const uint2 y = gp[beg + r];
+          m[r + 1] = y.x & 0xFFFFu;
+          sg[r + 1] = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+        }
+        const uint32_t more = end - beg > 5 ? 1u : 0u;
+        dslot(0, op, pos) = m[0] | (m[1] << 15) | (sg[1] << 30) | (more << 31);
+        dslot(1, op, pos) = m[2] | (m[3] << 15) | (sg[2] << 30) | (sg[3] << 31);
+        dslot(2, op, pos) = more ? (uint32_t)c : m[4] | (m[5] << 15) | (sg[4] << 30) | (sg[5] << 31);
       }
     }
   }
-  // Fix-ups of both operands from their descriptors, straight-line: every
-  // slot loads its six values, sums them in rank order and stores once.
+  // Fix-ups of both operands from their descriptors: every live slot adds
+  // its target and first row; the rows past those only in the waves whose
+  // positions hold longer chains (all waves when the order is the identity).
+  // The sum is taken in rank order and stored once into the target; a chain
+  // with more rows stores its partial sum (in the row's own type, so no
+  // extra rounding) and the rare pass continues from its fifth row.
+  const int wave_pos = (int)(threadIdx.x & ~63u);
   auto fix_desc = [&]() {
-    // float64: one operand after the other (registers); float32: both at once.
-    // A slot with more rows stores its partial sum (in the row's own type,
-    // so no extra rounding) and the rare pass continues from it.
-    constexpr int OPS = sizeof(T) == 8 ? 1 : 2;
     bool rare = false;
 #pragma unroll
-    for (int o0 = 0; o0 < 2; o0 += OPS) {
-      uint32_t q[OPS][kSlots16][3];
-      T v[OPS][kSlots16][6];
+    for (int op = 0; op < 2; ++op) {
+      T* row = op ? rowB : rowA;
+      const int nch_op = op ? nchB : nchA;
+      const bool all = nch_op > kSlots16 * NT;   // identity order
+      const int nl = nlong[op];
+      uint32_t q0[kSlots16];
+      T sum[kSlots16];
 #pragma unroll
-      for (int oo = 0; oo < OPS; ++oo)
+      for (int j = 0; j < kSlots16; ++j) q0[j] = dref(0, op, j);
 #pragma unroll
-        for (int j = 0; j < kSlots16; ++j)
-#pragma unroll
-          for (int wd = 0; wd < 3; ++wd) q[oo][j][wd] = dref(wd, o0 + oo, j);
-#pragma unroll
-      for (int oo = 0; oo < OPS; ++oo) {
-        const T* row = (o0 + oo) ? rowB : rowA;
-#pragma unroll
-        for (int j = 0; j < kSlots16; ++j)
-#pragma unroll
-          for (int r = 0; r < 6; ++r)
-            v[oo][j][r] = row[(q[oo][j][r >> 1] >> (15 * (r & 1))) & 0x7FFFu];
+      for (int j = 0; j < kSlots16; ++j) {
+        if (!(all || wave_pos + j * NT < nch_op)) continue;   // wave-uniform
+        const uint32_t w0 = q0[j];
+        const T v1 = row[(w0 >> 15) & 0x7FFFu];
+        T acc_ = row[w0 & 0x7FFFu] + flip_sign(v1, ((w0 >> 30) & 1u) << 31);
+        if (all || wave_pos + j * NT < nl) {                   // wave-uniform
+          const uint32_t w1 = dref(1, op, j), w2 = dref(2, op, j);
+          const T v2 = row[w1 & 0x7FFFu], v3 = row[(w1 >> 15) & 0x7FFFu];
+          // word 2 of a chain with more rows is its index (< n: in the row)
+          const bool mr = (w0 >> 31) != 0u;
+          const T v4 = row[w2 & 0x7FFFu], v5 = row[(w2 >> 15) & 0x7FFFu];
+          acc_ = acc_ + flip_sign(v2, ((w1 >> 30) & 1u) << 31);
+          acc_ = acc_ + flip_sign(v3, ((w1 >> 31) & 1u) << 31);
+          if (!mr) {
+            acc_ = acc_ + flip_sign(v4, ((w2 >> 30) & 1u) << 31);
+            acc_ = acc_ + flip_sign(v5, ((w2 >> 31) & 1u) << 31);
+          }
+        }
+        sum[j] = acc_;
       }
 #pragma unroll
-      for (int oo = 0; oo < OPS; ++oo) {
-        T* row = (o0 + oo) ? rowB : rowA;
-#pragma unroll
-        for (int j = 0; j < kSlots16; ++j) {
-          T acc_ = v[oo][j][0];
-#pragma unroll
-          for (int r = 1; r < 6; ++r) {
-            // sign of member r: w0 bit 30 for r = 1, else bit 30 + (r & 1) of word r / 2
-            const uint32_t word = q[oo][j][r >> 1];
-            const uint32_t neg = (r == 1) ? (word >> 30) & 1u : (word >> (30 + (r & 1))) & 1u;
-            acc_ = acc_ + flip_sign(v[oo][j][r], neg << 31);
-          }
-          rare = rare || (q[oo][j][0] >> 31) != 0u;
-          row[q[oo][j][0] & 0x7FFFu] = acc_;
-        }
+      for (int j = 0; j < kSlots16; ++j) {
+        if (!(all || wave_pos + j * NT < nch_op)) continue;
+        rare = rare || (q0[j] >> 31) != 0u;
+        row[q0[j] & 0x7FFFu] = sum[j];
       }
     }
     const bool extra = nchA > kSlots16 * NT || nchB > kSlots16 * NT;
@@ -547,16 +596,16 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
           const uint32_t w0 = dref(0, op, j);
           if (!(w0 >> 31)) continue;
           T acc_ = row[w0 & 0x7FFFu];
-          const int c = (int)threadIdx.x + j * NT;
+          const int c = (int)dref(2, op, j);
           const int beg = gc[c], end = gc[c + 1];
-          for (int r = beg + 5; r < end; ++r) {
+          for (int r = beg + 3; r < end; ++r) {
             const uint2 y = gp[r];
             const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
             acc_ = acc_ + flip_sign(row[y.x & 0xFFFFu], neg << 31);
           }
           row[w0 & 0x7FFFu] = acc_;
         }
-        // chains beyond the slots (disjoint targets)
+        // chains beyond the slots (identity order: disjoint targets)
         const int nch = op ? nchB : nchA;
         for (int c = kSlots16 * NT + (int)threadIdx.x; c < nch; c += NT) {
           const int beg = gc[c], end = gc[c + 1];
