@@ -79,7 +79,7 @@ struct cmm_batch {
   std::map<BatchConfig, BatchLayout> layouts;
   std::map<BatchConfig, void*> staging;   // pinned copies of the descriptor tables
   ~cmm_batch() {
-    for (auto& kv : staging) hipHostFree(kv.second);
+    for (auto& kv : staging) (void)hipHostFree(kv.second);
   }
 };
 
@@ -373,19 +373,22 @@ cmm_status time_config(cmm_batch& b, const BatchConfig& c, char* ws, hipStream_t
   hipEvent_t e0, e1;
   cmm_status st = hip_check(hipEventCreate(&e0), "autotune: event");
   if (st != CMM_OK) return st;
-  if ((st = hip_check(hipEventCreate(&e1), "autotune: event")) != CMM_OK) { hipEventDestroy(e0); return st; }
+  if ((st = hip_check(hipEventCreate(&e1), "autotune: event")) != CMM_OK) {
+    (void)hipEventDestroy(e0);
+    return st;
+  }
   float best = 1e30f;
   for (int rep = 0; rep < 3 && st == CMM_OK; ++rep) {   // the first run warms up
-    hipEventRecord(e0, s);
-    st = compress_all(b, c, ws, s);
-    hipEventRecord(e1, s);
+    st = hip_check(hipEventRecord(e0, s), "autotune: record");
+    if (st == CMM_OK) st = compress_all(b, c, ws, s);
+    if (st == CMM_OK) st = hip_check(hipEventRecord(e1, s), "autotune: record");
     if (st == CMM_OK) st = hip_check(hipEventSynchronize(e1), "autotune: wait");
     float t = 0.f;
     if (st == CMM_OK) st = hip_check(hipEventElapsedTime(&t, e0, e1), "autotune: elapsed");
     if (rep > 0 && t < best) best = t;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   *ms = best;
   return st;
 }
