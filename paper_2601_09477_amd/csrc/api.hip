@@ -98,6 +98,9 @@ struct EstimatePlan {
   cmm_dtype cdt = CMM_F64;
   size_t off_at = 0, off_bc = 0, off_planA = 0, off_planB = 0, off_part = 0, off_p = 0;
   size_t off_x = 0, off_y = 0;
+  // precision form: merged two-row chains (lists, counts, sums) per operand
+  int pair_cap[2] = {0, 0};
+  size_t off_plist[2] = {0, 0}, off_pcount[2] = {0, 0}, off_pvals[2] = {0, 0};
   size_t bytes = 0;
 };
 
@@ -176,6 +179,15 @@ EstimatePlan make_plan(const cmm_problem* pr) {
     P.off_planB = off; off = align_up(off + plan_bytes(d, pr->n_cols, 14), 256);
     P.off_part = off; off = align_up(off + sizeof(double) * (size_t)P.groups * d * b, 256);
     P.off_p = off; off = align_up(off + sizeof(double) * (size_t)d * b, 256);
+    for (int op = 0; op < 2; ++op) {
+      const int64_t n = op ? pr->n_cols : pr->n_rows;
+      P.pair_cap[op] = pr->n_inner > 0 ? mfma_pair_cap(pr->n_rows, pr->n_cols, op) : 0;
+      if (P.pair_cap[op] == 0) continue;
+      P.off_plist[op] = off; off = align_up(off + sizeof(uint2) * (size_t)d * (n / 2 + 1), 256);
+      P.off_pcount[op] = off; off = align_up(off + sizeof(int32_t) * (size_t)d, 256);
+      P.off_pvals[op] = off;
+      off = align_up(off + 2 * (size_t)d * pr->n_inner * 2 * P.pair_cap[op], 256);
+    }
     P.bytes = off;
     return P;
   }
@@ -275,6 +287,20 @@ cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
     a.variant = 0;
     if ((st = launch_plan(pr->tab1, d, pr->n_rows, P.lb, a.planA, s)) != CMM_OK) return st;
     if ((st = launch_plan(pr->tab2, d, pr->n_cols, P.lb, a.planB, s)) != CMM_OK) return st;
+    // the two-row chains merged ahead of the kernel, from the low-precision rows
+    for (int op = 0; op < 2; ++op) {
+      if (P.pair_cap[op] == 0) continue;
+      const int64_t n = op ? pr->n_cols : pr->n_rows;
+      uint2* list = reinterpret_cast<uint2*>(ws + P.off_plist[op]);
+      int32_t* count = reinterpret_cast<int32_t*>(ws + P.off_pcount[op]);
+      void* vals = ws + P.off_pvals[op];
+      if ((st = launch_pair_list(op ? a.planB : a.planA, d, n, list, count, s)) != CMM_OK) return st;
+      if ((st = launch_pair_sums(op ? Bc : At, n, pr->compute, d, pr->n_inner, n, list, count,
+                                 P.pair_cap[op], vals, s)) != CMM_OK)
+        return st;
+      if (op) { a.pair_listB = list; a.pair_countB = count; a.pair_valsB = vals; a.pair_capB = P.pair_cap[1]; }
+      else { a.pair_listA = list; a.pair_countA = count; a.pair_valsA = vals; a.pair_capA = P.pair_cap[0]; }
+    }
     if ((st = launch_compress_mfma(a, pr->compute, s)) != CMM_OK) return st;
     if ((st = launch_reduce_partials(a.partial, P.groups, (size_t)d * b, p, s)) != CMM_OK) return st;
   } else if (P.fused) {

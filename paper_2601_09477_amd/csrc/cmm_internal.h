@@ -141,6 +141,18 @@ struct CompressArgs {
   int64_t ex_cap;          // set by the launcher: LDS entries for the extras
   int dma;                 // set by the launcher: asynchronous row copies
   int variant;             // 0: default kernel for (dtype, b_lo); 1: 32 elements per thread
+  // Precision form only: the two-row chains of each repetition merged ahead
+  // of the kernel.  list [d][n / 2 + 1] holds a chain's plan entry (member |
+  // first << 16, hi-bits xor | sign xor << 31) in chain order, count [d] their
+  // number, vals [d][n_inner][2 cap] the low-precision sums x + y and x - y
+  // of the chain's two rows for every k.  cap = 0: no merged chains.
+  const uint2* pair_listA = nullptr;
+  const uint2* pair_listB = nullptr;
+  const int32_t* pair_countA = nullptr;
+  const int32_t* pair_countB = nullptr;
+  const void* pair_valsA = nullptr;
+  const void* pair_valsB = nullptr;
+  int pair_capA = 0, pair_capB = 0;
 };
 
 size_t plan_bytes(int d, int64_t n, int lb);
@@ -205,6 +217,17 @@ cmm_status launch_compress_batched(char* ws, const BatchPair* pairs, const Batch
 
 // Precision form: MFMA compress (b_lo = 2^14) on bf16 / fp16 rows.
 cmm_status launch_compress_mfma(const CompressArgs& a, cmm_dtype lp, hipStream_t s);
+// Merged two-row chains of the precision form: the largest number of chains
+// per repetition whose sums the kernel can stage beside a row of n values
+// (0 when none fit), the chain lists from the plans, and the sums of the
+// rows of At (n_inner x n_rows) or B (n_inner x n_cols, leading dimension
+// ld) in the low precision lp.
+int mfma_pair_cap(int64_t n_rows, int64_t n_cols, int operand);
+cmm_status launch_pair_list(const PlanView& pv, int d, int64_t n, uint2* list, int32_t* count,
+                            hipStream_t s);
+cmm_status launch_pair_sums(const void* rows, int64_t ld, cmm_dtype lp, int d, int64_t n_inner,
+                            int64_t n, const uint2* list, const int32_t* count, int cap,
+                            void* vals, hipStream_t s);
 // ------------------------------------------------ differentiation form
 // Shape of the W scatter (extract^T): row blocks of rows_per rows, windows
 // of 2^wb buckets (at most 128 KB of LDS).

@@ -152,8 +152,12 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   // rows first (small LDS offsets), then the two transpose buffers
   // 16-byte aligned rows: the row, a zero pad at index n, then 64 spare
   // elements (per-lane targets of absent collision slots)
-  const int64_t pitchA = (a.n_rows + 1 + 64 + 7) / 8 * 8;
-  const int64_t pitchB = (a.n_cols + 1 + 64 + 7) / 8 * 8;
+  // then, when the launcher reserved them, the sums of merged two-row
+  // chains (2 cap values)
+  const int64_t pbaseA = (a.n_rows + 1 + 64 + 7) / 8 * 8;
+  const int64_t pbaseB = (a.n_cols + 1 + 64 + 7) / 8 * 8;
+  const int64_t pitchA = pbaseA + 2 * (int64_t)a.pair_capA;
+  const int64_t pitchB = pbaseB + 2 * (int64_t)a.pair_capB;
   IN* rowA = reinterpret_cast<IN*>(smem);
   IN* rowB = rowA + pitchA;
   IN* tbufX = rowB + pitchB;                             // BLO
@@ -183,28 +187,72 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   // Two 16-bit words per register: byte offset of the row element in bits
   // 0..14 (empty bucket -> the zero pad at index n), folded sign in bit 15.
   uint32_t idxA[NS / 2], idxB[NS / 2];     // first rows of the buckets
-  {
-    const int32_t* f1 = a.planA.first + (size_t)t * BLO;
-    const int32_t* f2 = a.planB.first + (size_t)t * BLO;
-    const uint32_t* t1 = a.tab1 + (size_t)t * a.n_rows;
-    const uint32_t* t2 = a.tab2 + (size_t)t * a.n_cols;
+  const uint32_t* t1 = a.tab1 + (size_t)t * a.n_rows;
+  const uint32_t* t2 = a.tab2 + (size_t)t * a.n_cols;
+  const int nchA = a.planA.nchains[t], nchB = a.planB.nchains[t];
+  // Merged two-row chains: used by this work unit when the chains left to
+  // the descriptors (the longer ones and the two-row chains past the cap)
+  // fit their slots.  npair: merged chains; ndesc: descriptor positions.
+  int npair[2] = {0, 0}, ndesc[2] = {nchA, nchB};
+  if (DESC) {
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      const int cap = op ? a.pair_capB : a.pair_capA;
+      if (cap > 0) {
+        const int n2 = (op ? a.pair_countB : a.pair_countA)[t];
+        const int m = n2 < cap ? n2 : cap;
+        const int nd = (op ? nchB : nchA) - m;
+        if (nd <= kSlots * kNT) {
+          npair[op] = m;
+          ndesc[op] = nd;
+        }
+      }
+    }
+  }
+  // bucket -> 2 p + relative sign of merged chain p, in the transpose
+  // buffers (idle until the k loop), one operand at a time
+  int32_t* pmap = reinterpret_cast<int32_t*>(tbufX);   // [BLO]
+  auto gather_offsets = [&](int op, uint32_t (&idx)[NS / 2]) {
+    const int np = npair[op];
+    if (np > 0) {
+      for (int r = threadIdx.x; r < BLO; r += kNT) pmap[r] = -1;
+      __syncthreads();
+      const uint2* pl = (op ? a.pair_listB : a.pair_listA) +
+                        (size_t)t * ((op ? a.n_cols : a.n_rows) / 2 + 1);
+      const uint32_t* tb = op ? t2 : t1;
+      for (int q = threadIdx.x; q < np; q += kNT) {
+        const uint2 y = pl[q];
+        const uint32_t rel = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+        pmap[tb[y.x >> 16] & (uint32_t)(BLO - 1)] = 2 * q + (int32_t)rel;
+      }
+      __syncthreads();
+    }
+    const int32_t* f = (op ? a.planB.first : a.planA.first) + (size_t)t * BLO;
+    const uint32_t* tb = op ? t2 : t1;
+    const uint32_t pad = (uint32_t)(op ? a.n_cols : a.n_rows);
+    const uint32_t pbase = (uint32_t)(op ? pbaseB : pbaseA);
 #pragma unroll
     for (int e = 0; e < NS; ++e) {
       const uint32_t c = (uint32_t)e >> 2, v = (uint32_t)e & 3u;
       const uint32_t r = v | (lg << 2) | (lm << 4) | (c << 8) | (w << 11);
-      const int32_t r1 = f1[r], r2 = f2[r];
-      const uint32_t en1 = t1[r1 >= 0 ? r1 : 0], en2 = t2[r2 >= 0 ? r2 : 0];
-      const uint32_t s1 = r1 >= 0 ? (en1 >> 31) ^ (__popc(uhi & ((en1 & kBucketMask) >> kLB)) & 1u) : 0u;
-      const uint32_t s2 = r2 >= 0 ? (en2 >> 31) ^ (__popc(uhi & ((en2 & kBucketMask) >> kLB)) & 1u) : 0u;
-      const uint32_t ia = 2u * (r1 >= 0 ? (uint32_t)r1 : (uint32_t)a.n_rows) | (s1 << 15);
-      const uint32_t ib = 2u * (r2 >= 0 ? (uint32_t)r2 : (uint32_t)a.n_cols) | (s2 << 15);
-      if (e & 1) { idxA[e >> 1] |= ia << 16; idxB[e >> 1] |= ib << 16; }
-      else { idxA[e >> 1] = ia; idxB[e >> 1] = ib; }
+      const int32_t r1 = f[r];
+      const uint32_t en = tb[r1 >= 0 ? r1 : 0];
+      const uint32_t s1 = r1 >= 0 ? (en >> 31) ^ (__popc(uhi & ((en & kBucketMask) >> kLB)) & 1u) : 0u;
+      uint32_t el = r1 >= 0 ? (uint32_t)r1 : pad;
+      if (np > 0) {
+        const int32_t m = pmap[r];
+        if (m >= 0) el = pbase + (uint32_t)m;   // the merged sum, same folded sign
+      }
+      const uint32_t ix = 2u * el | (s1 << 15);
+      if (e & 1) idx[e >> 1] |= ix << 16;
+      else idx[e >> 1] = ix;
     }
-  }
+    if (np > 0) __syncthreads();   // the map is rebuilt for the next operand
+  };
+  gather_offsets(0, idxA);
+  gather_offsets(1, idxB);
   const int32_t* gcA = a.planA.cstart + (size_t)t * (a.n_rows + 2);
   const int32_t* gcB = a.planB.cstart + (size_t)t * (a.n_cols + 2);
-  const int nchA = a.planA.nchains[t], nchB = a.planB.nchains[t];
   const int cntA = gcA[nchA], cntB = gcB[nchB];
   const bool ex_lds = (int64_t)cntA + cntB + (nchA + nchB + 4) / 2 + 1 <= a.ex_cap;
   const uint2* gA = a.planA.pairs + (size_t)t * a.n_rows;
@@ -249,7 +297,10 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   // position of every chain (longer chains first) by a block-wide scan over
   // contiguous runs of chains; identity order when the chains exceed the slots
   auto build_desc = [&](int op, const int32_t* gc, const uint2* gp, int nch, uint32_t pad) {
-    const bool ordered = nch <= kSlots * kNT;
+    // merged two-row chains (the first npair in chain order) take no slot
+    const int np = npair[op];
+    const int nd = ndesc[op];
+    const bool ordered = nd <= kSlots * kNT;
     const int per = (nch + kNT - 1) / kNT;
     const int c0 = (int)threadIdx.x * per;
     int mine = 0;
@@ -278,7 +329,7 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
     // empty slots first: absent chains
     for (int j = 0; j < kSlots; ++j) {
       const int pos = (int)threadIdx.x + j * kNT;
-      if (pos >= nch) {
+      if (pos >= nd) {
         dref(0, op, j) = (pad + 1u + (threadIdx.x & 63u)) | (pad << 15);
         dref(1, op, j) = pad | (pad << 15);
         dref(2, op, j) = pad | (pad << 15);
@@ -289,7 +340,15 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
     for (int c = cb; c < ce; c += ordered ? 1 : kNT) {
       const int beg = gc[c], end = gc[c + 1];
       int pos = c;
-      if (ordered) pos = (end - beg > 1) ? lpos++ : ppos++;
+      if (ordered) {
+        if (end - beg > 1) {
+          pos = lpos++;
+        } else {
+          const int q = ppos++ - total;   // index among the two-row chains
+          if (q < np) continue;           // merged ahead of the kernel
+          pos = total + q - np;
+        }
+      }
       if (pos >= kSlots * kNT) continue;
       uint32_t m[6] = {gp[beg].x >> 16, pad, pad, pad, pad, pad};
       uint32_t sg[6] = {0, 0, 0, 0, 0, 0};
@@ -315,26 +374,52 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   // stores to its lane's spare element and is finished, still rounded once,
   // in the rare pass.
   const int wave_pos = (int)(threadIdx.x & ~63u);
+  // First descriptor words of the thread's slots, kept in registers for the
+  // whole k loop (the descriptors do not change with k), so a fix-up starts
+  // with the row reads.
+  uint32_t q0[2][kSlots];
+  if (DESC) {
+    __syncthreads();   // every thread's descriptors are written
+#pragma unroll
+    for (int op = 0; op < 2; ++op)
+#pragma unroll
+      for (int j = 0; j < kSlots; ++j) {
+        q0[op][j] = dref(0, op, j);
+        asm volatile("" : "+v"(q0[op][j]));
+      }
+  }
   auto fix_desc = [&](const int32_t* gcA_, const uint2* gpA_, const int32_t* gcB_, const uint2* gpB_) {
-    uint32_t q0[2][kSlots];
+    // Every slot's target and first row, straight-line so that all the reads
+    // are in flight together (an absent slot reads its lane's spare element
+    // and the zero pad, and writes the spare back unchanged).
+    IN r0[2][kSlots], r1[2][kSlots];
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      const IN* row = op ? rowB : rowA;
+#pragma unroll
+      for (int j = 0; j < kSlots; ++j) {
+        r0[op][j] = row[q0[op][j] & 0x7FFFu];
+        r1[op][j] = row[(q0[op][j] >> 15) & 0x7FFFu];
+      }
+    }
     float sum[2][kSlots];
 #pragma unroll
     for (int op = 0; op < 2; ++op)
 #pragma unroll
-      for (int j = 0; j < kSlots; ++j) q0[op][j] = dref(0, op, j);
+      for (int j = 0; j < kSlots; ++j) {
+        const float v1 = to_f(r1[op][j]);
+        sum[op][j] = to_f(r0[op][j]) + (((q0[op][j] >> 30) & 1u) ? -v1 : v1);
+      }
+    // rows three to six: only the waves whose positions hold longer chains
 #pragma unroll
     for (int op = 0; op < 2; ++op) {
       const IN* row = op ? rowB : rowA;
       const int nl = DESC ? nlong[op] : 0;
-      const int nch_op = op ? nchB : nchA;
-      const bool all_long = nch_op > kSlots * kNT;
+      const bool all_long = ndesc[op] > kSlots * kNT;
 #pragma unroll
       for (int j = 0; j < kSlots; ++j) {
-        const uint32_t w0 = q0[op][j];
-        const float v0 = to_f(row[w0 & 0x7FFFu]);
-        const float v1 = to_f(row[(w0 >> 15) & 0x7FFFu]);
-        float acc_ = v0 + (((w0 >> 30) & 1u) ? -v1 : v1);
         if (all_long || wave_pos + j * kNT < nl) {   // wave-uniform
+          const uint32_t w0 = q0[op][j];
           const uint32_t w1 = dref(1, op, j), w2 = dref(2, op, j);
           const float v2 = to_f(row[w1 & 0x7FFFu]), v3 = to_f(row[(w1 >> 15) & 0x7FFFu]);
           // w2 of a slot with more rows is a chain index (< n, so the reads
@@ -343,12 +428,13 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
           float v4 = to_f(row[w2 & 0x7FFFu]), v5 = to_f(row[(w2 >> 15) & 0x7FFFu]);
           v4 = mr ? 0.f : v4;
           v5 = mr ? 0.f : v5;
+          float acc_ = sum[op][j];
           acc_ = acc_ + (((w1 >> 30) & 1u) ? -v2 : v2);
           acc_ = acc_ + (((w1 >> 31) & 1u) ? -v3 : v3);
           acc_ = acc_ + ((!mr && ((w2 >> 30) & 1u)) ? -v4 : v4);
           acc_ = acc_ + ((!mr && ((w2 >> 31) & 1u)) ? -v5 : v5);
+          sum[op][j] = acc_;
         }
-        sum[op][j] = acc_;
       }
     }
     bool rare = false;
@@ -363,7 +449,7 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
         row[more ? spare : (q0[op][j] & 0x7FFFu)] = (IN)sum[op][j];
       }
     }
-    const bool extra = nchA > kSlots * kNT || nchB > kSlots * kNT;
+    const bool extra = ndesc[0] > kSlots * kNT || ndesc[1] > kSlots * kNT;
     if (rare || extra) {
 #pragma unroll
       for (int op = 0; op < 2; ++op) {
@@ -424,9 +510,21 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   const IN* At = reinterpret_cast<const IN*>(a.At);
   const IN* Bm = reinterpret_cast<const IN*>(a.B);
   const bool dma = a.dma != 0;
+  // the merged chains' sums of k follow each row (whole 16-byte chunks,
+  // inside the 2 cap values reserved per k)
+  const IN* pvA = reinterpret_cast<const IN*>(a.pair_valsA);
+  const IN* pvB = reinterpret_cast<const IN*>(a.pair_valsB);
+  const int64_t plenA = (2 * (int64_t)npair[0] + 7) / 8 * 8;
+  const int64_t plenB = (2 * (int64_t)npair[1] + 7) / 8 * 8;
   auto load_k = [&](int64_t kk) {
     stage_row_lp<IN, kNT>(rowA, At + kk * a.n_rows, a.n_rows, dma);
     stage_row_lp<IN, kNT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
+    if (plenA > 0)
+      stage_row_lp<IN, kNT>(rowA + pbaseA, pvA + ((size_t)t * a.n_inner + kk) * (2 * a.pair_capA),
+                            plenA, dma);
+    if (plenB > 0)
+      stage_row_lp<IN, kNT>(rowB + pbaseB, pvB + ((size_t)t * a.n_inner + kk) * (2 * a.pair_capB),
+                            plenB, dma);
   };
   // passes 1-2 of one operand from its staged row, each phase over all
   // tiles (independent MFMAs); result written (rounded) to the transpose buffer
@@ -530,7 +628,7 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   for (int64_t k = k0; k < k1; ++k) {
     if (dma) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();   // rows of k staged; the transpose buffers are free
-    if (nchA + nchB > 0) {
+    if ((DESC ? ndesc[0] + ndesc[1] : nchA + nchB) > 0) {
       if constexpr (DESC) {
         fix_desc(gcA, gA, gcB, gB);
       } else {
@@ -575,6 +673,114 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
 
 }  // namespace
 
+namespace {
+
+// Two-row chains of one repetition in chain order (one work-group per
+// repetition): a block scan over contiguous runs of chains numbers them.
+__global__ __launch_bounds__(kNT) void pair_list_kernel(PlanView pv, int64_t n, uint2* list,
+                                                        int32_t* count) {
+  __shared__ int32_t s_scan[kNT / 64];
+  const int t = blockIdx.x;
+  const int32_t* gc = pv.cstart + (size_t)t * (n + 2);
+  const uint2* gp = pv.pairs + (size_t)t * n;
+  uint2* out = list + (size_t)t * (n / 2 + 1);
+  const int nch = pv.nchains[t];
+  const int per = (nch + kNT - 1) / kNT;
+  const int c0 = (int)threadIdx.x * per;
+  const int c1 = c0 + per < nch ? c0 + per : nch;
+  int mine = 0;
+  for (int c = c0; c < c1; ++c) mine += (gc[c + 1] - gc[c] == 1) ? 1 : 0;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  int incl = mine;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off);
+    if ((int)lane >= off) incl += y;
+  }
+  if (lane == 63u) s_scan[wv] = incl;
+  __syncthreads();
+  int q = incl - mine, total = 0;
+  for (int v = 0; v < kNT / 64; ++v) {
+    if (v < (int)wv) q += s_scan[v];
+    total += s_scan[v];
+  }
+  for (int c = c0; c < c1; ++c)
+    if (gc[c + 1] - gc[c] == 1) out[q++] = gp[gc[c]];
+  if (threadIdx.x == 0) count[t] = total;
+}
+
+// Sums of the two rows of every listed chain: one work-group per k copies
+// row k into LDS (coalesced) and forms every repetition's sums from it:
+// vals[t][k][2 q + 0] = x + y, [2 q + 1] = x - y, with x the chain's first
+// row and y its second, added in float32 and rounded once (what the
+// in-kernel fix-up of such a chain computes).
+template <typename IN>
+__global__ __launch_bounds__(256) void pair_sums_kernel(const IN* __restrict__ rows, int64_t ld,
+                                                        int64_t n_inner, int64_t n, int d,
+                                                        const uint2* __restrict__ list,
+                                                        const int32_t* __restrict__ count,
+                                                        int cap, IN* __restrict__ vals) {
+  extern __shared__ __align__(16) unsigned char psm[];
+  IN* row = reinterpret_cast<IN*>(psm);
+  const int64_t kk = blockIdx.x;
+  const IN* src = rows + kk * ld;
+  for (int64_t i = threadIdx.x; i < n; i += 256) row[i] = src[i];
+  __syncthreads();
+  for (int t = 0; t < d; ++t) {
+    const int n2 = count[t] < cap ? count[t] : cap;
+    const uint2* pl = list + (size_t)t * (n / 2 + 1);
+    uint32_t* out = reinterpret_cast<uint32_t*>(vals + ((size_t)t * n_inner + kk) * (2 * (size_t)cap));
+    for (int q = threadIdx.x; q < n2; q += 256) {
+      const uint2 y = pl[q];
+      const float x0 = (float)row[y.x >> 16], x1 = (float)row[y.x & 0xFFFFu];
+      out[q] = pack2(x0 + x1, x0 - x1, (IN*)nullptr);
+    }
+  }
+}
+
+}  // namespace
+
+int mfma_pair_cap(int64_t n_rows, int64_t n_cols, int operand) {
+  if (n_rows > 16383 || n_cols > 16383 || n_rows < 1 || n_cols < 1) return 0;
+  const int64_t pA = (n_rows + 1 + 64 + 7) / 8 * 8, pB = (n_cols + 1 + 64 + 7) / 8 * 8;
+  const int64_t base = 2 * (2 * ((int64_t)1 << kLB) + pA + pB);   // 16-bit elements
+  const int64_t kMax = 160 * 1024 - 256;
+  if (base + kDescLds > kMax) return 0;   // the chain-list instance: nothing merged
+  // each operand's share of what is left, 2 values of 2 bytes per chain;
+  // every element of the row region addressable with 15-bit byte offsets
+  int64_t cap = (kMax - base - kDescLds) / 8;
+  const int64_t n = operand ? n_cols : n_rows;
+  const int64_t p0 = operand ? pB : pA;
+  if (cap > n / 2) cap = n / 2;
+  if (cap > (16384 - p0) / 2) cap = (16384 - p0) / 2;
+  cap &= ~(int64_t)3;
+  return cap > 0 ? (int)cap : 0;
+}
+
+cmm_status launch_pair_list(const PlanView& pv, int d, int64_t n, uint2* list, int32_t* count,
+                            hipStream_t s) {
+  ProfScope prof_("pairs", s);
+  hipLaunchKernelGGL(pair_list_kernel, dim3((unsigned)d), dim3(kNT), 0, s, pv, n, list, count);
+  return hip_check(hipGetLastError(), "pair list launch");
+}
+
+cmm_status launch_pair_sums(const void* rows, int64_t ld, cmm_dtype lp, int d, int64_t n_inner,
+                            int64_t n, const uint2* list, const int32_t* count, int cap,
+                            void* vals, hipStream_t s) {
+  ProfScope prof_("pairs", s);
+  if (cap <= 0 || n_inner <= 0) return CMM_OK;
+  if (n_inner > 0x7FFFFFFF || n > 16383) return invalid("pair sums: size out of range");
+  const size_t lds = 2 * (size_t)n;   // one row of 16-bit values
+  if (lp == CMM_BF16)
+    hipLaunchKernelGGL(pair_sums_kernel<__bf16>, dim3((unsigned)n_inner), dim3(256), lds, s,
+                       (const __bf16*)rows, ld, n_inner, n, d, list, count, cap, (__bf16*)vals);
+  else
+    hipLaunchKernelGGL(pair_sums_kernel<_Float16>, dim3((unsigned)n_inner), dim3(256), lds, s,
+                       (const _Float16*)rows, ld, n_inner, n, d, list, count, cap,
+                       (_Float16*)vals);
+  return hip_check(hipGetLastError(), "pair sums launch");
+}
+
 template <typename IN>
 static cmm_status launch_mfma_t(const CompressArgs& a0, hipStream_t s) {
   ProfScope prof_("compress", s);
@@ -584,7 +790,13 @@ static cmm_status launch_mfma_t(const CompressArgs& a0, hipStream_t s) {
     set_error("compress (mfma): needs n_rows, n_cols <= 16383");
     return CMM_EUNSUPPORTED;
   }
-  const size_t pitch = ((size_t)a.n_rows + 1 + 64 + 7) / 8 * 8 + ((size_t)a.n_cols + 1 + 64 + 7) / 8 * 8;
+  if (a.pair_capA < 0 || a.pair_capB < 0 || a.pair_capA > mfma_pair_cap(a.n_rows, a.n_cols, 0) ||
+      a.pair_capB > mfma_pair_cap(a.n_rows, a.n_cols, 1) || (a.pair_capA & 3) || (a.pair_capB & 3)) {
+    set_error("compress (mfma): merged-chain capacity out of range");
+    return CMM_EINVAL;
+  }
+  const size_t pitch = ((size_t)a.n_rows + 1 + 64 + 7) / 8 * 8 + 2 * (size_t)a.pair_capA +
+                       ((size_t)a.n_cols + 1 + 64 + 7) / 8 * 8 + 2 * (size_t)a.pair_capB;
   const size_t base = sizeof(IN) * (2 * ((size_t)1 << kLB) + pitch);
   const size_t kMax = 160 * 1024 - 256;   // the kernel's own counters take a few bytes more
   if (base > kMax) { set_error("compress (mfma): rows do not fit in LDS"); return CMM_EUNSUPPORTED; }

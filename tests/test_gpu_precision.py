@@ -89,3 +89,26 @@ def test_mfma_planted_8192_full_size():
             assert np.array_equal(p, p_ref)
             assert np.array_equal(C_hat[rows], C_ref_rows)
         assert rec["recall"] >= 1.0 - 2.0 / rec["planted"]
+
+
+@pytest.mark.parametrize("n", [10000, 12000])
+@pytest.mark.parametrize("compute,eps", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+def test_mfma_merged_chains_overflow(n, compute, eps):
+    # At n = 10000 the two-row chains outnumber the sums the kernel can stage
+    # beside a row (the rest take collision descriptors); at n = 12000 the
+    # chains left to descriptors exceed their slots, so no chain is merged
+    # ahead of the kernel.  Same error bound as the Gaussian case above.
+    announce(f"mfma {compute} merged-chain overflow n={n}")
+    rng = np.random.default_rng(n)
+    n_inner, log2b, d = 16, 14, 3
+    A = rng.standard_normal((n, n_inner))
+    B = rng.standard_normal((n_inner, n))
+    keys = draw_keys(d, 5 + n)
+    from types import SimpleNamespace
+    w = SimpleNamespace(A=A, B=B, keys=keys, log2b=log2b, d=d)
+    res = cmm.estimate(dev(A), dev(B), d, log2b, keys=keys, compute=compute)
+    C, p_ref, t1, t2 = _ref(w, n, n)
+    dp = np.abs(host(res.p) - p_ref)
+    rms_p = np.sqrt(np.mean(p_ref ** 2))
+    print(f"{compute} n={n}: rms(dp)/rms(p) = {np.sqrt(np.mean(dp ** 2)) / rms_p:.3e}", flush=True)
+    assert np.sqrt(np.mean(dp ** 2)) <= 8 * eps * rms_p * np.sqrt(n_inner)
