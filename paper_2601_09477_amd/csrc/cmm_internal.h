@@ -141,6 +141,8 @@ struct CompressArgs {
   int64_t ex_cap;          // set by the launcher: LDS entries for the extras
   int dma;                 // set by the launcher: asynchronous row copies
   int variant;             // 0: default kernel for (dtype, b_lo); 1: 32 elements per thread
+  int ovf16 = 0;           // set by the launcher: positions of the partial third
+                           // descriptor slot of the 16-element kernel (<= 512)
   // Precision form only: the two-row chains of each repetition merged ahead
   // of the kernel.  list [d][n / 2 + 1] holds a chain's plan entry (member |
   // first << 16, hi-bits xor | sign xor << 31) in chain order, count [d] their

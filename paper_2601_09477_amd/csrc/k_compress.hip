@@ -469,13 +469,22 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   // holds chain c.  A chain with more than six rows keeps its index in
   // word 2, adds only its first four rows here and is finished in the rare
   // pass.
+  // A third, partial slot (positions kSlots16 NT + i, i < ovf, held by
+  // threads i < ovf) uses the LDS the launcher found left over.
   uint32_t* dsc = reinterpret_cast<uint32_t*>(exl);   // [word][operand][slot][NT]
+  uint32_t* ovf = dsc + 3 * 2 * kSlots16 * NT;         // [word][operand][ovf]
+  const int novf = DESC ? a.ovf16 : 0;
+  const int npos = kSlots16 * NT + novf;              // descriptor positions per operand
   auto dref = [&](int word, int op, int j) -> uint32_t& {
-    return dsc[((word * 2 + op) * kSlots16 + j) * NT + threadIdx.x];
+    if (j < kSlots16) return dsc[((word * 2 + op) * kSlots16 + j) * NT + threadIdx.x];
+    return ovf[(word * 2 + op) * novf + threadIdx.x];   // threads below novf only
   };
   auto dslot = [&](int word, int op, int pos) -> uint32_t& {
-    return dsc[((word * 2 + op) * kSlots16 + pos / NT) * NT + pos % NT];
+    if (pos < kSlots16 * NT) return dsc[((word * 2 + op) * kSlots16 + pos / NT) * NT + pos % NT];
+    return ovf[(word * 2 + op) * novf + (pos - kSlots16 * NT)];
   };
+  // slot j of this thread exists (the partial slot only below novf)
+  auto has_slot = [&](int j) -> bool { return j < kSlots16 || (int)threadIdx.x < novf; };
   int nlong[2] = {0, 0};
   if constexpr (DESC) {
     // the transpose buffer is idle until the k loop: scan scratch
@@ -486,7 +495,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
       const uint2* gp = op ? gB : gA;
       const int nch = op ? nchB : nchA;
       const uint32_t pad = (uint32_t)(op ? a.n_cols : a.n_rows);
-      const bool ordered = nch <= kSlots16 * NT;
+      const bool ordered = nch <= npos;
       const int per = (nch + NT - 1) / NT;
       const int c0 = (int)threadIdx.x * per;
       int mine = 0;
@@ -510,8 +519,8 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
       nlong[op] = ordered ? total : 0;
       int lpos = wbase + incl - mine;                 // next position of a longer chain
       int ppos = total + c0 - (wbase + incl - mine);  // next position of a two-row chain
-      for (int j = 0; j < kSlots16; ++j) {            // absent chains
-        if ((int)threadIdx.x + j * NT >= nch) {
+      for (int j = 0; j <= kSlots16; ++j) {           // absent chains
+        if (has_slot(j) && (int)threadIdx.x + j * NT >= nch) {
           dref(0, op, j) = (pad + 1u + (threadIdx.x & 63u)) | (pad << 15);
           dref(1, op, j) = pad | (pad << 15);
           dref(2, op, j) = pad | (pad << 15);
@@ -523,7 +532,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
         const int beg = gc[c], end = gc[c + 1];
         int pos = c;
         if (ordered) pos = (end - beg > 1) ? lpos++ : ppos++;
-        if (pos >= kSlots16 * NT) continue;
+        if (pos >= npos) continue;
         uint32_t m[6] = {gp[beg].x >> 16, pad, pad, pad, pad, pad};
         uint32_t sg[6] = {0, 0, 0, 0, 0, 0};
         for (int r = 0; r < 5 && beg + r < end; ++r) {
@@ -545,26 +554,37 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   // with more rows stores its partial sum (in the row's own type, so no
   // extra rounding) and the rare pass continues from its fifth row.
   const int wave_pos = (int)(threadIdx.x & ~63u);
+  constexpr int kJ = kSlots16 + 1;   // full slots and the partial one
   auto fix_desc = [&]() {
     bool rare = false;
 #pragma unroll
     for (int op = 0; op < 2; ++op) {
       T* row = op ? rowB : rowA;
       const int nch_op = op ? nchB : nchA;
-      const bool all = nch_op > kSlots16 * NT;   // identity order
+      const bool all = nch_op > npos;   // identity order
       const int nl = nlong[op];
-      uint32_t q0[kSlots16];
-      T sum[kSlots16];
+      const uint32_t pad = (uint32_t)(op ? a.n_cols : a.n_rows);
+      const uint32_t absent0 = (pad + 1u + (threadIdx.x & 63u)) | (pad << 15);
+      const uint32_t padw = pad | (pad << 15);
+      // a wave takes a slot when the slot's positions in the wave hold chains
+      // (wave-uniform); a lane without the partial slot sums its spare
+      bool live[kJ];
+      uint32_t q0[kJ];
+      T sum[kJ];
 #pragma unroll
-      for (int j = 0; j < kSlots16; ++j) q0[j] = dref(0, op, j);
+      for (int jj = 0; jj < kJ; ++jj) {
+        live[jj] = (jj < kSlots16 || wave_pos < novf) && (all || wave_pos + jj * NT < nch_op);
+        q0[jj] = (live[jj] && has_slot(jj)) ? dref(0, op, jj) : absent0;
+      }
 #pragma unroll
-      for (int j = 0; j < kSlots16; ++j) {
-        if (!(all || wave_pos + j * NT < nch_op)) continue;   // wave-uniform
-        const uint32_t w0 = q0[j];
+      for (int jj = 0; jj < kJ; ++jj) {
+        if (!live[jj]) continue;
+        const uint32_t w0 = q0[jj];
         const T v1 = row[(w0 >> 15) & 0x7FFFu];
         T acc_ = row[w0 & 0x7FFFu] + flip_sign(v1, ((w0 >> 30) & 1u) << 31);
-        if (all || wave_pos + j * NT < nl) {                   // wave-uniform
-          const uint32_t w1 = dref(1, op, j), w2 = dref(2, op, j);
+        if (all || wave_pos + jj * NT < nl) {                  // wave-uniform
+          const bool hs = has_slot(jj);
+          const uint32_t w1 = hs ? dref(1, op, jj) : padw, w2 = hs ? dref(2, op, jj) : padw;
           const T v2 = row[w1 & 0x7FFFu], v3 = row[(w1 >> 15) & 0x7FFFu];
           // word 2 of a chain with more rows is its index (< n: in the row)
           const bool mr = (w0 >> 31) != 0u;
@@ -576,27 +596,28 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
             acc_ = acc_ + flip_sign(v5, ((w2 >> 31) & 1u) << 31);
           }
         }
-        sum[j] = acc_;
+        sum[jj] = acc_;
       }
 #pragma unroll
-      for (int j = 0; j < kSlots16; ++j) {
-        if (!(all || wave_pos + j * NT < nch_op)) continue;
-        rare = rare || (q0[j] >> 31) != 0u;
-        row[q0[j] & 0x7FFFu] = sum[j];
+      for (int jj = 0; jj < kJ; ++jj) {
+        if (!live[jj]) continue;
+        rare = rare || (q0[jj] >> 31) != 0u;
+        row[q0[jj] & 0x7FFFu] = sum[jj];
       }
     }
-    const bool extra = nchA > kSlots16 * NT || nchB > kSlots16 * NT;
+    const bool extra = nchA > npos || nchB > npos;
     if (rare || extra) {
 #pragma unroll
       for (int op = 0; op < 2; ++op) {
         T* row = op ? rowB : rowA;
         const int32_t* gc = op ? gcB : gcA;
         const uint2* gp = op ? gB : gA;
-        for (int j = 0; j < kSlots16; ++j) {
-          const uint32_t w0 = dref(0, op, j);
+        for (int jj = 0; jj < kJ; ++jj) {
+          if (!has_slot(jj)) continue;
+          const uint32_t w0 = dref(0, op, jj);
           if (!(w0 >> 31)) continue;
           T acc_ = row[w0 & 0x7FFFu];
-          const int c = (int)dref(2, op, j);
+          const int c = (int)dref(2, op, jj);
           const int beg = gc[c], end = gc[c + 1];
           for (int r = beg + 3; r < end; ++r) {
             const uint2 y = gp[r];
@@ -607,7 +628,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
         }
         // chains beyond the slots (identity order: disjoint targets)
         const int nch = op ? nchB : nchA;
-        for (int c = kSlots16 * NT + (int)threadIdx.x; c < nch; c += NT) {
+        for (int c = npos + (int)threadIdx.x; c < nch; c += NT) {
           const int beg = gc[c], end = gc[c + 1];
           const uint32_t tgt = gp[beg].x >> 16;
           T acc_ = row[tgt];
@@ -889,8 +910,19 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
     single = true;
   }
   if (base > kMax) { set_error("compress: rows do not fit in LDS"); return CMM_EUNSUPPORTED; }
+  // the descriptor slots, and a partial third slot in whatever LDS is left
+  // (three words per position and operand)
+  a.ovf16 = 0;
+  if (desc && !single) {
+    size_t left = kMax - base - desc_lds;
+    size_t ovf = left / (sizeof(uint32_t) * 3 * 2);
+    if (ovf > 512) ovf = 512;
+    a.ovf16 = (int)ovf;
+  }
   int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
-  const int64_t want = desc ? (int64_t)(desc_lds / sizeof(uint2)) : a.n_rows + a.n_cols;
+  const int64_t want = desc ? (int64_t)((desc_lds + sizeof(uint32_t) * 3 * 2 * (size_t)a.ovf16) /
+                                        sizeof(uint2))
+                            : a.n_rows + a.n_cols;
   if (cap > want) cap = want;
   a.ex_cap = cap;
   const size_t lds = base + sizeof(uint2) * (size_t)cap;
