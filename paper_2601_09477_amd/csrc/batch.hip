@@ -121,7 +121,11 @@ BatchLayout make_layout(const cmm_batch& b, const BatchConfig& c) {
       desc = need <= lds_cap && p.n_rows + 64 < 32768 && p.n_cols + 64 < 32768;
       dl = std::max(dl, need);
     }
-    if (desc) { L.desc = true; lds = dl; }
+    // room for a partial third descriptor slot of up to 512 positions
+    if (desc) {
+      L.desc = true;
+      lds = std::min(lds_cap, dl + sizeof(uint32_t) * 3 * 2 * 512);
+    }
   }
   L.lds = lds;
   // items
@@ -187,6 +191,12 @@ BatchLayout make_layout(const cmm_batch& b, const BatchConfig& c) {
     const size_t base = lds_base(b.cdt, c, p.n_rows, p.n_cols);
     int64_t cap = (int64_t)((lds - std::min(lds, base)) / sizeof(uint2));
     bp.ex_cap = L.desc ? 0 : std::min<int64_t>(cap, p.n_rows + p.n_cols);
+    bp.ovf16 = 0;
+    if (L.desc) {
+      const size_t need = compress16_desc_lds(b.cdt, p.n_rows, p.n_cols);
+      const size_t extra = lds > need ? (lds - need) / (sizeof(uint32_t) * 3 * 2) : 0;
+      bp.ovf16 = (int)std::min<size_t>(extra, 512);
+    }
     // 16-byte row copies: the workspace is 256-byte aligned, the caller's B is checked here
     const bool b_ok = bp.bc >= 0 || ((uintptr_t)p.B % 16 == 0);
     bp.dma = (p.n_rows % V == 0) && (p.n_cols % V == 0) && (bp.ldb % V == 0) && b_ok;

@@ -204,6 +204,7 @@ struct BatchPair {
   int64_t partial;         // [groups][d][2^log2b] float64
   int64_t ex_cap;
   int d, log2b, groups, dma;
+  int ovf16;               // partial third descriptor slot (16-element layout)
 };
 struct BatchItem {
   uint32_t pair, unit, group;   // unit = t * b_hi + u_hi

@@ -815,6 +815,7 @@ __global__ __launch_bounds__(512, waves16<T>()) void compress16_batched_kernel(
     a.ex_cap = bp.ex_cap;
     a.dma = bp.dma;
     a.variant = 0;
+    a.ovf16 = DESC ? bp.ovf16 : 0;
     const int b_hi_bits = a.log2b - LB;
     const int t = (int)(bi.unit >> b_hi_bits);
     const uint32_t uhi = bi.unit & ((1u << b_hi_bits) - 1u);
