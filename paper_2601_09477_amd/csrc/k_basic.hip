@@ -93,61 +93,27 @@ __global__ void accumulate_kernel(const T* __restrict__ X, const T* __restrict__
     double acc = p_hat[(size_t)t * b + u];
     const T* xp = X + (size_t)t * kc * b + u;
     const T* yp = Y + (size_t)t * kc * b + u;
-    for (int64_t kk = 0; kk < kc; ++kk) {
+    // the loads of 8 values of kk are issued before their adds, which stay
+    // in ascending kk order
+    int64_t kk = 0;
+    for (; kk + 8 <= kc; kk += 8) {
+      T xv[8], yv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        xv[j] = xp[(kk + j) * b];
+        yv[j] = yp[(kk + j) * b];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double prod = (double)xv[j] * (double)yv[j];
+        acc = acc + prod;
+      }
+    }
+    for (; kk < kc; ++kk) {
       const double prod = (double)xp[kk * b] * (double)yp[kk * b];
       acc = acc + prod;
     }
     p_hat[(size_t)t * b + u] = acc;
-  }
-}
-
-// The same sums for two consecutive u per thread (pair loads and stores),
-// with the loads of 8 values of kk issued before their adds; the adds stay
-// in ascending kk order, one rounded product at a time.  Needs b even and X,
-// Y, p_hat aligned to two elements.
-template <typename T> struct Pair2;
-template <> struct Pair2<double> { typedef double2 type; };
-template <> struct Pair2<float> { typedef float2 type; };
-
-template <typename T>
-__global__ __launch_bounds__(256) void accumulate2_kernel(const T* __restrict__ X,
-                                                          const T* __restrict__ Y, int64_t kc,
-                                                          int64_t b, double* __restrict__ p_hat) {
-#pragma clang fp contract(off)
-  typedef typename Pair2<T>::type V;
-  constexpr int U = 8;
-  const int t = blockIdx.y;
-  const int64_t half = b >> 1;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < half; q += stride) {
-    double2* pp = reinterpret_cast<double2*>(p_hat + (size_t)t * b) + q;
-    double2 acc = *pp;
-    const V* xp = reinterpret_cast<const V*>(X + (size_t)t * kc * b) + q;
-    const V* yp = reinterpret_cast<const V*>(Y + (size_t)t * kc * b) + q;
-    int64_t kk = 0;
-    for (; kk + U <= kc; kk += U) {
-      V xv[U], yv[U];
-#pragma unroll
-      for (int j = 0; j < U; ++j) {
-        xv[j] = xp[(kk + j) * half];
-        yv[j] = yp[(kk + j) * half];
-      }
-#pragma unroll
-      for (int j = 0; j < U; ++j) {
-        const double px = (double)xv[j].x * (double)yv[j].x;
-        const double py = (double)xv[j].y * (double)yv[j].y;
-        acc.x = acc.x + px;
-        acc.y = acc.y + py;
-      }
-    }
-    for (; kk < kc; ++kk) {
-      const V xv = xp[kk * half], yv = yp[kk * half];
-      const double px = (double)xv.x * (double)yv.x;
-      const double py = (double)xv.y * (double)yv.y;
-      acc.x = acc.x + px;
-      acc.y = acc.y + py;
-    }
-    *pp = acc;
   }
 }
 
@@ -209,20 +175,6 @@ cmm_status launch_accumulate(const void* X, const void* Y, cmm_dtype dt, int d, 
                              int log2b, double* p_hat, hipStream_t s) {
   ProfScope prof_("accumulate", s);
   const int64_t b = (int64_t)1 << log2b;
-  const size_t el = dt == CMM_F64 ? 8 : 4;
-  const bool pairs = b >= 2 && reinterpret_cast<uintptr_t>(X) % (2 * el) == 0 &&
-                     reinterpret_cast<uintptr_t>(Y) % (2 * el) == 0 &&
-                     reinterpret_cast<uintptr_t>(p_hat) % 16 == 0;
-  if (pairs) {
-    dim3 grid2(grid_for((size_t)(b >> 1), 256, 4096), d);
-    if (dt == CMM_F64)
-      hipLaunchKernelGGL(accumulate2_kernel<double>, grid2, dim3(256), 0, s, (const double*)X,
-                         (const double*)Y, kc, b, p_hat);
-    else
-      hipLaunchKernelGGL(accumulate2_kernel<float>, grid2, dim3(256), 0, s, (const float*)X,
-                         (const float*)Y, kc, b, p_hat);
-    return hip_check(hipGetLastError(), "accumulate kernel launch");
-  }
   dim3 grid(grid_for((size_t)b, 256, 4096), d);
   if (dt == CMM_F64)
     hipLaunchKernelGGL(accumulate_kernel<double>, grid, dim3(256), 0, s, (const double*)X,

@@ -130,9 +130,9 @@ def test_fwht_real_close(log2b):
     (10, 17, "f64", 0), (1, 9, "f64", 0), (12, 8, "f32", 0), (10, 17, "f64", 1),
     (11, 5, "f32", 1)])
 def test_accumulate_bit_exact(log2b, kc, dtype, offset):
-    """Pair loads on aligned operands, element loads one element past an
-    aligned address; float32 operands widen exactly; p_hat starts nonzero
-    (the sums are added into it)."""
+    """Aligned operands and operands one element past an aligned address;
+    tails of kc below the 8-wide load groups; float32 operands widen
+    exactly; p_hat starts nonzero (the sums are added into it)."""
     announce(f"accumulate log2b={log2b} kc={kc} {dtype} offset={offset}")
     t = torch()
     rng = np.random.default_rng(3 + log2b)
