@@ -68,6 +68,38 @@ ProfScope::~ProfScope() {
 
 namespace {
 
+// Compute units of the current device (256 when it cannot be queried).
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    return 256;
+  return cus;
+}
+
+// k-ranges per work unit of a fused kernel that runs one work-group per
+// CU: its units * g work-groups take ceil(units g / CUs) rounds of
+// ceil(n_inner / g) values of k each.  The g that minimises that product
+// (the fewest work-groups on ties), among those with units * g a multiple
+// of 8 for the XCD-aware order, within eight times the count that gives
+// 2048 work-groups.
+int64_t pick_groups(int64_t units, int64_t n_inner) {
+  if (n_inner <= 1 || units < 1) return 1;
+  const int64_t cus = device_cus();
+  int64_t hi = 8 * ((2048 + units - 1) / units);
+  if (hi > n_inner) hi = n_inner;
+  int64_t best = 0, best_cost = 0;
+  for (int64_t g = 1; g <= hi; ++g) {
+    if (((units * g) & 7) != 0 && g != n_inner) continue;
+    const int64_t cost = ((units * g + cus - 1) / cus) * ((n_inner + g - 1) / g);
+    if (best == 0 || cost < best_cost) {
+      best = g;
+      best_cost = cost;
+    }
+  }
+  return best > 0 ? best : 1;
+}
 
 constexpr int kMaxLog2b = 30;
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -167,11 +199,7 @@ EstimatePlan make_plan(const cmm_problem* pr) {
     P.fused = true;
     P.lb = 14;
     const int64_t units = (int64_t)d << (pr->log2b - 14);
-    int64_t g = (2048 + units - 1) / units;
-    if (g > pr->n_inner) g = pr->n_inner;
-    if (g < 1) g = 1;
-    while (g > 1 && ((units * g) & 7) != 0 && g < pr->n_inner) ++g;
-    P.groups = (int)g;
+    P.groups = (int)pick_groups(units, pr->n_inner);
     size_t off = 0;
     P.off_at = off; off = align_up(off + 2 * (size_t)pr->n_rows * pr->n_inner, 256);
     P.off_bc = off; off = align_up(off + 2 * (size_t)pr->n_inner * pr->n_cols, 256);
@@ -213,12 +241,7 @@ EstimatePlan make_plan(const cmm_problem* pr) {
   if (P.fused) {
     P.lb = lb;
     const int64_t units = (int64_t)d << (pr->log2b - lb);
-    // aim at >= 8 work-groups per CU over the 256 CUs, whole multiple of 8
-    int64_t g = (2048 + units - 1) / units;
-    if (g > pr->n_inner) g = pr->n_inner;
-    if (g < 1) g = 1;
-    while (g > 1 && ((units * g) & 7) != 0 && g < pr->n_inner) ++g;
-    P.groups = (int)g;
+    P.groups = (int)pick_groups(units, pr->n_inner);
     P.off_at = off; off = align_up(off + es * (size_t)pr->n_rows * pr->n_inner, 256);
     if (P.cdt != pr->in_dtype) {
       P.off_bc = off; off = align_up(off + es * (size_t)pr->n_inner * pr->n_cols, 256);
@@ -823,11 +846,7 @@ FftPlan make_fft_plan(const cmm_problem* pr) {
             plan_lds_bytes(pr->n_cols, 12) <= 160 * 1024;
   if (P.fused) {
     const int64_t units = (int64_t)d * (((int64_t)1 << (pr->log2b - 12)) / 2 + 1);
-    int64_t g = (2048 + units - 1) / units;
-    if (g > pr->n_inner) g = pr->n_inner;
-    if (g < 1) g = 1;
-    while (g > 1 && ((units * g) & 7) != 0 && g < pr->n_inner) ++g;
-    P.groups = (int)g;
+    P.groups = (int)pick_groups(units, pr->n_inner);
     P.off_at = off; off = align_up(off + 8 * (size_t)pr->n_rows * pr->n_inner, 256);
     P.off_planA = off; off = align_up(off + plan_bytes(pr->d, pr->n_rows, 12), 256);
     P.off_planB = off; off = align_up(off + plan_bytes(pr->d, pr->n_cols, 12), 256);
