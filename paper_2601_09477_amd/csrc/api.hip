@@ -83,12 +83,14 @@ int device_cus() {
 // ceil(n_inner / g) values of k each.  The g that minimises that product
 // (the fewest work-groups on ties), among those with units * g a multiple
 // of 8 for the XCD-aware order, within eight times the count that gives
-// 2048 work-groups.
+// 2048 work-groups and with at least 32 values of k per work-group (each
+// work-group first builds its gather offsets and collision descriptors).
 int64_t pick_groups(int64_t units, int64_t n_inner) {
   if (n_inner <= 1 || units < 1) return 1;
   const int64_t cus = device_cus();
   int64_t hi = 8 * ((2048 + units - 1) / units);
-  if (hi > n_inner) hi = n_inner;
+  if (hi > n_inner / 32) hi = n_inner / 32;
+  if (hi < 1) hi = 1;
   int64_t best = 0, best_cost = 0;
   for (int64_t g = 1; g <= hi; ++g) {
     if (((units * g) & 7) != 0 && g != n_inner) continue;
@@ -463,11 +465,7 @@ BackwardPlan make_backward_plan(const cmm_problem* pr) {
   if (kc > 65535) kc = 65535;
   if (kc < 1) kc = 1;
   P.kc = kc;
-  int64_t g = (2048 + units - 1) / units;
-  if (g > kc) g = kc;
-  if (g < 1) g = 1;
-  while (g > 1 && ((units * g) & 7) != 0 && g < kc) ++g;
-  P.groups = (int)g;
+  P.groups = (int)pick_groups(units, kc);
   // W scatter: LDS windows of 128 KB (2^15 float32 or 2^14 float64 sums),
   // about 512 work-groups
   P.sh.f32 = P.cdt == CMM_F32;
