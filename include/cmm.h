@@ -241,7 +241,11 @@ cmm_status cmm_extract_cyclic(const double* p, const uint32_t* tab1, const uint3
  *   C_hat: device out_dtype (CMM_F64 / CMM_F32) n_rows x n_cols (ldc), or
  *         NULL to run Compress only.
  * Requires n_rows, n_cols <= 2^32 and the workspace size reported by
- * cmm_workspace_size for the same problem. */
+ * cmm_workspace_size for the same problem, asked with the same device
+ * current: the split of the inner dimension over work-groups follows the
+ * device's compute-unit count, so the size can differ between devices.  A
+ * workspace smaller than the plan at call time is rejected with
+ * CMM_ENOMEM before anything is launched. */
 typedef struct {
   int64_t n_rows, n_inner, n_cols;
   const void* A; int64_t lda;
