@@ -35,9 +35,10 @@ sys.path.insert(0, ROOT)
 PEAK_F64_ADD = 256 * 4 * 16 * 2.4e9
 PEAK_HBM = 8.0e12
 PEAK_MFMA_16 = 2.5e15   # dense bf16 / fp16 matrix-core peak
-# float32 adds: 2 per lane and cycle with packed instructions (78.6e12/s);
-# this build keeps packed float32 instructions out of its code, which
-# leaves one per lane and cycle (39.3e12/s) attainable.
+# float32 adds: the published figure (78.6e12/s) counts 2 per lane and cycle,
+# which needs packed instructions.  The library is compiled without them, so
+# at most half of it (one per lane and cycle) is attainable; fractions are
+# still reported against the published figure.
 PEAK_F32_ADD = 2 * 256 * 4 * 16 * 2.4e9
 
 
@@ -559,7 +560,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              f"(the path shards over GPUs only by design, see DESIGN.md)", file=sys.stderr)
+              f"(the path runs on one GPU; sharding over several is a design note only)", file=sys.stderr)
         return 2
 
     from workloads import planted_4096
