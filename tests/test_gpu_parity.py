@@ -128,7 +128,7 @@ def test_fwht_real_close(log2b):
 # ----------------------------------------------------------- accumulate
 @pytest.mark.parametrize("log2b,kc,dtype,offset", [
     (10, 17, "f64", 0), (1, 9, "f64", 0), (12, 8, "f32", 0), (10, 17, "f64", 1),
-    (11, 5, "f32", 1)])
+    (11, 5, "f32", 1), (1, 9, "f32", 0), (2, 12, "f32", 0), (13, 3, "f64", 0)])
 def test_accumulate_bit_exact(log2b, kc, dtype, offset):
     """Aligned operands and operands one element past an aligned address;
     tails of kc below the 8-wide load groups; float32 operands widen
