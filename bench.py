@@ -52,8 +52,8 @@ PEAK_F32_ADD = 2 * 256 * 4 * 16 * 2.4e9
 TRAFFIC_SOURCES = ["paper_2601_09477_amd/csrc/k_compress.hip",
                    "paper_2601_09477_amd/csrc/wht_regs.h",
                    "paper_2601_09477_amd/csrc/api.hip"]   # the launch plan (k-ranges)
-TRAFFIC_MEASURED = {"sha1": "a9dd068234cc4a0c48cdb35766781ceaf57e0a12",
-                    "fetch_bytes": 1.5258e+09, "write_bytes": 1.7451e+08}
+TRAFFIC_MEASURED = {"sha1": "de066c4d6e40f3e7d988330b4e85fb4ebebdda7e",
+                    "fetch_bytes": 1.5274e+09, "write_bytes": 1.7450e+08}
 
 
 def compress_traffic():
@@ -102,9 +102,42 @@ def cpu_baseline(w, budget_s: float = 20.0) -> dict:
                       f"{blas_threads} BLAS threads, the rest one thread"}
 
 
+def timed_loop(step, steps: int, dominant: str, kernels, breakdown: int = 3):
+    """Time `steps` calls of step() (warm-up done by the caller).  Inside the
+    timed region only the launches of `dominant` are bracketed by the
+    library's HIP events: each event record delays the stream's next launch
+    by a few microseconds, so bracketing every kernel would slow the step
+    being timed.  `breakdown` more calls after the timed region, with every
+    kernel bracketed, give the other kernels' times.  Returns (ms per step,
+    (total ms, launches) of `dominant` in the timed region, {kernel: ms per
+    step})."""
+    import torch
+
+    import paper_2601_09477_amd as cmm
+    cmm.cmm_profile_only(dominant)
+    cmm.cmm_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    dom = cmm.cmm_profile_query(dominant)
+    cmm.cmm_profile_only(None)
+    cmm.cmm_profile_enable(True)
+    for _ in range(breakdown):
+        step()
+    torch.cuda.synchronize()
+    per_step = {k: cmm.cmm_profile_query(k)[0] / breakdown for k in kernels}
+    per_step[dominant] = dom[0] / steps
+    cmm.cmm_profile_enable(False)
+    return ms, dom, per_step
+
+
 def run_estimate(w, compute: str, steps: int, warmup: int, out_dtype=None):
     """Time `steps` full estimates of workload w (inputs resident on the GPU).
-    Returns (ms_per_step, per-kernel ms per step, C_hat on the GPU, p)."""
+    Returns (ms_per_step, (total ms, launches) of the compress in the timed
+    region, per-kernel ms per step, C_hat on the GPU, p)."""
     import torch
 
     import paper_2601_09477_amd as cmm
@@ -126,18 +159,11 @@ def run_estimate(w, compute: str, steps: int, warmup: int, out_dtype=None):
     for _ in range(warmup):
         cmm.cmm_estimate(pr, ws, nbytes, stream)
     torch.cuda.synchronize()
-    cmm.cmm_profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        cmm.cmm_estimate(pr, ws, nbytes, stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kern = {k: cmm.cmm_profile_query(k) for k in
-            ("hash", "transpose", "plan", "compress", "reduce", "fwht", "extract")}
-    cmm.cmm_profile_enable(False)
+    ms, dom, per_step = timed_loop(
+        lambda: cmm.cmm_estimate(pr, ws, nbytes, stream), steps, "compress",
+        ("hash", "transpose", "plan", "pairs", "compress", "reduce", "fwht", "extract"))
     del ws
-    return elapsed / steps * 1e3, kern, C_hat, p
+    return ms, dom, per_step, C_hat, p
 
 
 def heavy_hitter_extract(w, p, steps: int) -> dict:
@@ -252,9 +278,8 @@ def precision_form(steps: int, warmup: int) -> dict:
     ref_p = None
     ref_ms = None
     for compute in ("f64", "bf16", "f16"):
-        ms, kern, C_hat, p = run_estimate(w, compute, steps, warmup)
+        ms, (ms_c, n_c), _, C_hat, p = run_estimate(w, compute, steps, warmup)
         rec = planted_recall(C_hat.cpu().numpy(), w.rows, w.cols, w.tau)
-        ms_c, n_c = kern["compress"]
         avg_c = ms_c / max(1, n_c) * 1e-3
         entry = {"ms_per_step": ms, "value": 2.0 * w.n ** 3 / (ms * 1e-3) / 1e12,
                  "compress_ms": avg_c * 1e3,
@@ -378,25 +403,19 @@ def differentiation_form(steps: int, warmup: int) -> dict:
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    cmm.cmm_profile_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) / steps * 1e3
-    kern = {k: cmm.cmm_profile_query(k) for k in ("compress", "extract", "wscatter", "adjoint",
-                                                  "adjoint_reduce", "plan", "transpose", "fwht")}
-    cmm.cmm_profile_enable(False)
+    ms, (ms_a, n_a), per_step = timed_loop(
+        step, steps, "adjoint",
+        ("compress", "extract", "wscatter", "adjoint", "adjoint_reduce", "plan", "transpose",
+         "fwht"))
     b = 1 << w.log2b
     n, d = w.n, w.d
     # adjoint: forward transforms again, the transposed transforms (4 d n b log2 b),
     # the products (2 d n b), sketches and transposed sketches (4 d n^2)
     adj_ops = 4.0 * d * n * b * w.log2b + 2.0 * d * n * b + 4.0 * d * n * n
-    ms_a, n_a = kern["adjoint"]
     avg_a = ms_a / max(1, n_a) * 1e-3
     return {"workload": "Gaussian + 2048 planted rows (3x), n=2048, b=2^15, d=7, float32, mean",
             "ms_per_step_fwd_bwd": ms,
-            "kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
+            "kernels_ms_per_step": per_step,
             "adjoint_roofline": {"bound": "alu", "achieved": adj_ops / avg_a / 1e12,
                                  "peak": PEAK_F32_ADD / 1e12, "unit": "TFLOP/s",
                                  "frac": adj_ops / avg_a / PEAK_F32_ADD}}
@@ -431,15 +450,9 @@ def fft_form(steps: int, warmup: int, seed: int = 0) -> dict:
     for _ in range(warmup):
         cmm.cmm_estimate_fft(pr, ws, nbytes, stream)
     torch.cuda.synchronize()
-    cmm.cmm_profile_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        cmm.cmm_estimate_fft(pr, ws, nbytes, stream)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) / steps * 1e3
-    kern = {k: cmm.cmm_profile_query(k) for k in
-            ("hash", "sketch", "fft", "accumulate", "compress", "extract")}
-    cmm.cmm_profile_enable(False)
+    ms, _, per_step = timed_loop(
+        lambda: cmm.cmm_estimate_fft(pr, ws, nbytes, stream), steps, "compress",
+        ("hash", "sketch", "fft", "accumulate", "compress", "extract"))
     rec = planted_recall(C_hat.cpu().numpy(), w.rows, w.cols, w.tau)
     b = 1 << log2b
     # executed forward transforms of the fused kernel: per (t, slice u_hi <=
@@ -447,11 +460,11 @@ def fft_form(steps: int, warmup: int, seed: int = 0) -> dict:
     # count for a radix-2 transform)
     slices = (b >> 12) // 2 + 1
     flops = 2.0 * d * slices * n * 5.0 * 4096 * 12
-    comp_ms = kern["compress"][0] / steps
+    comp_ms = per_step["compress"]
     return {"workload": "planted +-1, n=4096, b=2^16, d=9 (the headline), h = h1 + h2 mod b",
             "ms_per_step": ms, "value": 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
             "unit": "TFLOP/s-equivalent (2n^3/s)",
-            "kernels_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
+            "kernels_ms_per_step": per_step,
             "compress_transform_rate_TFLOPs": flops / (comp_ms * 1e-3) / 1e12 if comp_ms > 0 else None,
             "recall": {"planted": rec["planted"], "recalled": rec["recalled"]},
             "workspace_bytes": nbytes}
@@ -575,11 +588,11 @@ def main() -> int:
         del src, dst
     w = planted_4096(args.seed)
     n, d, log2b = w.n, w.d, w.log2b
-    ms_per_step, kern, C_hat, p = run_estimate(w, "f64", args.steps, args.warmup)
+    ms_per_step, (ms_comp, n_comp), per_step, C_hat, p = run_estimate(w, "f64", args.steps,
+                                                                       args.warmup)
     rec = planted_recall(C_hat.cpu().numpy(), w.rows, w.cols, w.tau)
     heavy = heavy_hitter_extract(w, p, args.steps)
     unfused = unfused_steps(w, max(3, args.steps // 2), 1)
-    ms_comp, n_comp = kern["compress"]
     avg_comp = ms_comp / max(1, n_comp) * 1e-3
     ops = compress_ops(n, d, log2b)
     achieved = ops / avg_comp
@@ -595,7 +608,7 @@ def main() -> int:
         "recall": {"planted": rec["planted"], "recalled": rec["recalled"],
                    "recall": rec["recall"], "background_ge_tau": rec["background_ge_tau"],
                    "tau": w.tau},
-        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
+        "kernels_ms_per_step": per_step,
         "heavy_hitter_extract": heavy,
         "unfused_steps": unfused,
         "roofline": {"kernel": "compress (fused sketch + WHT + accumulate)", "bound": "alu",

@@ -351,10 +351,18 @@ cmm_status cmm_estimate_backward(const cmm_problem* prob, const void* W, int64_t
  * launches of one kernel ("hash", "transpose", "plan", "compress",
  * "reduce", "fwht", "extract", "sketch", "accumulate", "wscatter",
  * "adjoint", "adjoint_reduce", "extract_entries", "extract_heavy",
- * "extract_reps", "correctness", "fft") since the last
+ * "extract_reps", "correctness", "fft", "pairs") since the last
  * cmm_profile_enable call.  Enabling or disabling discards the records.
- * query waits for the recorded events.  Off by default. */
+ * query waits for the recorded events.  Off by default.
+ *
+ * Each event record delays the stream's next launch by a few microseconds.
+ * cmm_profile_only(kernel) brackets only the launches of that kernel (one of
+ * the names above; NULL brackets every kernel again, the default), so that a
+ * timed loop pays for two events per launch of the kernel it measures and
+ * no others.  It discards the records; an unknown name returns CMM_EINVAL
+ * and leaves the setting as it was.  The setting is process-wide. */
 void cmm_profile_enable(int on);
+cmm_status cmm_profile_only(const char* kernel);
 cmm_status cmm_profile_query(const char* kernel, double* total_ms, int* launches);
 
 /* ---------------------------------------------------------------- status */

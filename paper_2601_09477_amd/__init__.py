@@ -38,7 +38,8 @@ EXPORTED = ["cmm_hash", "cmm_hash_family", "cmm_sketch", "cmm_fwht", "cmm_accumu
             "cmm_estimate_backward", "cmm_batch_create", "cmm_batch_destroy",
             "cmm_batch_workspace_size", "cmm_batch_autotune", "cmm_batch_set_config",
             "cmm_batch_get_config", "cmm_estimate_batched", "cmm_status_string", "cmm_last_error",
-            "cmm_abi_version", "cmm_profile_enable", "cmm_profile_query"]
+            "cmm_abi_version", "cmm_profile_enable", "cmm_profile_only",
+            "cmm_profile_query"]
 
 
 class CmmError(RuntimeError):
@@ -122,6 +123,8 @@ def lib() -> ctypes.CDLL:
     L.cmm_abi_version.restype = ctypes.c_int
     L.cmm_profile_enable.argtypes = [ctypes.c_int]
     L.cmm_profile_enable.restype = None
+    L.cmm_profile_only.argtypes = [ctypes.c_char_p]
+    L.cmm_profile_only.restype = ctypes.c_int
     L.cmm_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int)]
     L.cmm_profile_query.restype = ctypes.c_int
@@ -336,6 +339,11 @@ def cmm_estimate_backward(prob: Problem, W, dA, dB, workspace, workspace_bytes: 
 
 def cmm_profile_enable(on: bool = True) -> None:
     lib().cmm_profile_enable(1 if on else 0)
+
+
+def cmm_profile_only(kernel=None) -> None:
+    """Bracket only the launches of one kernel with timing events (None: all)."""
+    _check("cmm_profile_only", lib().cmm_profile_only(kernel.encode() if kernel else None))
 
 
 def cmm_profile_query(kernel: str):

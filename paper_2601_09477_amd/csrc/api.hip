@@ -2,6 +2,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -33,6 +34,14 @@ namespace {
 std::atomic<int> g_prof_on{0};
 std::mutex g_prof_mu;
 std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> g_prof;
+std::string g_prof_only;  // guarded by g_prof_mu; empty: every kernel is bracketed
+
+// the names ProfScope is constructed with
+const char* const kProfNames[] = {
+    "hash",        "transpose",       "plan",          "compress",    "reduce",
+    "fwht",        "extract",         "sketch",        "accumulate",  "wscatter",
+    "adjoint",     "adjoint_reduce",  "extract_entries", "extract_heavy",
+    "extract_reps", "correctness",    "fft",           "pairs"};
 
 void prof_clear_locked() {
   for (auto& kv : g_prof)
@@ -46,6 +55,10 @@ void prof_clear_locked() {
 
 ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), stream_(s) {
   if (!g_prof_on.load(std::memory_order_relaxed)) return;
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_only.empty() && g_prof_only != name_) return;
+  }
   if (hipEventCreate(&start_) != hipSuccess) { start_ = nullptr; return; }
   if (hipEventRecord(start_, stream_) != hipSuccess) {
     (void)hipEventDestroy(start_);
@@ -588,6 +601,18 @@ void cmm_profile_enable(int on) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   prof_clear_locked();
   g_prof_on.store(on ? 1 : 0);
+}
+
+cmm_status cmm_profile_only(const char* kernel) {
+  if (kernel) {
+    bool known = false;
+    for (const char* k : kProfNames) known = known || std::strcmp(k, kernel) == 0;
+    if (!known) return invalid(std::string("cmm_profile_only: unknown kernel name ") + kernel);
+  }
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  prof_clear_locked();
+  g_prof_only = kernel ? kernel : "";
+  return CMM_OK;
 }
 
 cmm_status cmm_profile_query(const char* kernel, double* total_ms, int* launches) {

@@ -216,3 +216,32 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(cmm, "LIB_PATH", "/nonexistent/libcmm.so")
     with pytest.raises(cmm.CmmError):
         cmm.lib()
+
+
+def _profiled_names():
+    """Names the library's timing scopes are constructed with, from its sources."""
+    csrc = os.path.join(ROOT, "paper_2601_09477_amd", "csrc")
+    names = set()
+    for f in os.listdir(csrc):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f)) as fh:
+                names |= set(re.findall(r'ProfScope\s+\w+\("(\w+)"', fh.read()))
+    return names
+
+
+def test_profile_names_listed_in_header():
+    with open(os.path.join(ROOT, "include", "cmm.h")) as fh:
+        hdr = fh.read()
+    block = hdr[hdr.index("Tracing for measurement"):hdr.index("void cmm_profile_enable")]
+    listed = set(re.findall(r'"(\w+)"', block))
+    assert _profiled_names() == listed
+
+
+def test_profile_only_validates_names():
+    L = _lib_or_skip()
+    L.cmm_last_error.restype = ctypes.c_char_p
+    assert L.cmm_profile_only(b"no_such_kernel") == 1          # CMM_EINVAL
+    assert b"no_such_kernel" in L.cmm_last_error()
+    for name in sorted(_profiled_names()):
+        assert L.cmm_profile_only(name.encode()) == 0, name
+    assert L.cmm_profile_only(None) == 0
