@@ -306,6 +306,42 @@ def precision_form(steps: int, warmup: int) -> dict:
         out[compute] = entry
         del C_hat, p
         torch.cuda.empty_cache()
+    del ref_p
+    out["gaussian"] = precision_error_gaussian()
+    return out
+
+
+def precision_error_gaussian() -> dict:
+    """The precision form's error on the same shape with N(0,1) entries
+    (n = 8192, b = 2^18, d = 9, one planted row per row of A at scale 3):
+    on the +-1 inputs bf16 and fp16 are nearly exact, here their rounding
+    shows.  One short run per compute type; errors of p and of C_hat against
+    the float64 path on the same GPU (itself checked against the float64
+    oracle in the test suite)."""
+    import torch
+
+    from workloads import planted_8192
+    from workloads.metrics import planted_recall
+    w = planted_8192(0, gaussian=True)
+    out = {"workload": "N(0,1) entries, n=8192, b=2^18, d=9, 8192 planted rows at scale 3"}
+    ref_p = ref_C = None
+    for compute in ("f64", "bf16", "f16"):
+        ms, _, _, C_hat, p = run_estimate(w, compute, 2, 1)
+        rec = planted_recall(C_hat.cpu().numpy(), w.rows, w.cols, w.tau)
+        entry = {"ms_per_step": ms,
+                 "recall": {"recalled": rec["recalled"], "planted": rec["planted"]}}
+        if compute == "f64":
+            ref_p, ref_C = p, C_hat
+        else:
+            dp = (p - ref_p).abs()
+            dC = (C_hat - ref_C).abs()
+            entry["error_vs_f64"] = {
+                "max_abs_dp_over_max_abs_p": float(dp.max() / ref_p.abs().max()),
+                "rms_dp_over_rms_p": float(dp.pow(2).mean().sqrt() / ref_p.pow(2).mean().sqrt()),
+                "max_abs_dC_over_tau": float(dC.max() / w.tau)}
+            del C_hat, p
+        out[compute] = entry
+        torch.cuda.empty_cache()
     return out
 
 
