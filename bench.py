@@ -255,6 +255,25 @@ def unfused_steps(w, steps: int, warmup: int, kc: int = 64) -> dict:
         gbs = algo[k] / (t * 1e-3) / 1e9
         rows[k] = {"ms": t, "algorithmic_bytes": algo[k], "GB_per_s": gbs,
                    "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    # the extract against the random-gather rate at its footprint: as many
+    # gathers (d n^2) as it makes, over a table as long as p
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    gathers = d * n * n
+    cmm.cmm_gather_probe(p_hat, gathers, sink)
+    times = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        issued = cmm.cmm_gather_probe(p_hat, gathers, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    probe_rate = issued / (sorted(times)[1] * 1e-3)
+    extract_rate = gathers / (ms["extract"] * 1e-3)
+    rows["extract"].update({"gathers": gathers, "gathers_per_s": extract_rate,
+                            "probe_gathers_per_s": probe_rate,
+                            "frac_of_probe_gather_rate": extract_rate / probe_rate})
     rows["fwht"]["passes"] = passes
     rows["fwht"]["pass_GB_per_s"] = passes * rows["fwht"]["GB_per_s"]
     rows["fwht"]["pass_frac_of_hbm_peak"] = passes * rows["fwht"]["frac_of_hbm_peak"]

@@ -365,6 +365,25 @@ void cmm_profile_enable(int on);
 cmm_status cmm_profile_only(const char* kernel);
 cmm_status cmm_profile_query(const char* kernel, double* total_ms, int* launches);
 
+/* ------------------------------------------------------ gather probe */
+/* A measurement aid, not a step of the method.  Decompress (Algorithm 1)
+ * reads p at h1(i) XOR h2(j) for every entry and repetition: d n_rows n_cols
+ * random 8-byte gathers over the d 2^log2b values of p, whose rate, not HBM
+ * bandwidth, bounds the dense extract.  cmm_gather_probe issues at least
+ * `gathers` such gathers, at positions drawn uniformly (a hash of a counter
+ * and `seed`) from table[0, len), so that the extract's gather rate can be
+ * set against what the memory hierarchy gives at the same footprint.
+ *   table   device, len float64 values (read only; the caller's, e.g. p)
+ *   len     in [1, 2^32]
+ *   gathers in [1, 2^40]; rounded up to whole work-groups of 16384
+ *   sink    device, one float64; written only if the gathered values sum to
+ *           one fixed value (it keeps the loads live)
+ *   issued  host, may be NULL: receives the number of gathers issued
+ * Launches one kernel on `stream` and returns; CMM_EINVAL for a null table
+ * or sink or a size out of range. */
+cmm_status cmm_gather_probe(const double* table, int64_t len, int64_t gathers, uint32_t seed,
+                            double* sink, int64_t* issued, void* stream);
+
 /* ---------------------------------------------------------------- status */
 const char* cmm_status_string(cmm_status s);
 const char* cmm_last_error(void);

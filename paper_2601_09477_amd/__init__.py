@@ -39,7 +39,7 @@ EXPORTED = ["cmm_hash", "cmm_hash_family", "cmm_sketch", "cmm_fwht", "cmm_accumu
             "cmm_batch_workspace_size", "cmm_batch_autotune", "cmm_batch_set_config",
             "cmm_batch_get_config", "cmm_estimate_batched", "cmm_status_string", "cmm_last_error",
             "cmm_abi_version", "cmm_profile_enable", "cmm_profile_only",
-            "cmm_profile_query"]
+            "cmm_profile_query", "cmm_gather_probe"]
 
 
 class CmmError(RuntimeError):
@@ -123,6 +123,10 @@ def lib() -> ctypes.CDLL:
     L.cmm_abi_version.restype = ctypes.c_int
     L.cmm_profile_enable.argtypes = [ctypes.c_int]
     L.cmm_profile_enable.restype = None
+    L.cmm_gather_probe.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_uint32, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
+    L.cmm_gather_probe.restype = ctypes.c_int
     L.cmm_profile_only.argtypes = [ctypes.c_char_p]
     L.cmm_profile_only.restype = ctypes.c_int
     L.cmm_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -339,6 +343,18 @@ def cmm_estimate_backward(prob: Problem, W, dA, dB, workspace, workspace_bytes: 
 
 def cmm_profile_enable(on: bool = True) -> None:
     lib().cmm_profile_enable(1 if on else 0)
+
+
+def cmm_gather_probe(table, gathers: int, sink, seed: int = 0, stream=None) -> int:
+    """Random 8-byte gathers from a float64 CUDA tensor (a measurement aid);
+    returns the number issued."""
+    if table.dtype != _torch().float64 or sink.dtype != _torch().float64:
+        raise TypeError("cmm_gather_probe: table and sink must be float64")
+    issued = ctypes.c_int64(0)
+    _check("cmm_gather_probe",
+           lib().cmm_gather_probe(_ptr(table), table.numel(), int(gathers), seed & 0xFFFFFFFF,
+                                  _ptr(sink), ctypes.byref(issued), _stream(stream)))
+    return issued.value
 
 
 def cmm_profile_only(kernel=None) -> None:

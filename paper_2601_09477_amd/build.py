@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libcmm.so")
 
 SOURCES = ["api.hip", "k_basic.hip", "k_sketch.hip", "k_fwht.hip", "k_extract.hip",
            "k_compress.hip", "k_mfma.hip", "k_adjoint.hip", "batch.hip", "k_fft.hip",
-           "k_fft_compress.hip"]
+           "k_fft_compress.hip", "k_probe.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

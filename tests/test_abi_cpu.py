@@ -69,6 +69,12 @@ def test_problem_struct_layout_matches_header():
     lambda L: L.cmm_accumulate(None, 1, 0, 3, 2, 8, 1, None),           # null X
     lambda L: L.cmm_extract(1, 1, 1, 4, 8, 8, 8, 0, 1, 0, 8, None),     # median with even d
     lambda L: L.cmm_extract(1, 1, 1, 3, 8, 8, 8, 0, 1, 0, 7, None),     # ldc < n_cols
+    lambda L: L.cmm_gather_probe(None, 10, 10, 0, 1, None, None),      # null table
+    lambda L: L.cmm_gather_probe(1, 10, 10, 0, None, None, None),      # null sink
+    lambda L: L.cmm_gather_probe(1, 0, 10, 0, 1, None, None),          # empty table
+    lambda L: L.cmm_gather_probe(1, (1 << 32) + 1, 10, 0, 1, None, None),  # table too long
+    lambda L: L.cmm_gather_probe(1, 10, 0, 0, 1, None, None),          # no gathers
+    lambda L: L.cmm_gather_probe(1, 10, (1 << 40) + 1, 0, 1, None, None),  # too many
     lambda L: L.cmm_extract(1, 1, 1, 3, 8, 8, 8, 5, 1, 0, 8, None),     # unknown estimator
     lambda L: L.cmm_extract_entries(1, 1, 1, 4, 8, 8, 8, 0, 1, 1, 4, 1, 0, None),  # median, even d
     lambda L: L.cmm_extract_entries(1, 1, 1, 3, 8, 8, 8, 0, None, 1, 4, 1, 0, None),  # rows null
