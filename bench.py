@@ -635,6 +635,8 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-eval", action="store_true",
                     help="skip the evaluation protocol (variance and correctness experiments)")
+    ap.add_argument("--only-precision", action="store_true",
+                    help="run only the precision-form leg and print it (for counter runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain elementwise copy of MIB MiB (read MIB, write "
                          "MIB): the reference dispatch for hardware byte counters")
@@ -643,6 +645,10 @@ def main() -> int:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(the path runs on one GPU; sharding over several is a design note only)", file=sys.stderr)
         return 2
+    if args.only_precision:
+        # the precision form's leg alone (for hardware-counter runs of its kernels)
+        print(json.dumps({"mfma_form": precision_form(max(3, args.steps // 4), 1)}), flush=True)
+        return 0
 
     from workloads import planted_4096
     from workloads.metrics import planted_recall
