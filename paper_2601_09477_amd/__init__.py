@@ -350,6 +350,8 @@ def cmm_gather_probe(table, gathers: int, sink, seed: int = 0, stream=None) -> i
     returns the number issued."""
     if table.dtype != _torch().float64 or sink.dtype != _torch().float64:
         raise TypeError("cmm_gather_probe: table and sink must be float64")
+    if not table.is_contiguous():
+        raise ValueError("cmm_gather_probe: the table must be contiguous (its numel is the length)")
     issued = ctypes.c_int64(0)
     _check("cmm_gather_probe",
            lib().cmm_gather_probe(_ptr(table), table.numel(), int(gathers), seed & 0xFFFFFFFF,

@@ -251,3 +251,13 @@ def test_profile_only_validates_names():
     for name in sorted(_profiled_names()):
         assert L.cmm_profile_only(name.encode()) == 0, name
     assert L.cmm_profile_only(None) == 0
+
+
+def test_gather_probe_binding_rejects_strided_tables():
+    import torch
+    t = torch.zeros((4, 4), dtype=torch.float64).t()
+    with pytest.raises(ValueError):
+        cmm.cmm_gather_probe(t, 16, torch.zeros(1, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        cmm.cmm_gather_probe(torch.zeros(4, dtype=torch.float32), 16,
+                             torch.zeros(1, dtype=torch.float64))
