@@ -156,11 +156,24 @@ def _dtype_code(t) -> int:
     raise CmmError("dtype", CMM_EINVAL, f"unsupported tensor dtype {t.dtype}")
 
 
-def _ptr(t) -> Optional[int]:
+def _ptr(t, ld: bool = False) -> Optional[int]:
+    """Device address of t.  The library reads and writes dense row-major
+    extents from its size arguments: a buffer must be contiguous, and a
+    matrix passed with a leading dimension (ld=True) needs unit stride along
+    its rows and no zero strides (an expanded view covers less memory than
+    the library would touch)."""
     if t is None:
         return None
     if not t.is_cuda:
         raise CmmError("marshal", CMM_EINVAL, "tensors must live on the GPU")
+    if ld:
+        if t.dim() == 2 and t.numel() > 0 and (
+                (t.shape[1] > 1 and t.stride(1) != 1) or (t.shape[0] > 1 and t.stride(0) < t.shape[1])):
+            raise CmmError("marshal", CMM_EINVAL,
+                           "a matrix needs unit stride along its rows and a leading dimension "
+                           ">= its row length")
+    elif not t.is_contiguous():
+        raise CmmError("marshal", CMM_EINVAL, "buffers must be contiguous")
     return t.data_ptr()
 
 
@@ -198,7 +211,7 @@ def cmm_extract(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat, ldc=N
                 stream=None) -> None:
     ldc = n_cols if ldc is None else ldc
     _check("cmm_extract", lib().cmm_extract(_ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols,
-                                            log2b, estimator, _ptr(C_hat), _dtype_code(C_hat),
+                                            log2b, estimator, _ptr(C_hat, True), _dtype_code(C_hat),
                                             ldc, _stream(stream)))
 
 
@@ -225,7 +238,7 @@ def cmm_correctness_counts(C_hat, C, big_rows, big_cols, counts, threshold=0.5, 
     [big >= thr, small <= thr, big within tol, small within tol]."""
     n_rows, n_cols = C_hat.shape
     _check("cmm_correctness_counts", lib().cmm_correctness_counts(
-        _ptr(C_hat), _dtype_code(C_hat), C_hat.stride(0), _ptr(C), C.stride(0), n_rows, n_cols,
+        _ptr(C_hat, True), _dtype_code(C_hat), C_hat.stride(0), _ptr(C, True), C.stride(0), n_rows, n_cols,
         _ptr(big_rows), _ptr(big_cols), big_rows.numel(), threshold, tolerance, _ptr(counts),
         _stream(stream)))
 
@@ -298,7 +311,7 @@ def cmm_fft(x, out, inverse=False, scale=1.0, stream=None) -> None:
 def cmm_extract_cyclic(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat,
                        stream=None) -> None:
     _check("cmm_extract_cyclic", lib().cmm_extract_cyclic(
-        _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, estimator, _ptr(C_hat),
+        _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, estimator, _ptr(C_hat, True),
         _dtype_code(C_hat), C_hat.stride(0), _stream(stream)))
 
 
@@ -336,8 +349,8 @@ def cmm_estimate_backward(prob: Problem, W, dA, dB, workspace, workspace_bytes: 
                           stream=None) -> None:
     """dA, dB of L = sum(W o C_hat) for the mean-over-d estimate of ``prob``."""
     _check("cmm_estimate_backward",
-           lib().cmm_estimate_backward(ctypes.byref(prob), _ptr(W), W.stride(0), _ptr(dA),
-                                       dA.stride(0), _ptr(dB), dB.stride(0), _ptr(workspace),
+           lib().cmm_estimate_backward(ctypes.byref(prob), _ptr(W, True), W.stride(0), _ptr(dA, True),
+                                       dA.stride(0), _ptr(dB, True), dB.stride(0), _ptr(workspace),
                                        workspace_bytes, _stream(stream)))
 
 
@@ -408,8 +421,8 @@ def make_problem(A, B, d, log2b, *, keys=None, tab1=None, tab2=None, p=None, C_h
     pr = Problem()
     pr.n_rows, pr.n_inner = A.shape
     pr.n_cols = B.shape[1]
-    pr.A, pr.lda = _ptr(A), A.stride(0)
-    pr.B, pr.ldb = _ptr(B), B.stride(0)
+    pr.A, pr.lda = _ptr(A, True), A.stride(0)
+    pr.B, pr.ldb = _ptr(B, True), B.stride(0)
     pr.in_dtype = _dtype_code(A)
     pr.compute = _COMPUTE[compute]
     pr.d, pr.log2b = d, log2b
@@ -418,7 +431,7 @@ def make_problem(A, B, d, log2b, *, keys=None, tab1=None, tab2=None, p=None, C_h
     pr.tab1, pr.tab2 = _ptr(tab1), _ptr(tab2)
     pr.p = _ptr(p)
     if C_hat is not None:
-        pr.C_hat, pr.out_dtype, pr.ldc = _ptr(C_hat), _dtype_code(C_hat), C_hat.stride(0)
+        pr.C_hat, pr.out_dtype, pr.ldc = _ptr(C_hat, True), _dtype_code(C_hat), C_hat.stride(0)
     # the struct holds raw device pointers: keep the tensors alive with it
     pr._tensors = (A, B, keys, tab1, tab2, p, C_hat)
     return pr
