@@ -177,6 +177,44 @@ def _ptr(t, ld: bool = False) -> Optional[int]:
     return t.data_ptr()
 
 
+def _need(ok: bool, fn: str, msg: str) -> None:
+    """Raise CmmError(fn, CMM_EINVAL) before any launch unless ok."""
+    if not ok:
+        raise CmmError(fn, CMM_EINVAL, msg)
+
+
+def _like(t, fn: str, name: str, dtypes=None, shape=None, min_numel=None) -> None:
+    """t is a tensor of one of dtypes (torch dtypes), of exactly shape (a
+    tuple) or holding at least min_numel elements: the sizes the library
+    will read or write through t's pointer."""
+    _need(t is not None, fn, f"{name} is missing")
+    if dtypes is not None:
+        _need(t.dtype in dtypes, fn, f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if shape is not None:
+        _need(tuple(t.shape) == tuple(shape), fn,
+              f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if min_numel is not None:
+        _need(t.numel() >= min_numel, fn,
+              f"{name} holds {t.numel()} elements, the call addresses {min_numel}")
+
+
+def _floats():
+    torch = _torch()
+    return (torch.float64, torch.float32)
+
+
+def _tables(fn, tab1, tab2, d, n_rows, n_cols) -> None:
+    i32 = (_torch().int32,)
+    if n_rows > 0:
+        _like(tab1, fn, "tab1", i32, (d, n_rows))
+    if n_cols > 0:
+        _like(tab2, fn, "tab2", i32, (d, n_cols))
+
+
+def _sketch_p(fn, p, d, log2b) -> None:
+    _like(p, fn, "p", (_torch().float64,), (d, 1 << log2b))
+
+
 def _stream(stream) -> Optional[int]:
     torch = _torch()
     if stream is None:
@@ -187,29 +225,52 @@ def _stream(stream) -> Optional[int]:
 # -------------------------------------------------------- C-ABI wrappers
 def cmm_hash(keys, d, n_rows, n_cols, log2b, tab1, tab2, stream=None) -> None:
     """keys int64[d][4][2] (uint64 bits), tab1 int32[d][n_rows], tab2 int32[d][n_cols]."""
+    _like(keys, "cmm_hash", "keys", (_torch().int64,), min_numel=8 * d)
+    _tables("cmm_hash", tab1, tab2, d, n_rows, n_cols)
     _check("cmm_hash", lib().cmm_hash(_ptr(keys), d, n_rows, n_cols, log2b, _ptr(tab1),
                                       _ptr(tab2), _stream(stream)))
 
 
-def cmm_sketch(side, M, rows, cols, ld, tab, d, log2b, k0, kc, out, stream=None) -> None:
-    _check("cmm_sketch", lib().cmm_sketch(side, _ptr(M), _dtype_code(M), rows, cols, ld,
+def cmm_sketch(side, M, rows, cols, ld=None, tab=None, d=None, log2b=None, k0=0, kc=None,
+               out=None, stream=None) -> None:
+    """Count sketches of columns k0 .. k0 + kc - 1 of A (side 0, M = A) or
+    rows of B (side 1, M = B) into out [d][kc][2^log2b] (M's dtype); ld
+    defaults to M's row stride and must equal it when given."""
+    fn = "cmm_sketch"
+    _like(M, fn, "M", _floats(), (rows, cols))
+    ld = M.stride(0) if ld is None else ld
+    _need(rows <= 1 or ld == M.stride(0), fn, f"ld {ld} differs from M's row stride {M.stride(0)}")
+    _like(tab, fn, "tab", (_torch().int32,), (d, rows if side == 0 else cols))
+    _like(out, fn, "out", (M.dtype,), min_numel=d * kc << log2b)
+    _check("cmm_sketch", lib().cmm_sketch(side, _ptr(M, True), _dtype_code(M), rows, cols, ld,
                                           _ptr(tab), d, log2b, k0, kc, _ptr(out),
                                           _stream(stream)))
 
 
 def cmm_fwht(x, batch, log2b, scale=1.0, stream=None) -> None:
+    _like(x, "cmm_fwht", "x", _floats(), min_numel=batch << log2b)
     _check("cmm_fwht", lib().cmm_fwht(_ptr(x), _dtype_code(x), batch, log2b, float(scale),
                                       _stream(stream)))
 
 
 def cmm_accumulate(X, Y, d, kc, log2b, p_hat, stream=None) -> None:
+    fn = "cmm_accumulate"
+    _like(X, fn, "X", _floats(), min_numel=d * kc << log2b)
+    _like(Y, fn, "Y", (X.dtype,), min_numel=d * kc << log2b)
+    _like(p_hat, fn, "p_hat", (_torch().float64,), min_numel=d << log2b)
     _check("cmm_accumulate", lib().cmm_accumulate(_ptr(X), _ptr(Y), _dtype_code(X), d, kc,
                                                   log2b, _ptr(p_hat), _stream(stream)))
 
 
 def cmm_extract(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat, ldc=None,
                 stream=None) -> None:
-    ldc = n_cols if ldc is None else ldc
+    fn = "cmm_extract"
+    _sketch_p(fn, p, d, log2b)
+    _tables(fn, tab1, tab2, d, n_rows, n_cols)
+    _like(C_hat, fn, "C_hat", _floats(), (n_rows, n_cols))
+    ldc = C_hat.stride(0) if ldc is None else ldc
+    _need(n_rows <= 1 or ldc == C_hat.stride(0), fn,
+          f"ldc {ldc} differs from C_hat's row stride {C_hat.stride(0)}")
     _check("cmm_extract", lib().cmm_extract(_ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols,
                                             log2b, estimator, _ptr(C_hat, True), _dtype_code(C_hat),
                                             ldc, _stream(stream)))
@@ -218,6 +279,12 @@ def cmm_extract(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat, ldc=N
 def cmm_extract_entries(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, rows, cols, out,
                         stream=None) -> None:
     """out[q] = estimate at (rows[q], cols[q]); rows, cols int64 device tensors."""
+    fn = "cmm_extract_entries"
+    _sketch_p(fn, p, d, log2b)
+    _tables(fn, tab1, tab2, d, n_rows, n_cols)
+    _like(rows, fn, "rows", (_torch().int64,))
+    _like(cols, fn, "cols", (_torch().int64,), min_numel=rows.numel())
+    _like(out, fn, "out", _floats(), min_numel=rows.numel())
     _check("cmm_extract_entries", lib().cmm_extract_entries(
         _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, estimator, _ptr(rows),
         _ptr(cols), rows.numel(), _ptr(out), _dtype_code(out), _stream(stream)))
@@ -227,6 +294,12 @@ def cmm_extract_reps(p, tab1, tab2, d, n_rows, n_cols, log2b, rows, cols, out,
                      stream=None) -> None:
     """out[t][q] = the repetition-t estimate at (rows[q], cols[q]); out is a
     [d][count] float64 or float32 device tensor."""
+    fn = "cmm_extract_reps"
+    _sketch_p(fn, p, d, log2b)
+    _tables(fn, tab1, tab2, d, n_rows, n_cols)
+    _like(rows, fn, "rows", (_torch().int64,))
+    _like(cols, fn, "cols", (_torch().int64,), min_numel=rows.numel())
+    _like(out, fn, "out", _floats(), min_numel=d * rows.numel())
     _check("cmm_extract_reps", lib().cmm_extract_reps(
         _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, _ptr(rows), _ptr(cols),
         rows.numel(), _ptr(out), _dtype_code(out), _stream(stream)))
@@ -236,7 +309,13 @@ def cmm_correctness_counts(C_hat, C, big_rows, big_cols, counts, threshold=0.5, 
                            stream=None) -> None:
     """Section 5.4 counters into counts (int64 device tensor of 4):
     [big >= thr, small <= thr, big within tol, small within tol]."""
+    fn = "cmm_correctness_counts"
     n_rows, n_cols = C_hat.shape
+    _like(C_hat, fn, "C_hat", _floats())
+    _like(C, fn, "C", (_torch().float64,), (n_rows, n_cols))
+    _like(big_rows, fn, "big_rows", (_torch().int64,))
+    _like(big_cols, fn, "big_cols", (_torch().int64,), min_numel=big_rows.numel())
+    _like(counts, fn, "counts", (_torch().int64,), min_numel=4)
     _check("cmm_correctness_counts", lib().cmm_correctness_counts(
         _ptr(C_hat, True), _dtype_code(C_hat), C_hat.stride(0), _ptr(C, True), C.stride(0), n_rows, n_cols,
         _ptr(big_rows), _ptr(big_cols), big_rows.numel(), threshold, tolerance, _ptr(counts),
@@ -247,6 +326,14 @@ def cmm_extract_heavy(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, thresh
                       out_cols, out_vals, count, stream=None) -> None:
     """Entries with |C_hat| >= threshold into the lists (capacity = their length);
     count: int64 device tensor of one element, receives the number of hits."""
+    fn = "cmm_extract_heavy"
+    i64 = (_torch().int64,)
+    _sketch_p(fn, p, d, log2b)
+    _tables(fn, tab1, tab2, d, n_rows, n_cols)
+    _like(out_rows, fn, "out_rows", i64)
+    _like(out_cols, fn, "out_cols", i64, min_numel=out_rows.numel())
+    _like(out_vals, fn, "out_vals", _floats(), min_numel=out_rows.numel())
+    _like(count, fn, "count", i64, min_numel=1)
     _check("cmm_extract_heavy", lib().cmm_extract_heavy(
         _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, estimator, float(threshold),
         _ptr(out_rows), _ptr(out_cols), _ptr(out_vals), _dtype_code(out_vals), out_rows.numel(),
@@ -301,7 +388,11 @@ def cmm_estimate_fft(prob: Problem, workspace, workspace_bytes: int, stream=None
 def cmm_fft(x, out, inverse=False, scale=1.0, stream=None) -> None:
     """Batched complex transform along the last axis of complex128 tensors
     (length a power of two); out may be x when the length is <= 4096."""
+    torch = _torch()
     n = x.shape[-1]
+    _like(x, "cmm_fft", "x", (torch.complex128,))
+    _like(out, "cmm_fft", "out", (torch.complex128,), tuple(x.shape))
+    _need(n > 0 and n & (n - 1) == 0, "cmm_fft", f"length {n} is not a power of two")
     log2n = n.bit_length() - 1
     batch = x.numel() // n if n else 0
     _check("cmm_fft", lib().cmm_fft(_ptr(x), _ptr(out), batch, log2n, int(bool(inverse)),
@@ -310,6 +401,10 @@ def cmm_fft(x, out, inverse=False, scale=1.0, stream=None) -> None:
 
 def cmm_extract_cyclic(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat,
                        stream=None) -> None:
+    fn = "cmm_extract_cyclic"
+    _sketch_p(fn, p, d, log2b)
+    _tables(fn, tab1, tab2, d, n_rows, n_cols)
+    _like(C_hat, fn, "C_hat", _floats(), (n_rows, n_cols))
     _check("cmm_extract_cyclic", lib().cmm_extract_cyclic(
         _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, estimator, _ptr(C_hat, True),
         _dtype_code(C_hat), C_hat.stride(0), _stream(stream)))
@@ -348,6 +443,11 @@ def cmm_backward_workspace_size(prob: Problem) -> int:
 def cmm_estimate_backward(prob: Problem, W, dA, dB, workspace, workspace_bytes: int,
                           stream=None) -> None:
     """dA, dB of L = sum(W o C_hat) for the mean-over-d estimate of ``prob``."""
+    fn = "cmm_estimate_backward"
+    dt = (prob._tensors[0].dtype,)
+    _like(W, fn, "W", dt, (prob.n_rows, prob.n_cols))
+    _like(dA, fn, "dA", dt, (prob.n_rows, prob.n_inner))
+    _like(dB, fn, "dB", dt, (prob.n_inner, prob.n_cols))
     _check("cmm_estimate_backward",
            lib().cmm_estimate_backward(ctypes.byref(prob), _ptr(W, True), W.stride(0), _ptr(dA, True),
                                        dA.stride(0), _ptr(dB, True), dB.stride(0), _ptr(workspace),
@@ -392,6 +492,10 @@ _COMPUTE = {"f64": CMM_F64, "f32": CMM_F32, "bf16": CMM_BF16, "f16": CMM_F16}
 def cmm_hash_family(kind, keys, d, n_rows, n_cols, log2b, tab1, tab2, stream=None) -> None:
     """kind CMM_HASH_*; keys int64 [d][4][2] (multiply families) or [d][4][4][256]
     (tabulation), uint64 bits; tables as for cmm_hash."""
+    fn = "cmm_hash_family"
+    per_t = 4 * 4 * 256 if kind == CMM_HASH_TABULATION else 8
+    _like(keys, fn, "keys", (_torch().int64,), min_numel=per_t * d)
+    _tables(fn, tab1, tab2, d, n_rows, n_cols)
     _check("cmm_hash_family", lib().cmm_hash_family(kind, _ptr(keys), d, n_rows, n_cols, log2b,
                                                     _ptr(tab1), _ptr(tab2), _stream(stream)))
 
@@ -418,6 +522,21 @@ def keys_tensor(keys: np.ndarray, device="cuda"):
 
 def make_problem(A, B, d, log2b, *, keys=None, tab1=None, tab2=None, p=None, C_hat=None,
                  compute="f64", estimator="median") -> Problem:
+    fn = "make_problem"
+    torch = _torch()
+    _like(A, fn, "A", _floats())
+    _need(A.dim() == 2 and B.dim() == 2, fn, "A and B must be matrices")
+    _like(B, fn, "B", (A.dtype,))
+    _need(B.shape[0] == A.shape[1], fn,
+          f"inner dimensions differ: A is {tuple(A.shape)}, B is {tuple(B.shape)}")
+    n_rows, n_cols = A.shape[0], B.shape[1]
+    if keys is not None:
+        _like(keys, fn, "keys", (torch.int64,), min_numel=8 * d)
+    _tables(fn, tab1, tab2, d, n_rows, n_cols)
+    if p is not None:
+        _sketch_p(fn, p, d, log2b)
+    if C_hat is not None:
+        _like(C_hat, fn, "C_hat", _floats(), (n_rows, n_cols))
     pr = Problem()
     pr.n_rows, pr.n_inner = A.shape
     pr.n_cols = B.shape[1]

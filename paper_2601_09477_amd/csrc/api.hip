@@ -117,6 +117,23 @@ int64_t pick_groups(int64_t units, int64_t n_inner) {
 }
 
 constexpr int kMaxLog2b = 30;
+constexpr int kMaxFftLog2 = 24;       // two LDS-tile passes of at most 2^12 points
+// Every buffer the kernels address holds fewer than 2^31 elements: their
+// index arithmetic is not audited beyond that.
+constexpr int64_t kMaxElems = (int64_t)1 << 31;
+
+// a * b (* c) < 2^31 for non-negative factors (exact: 128-bit product)
+bool fits_elems(int64_t a, int64_t b, int64_t c = 1) {
+  if (a <= 0 || b <= 0 || c <= 0) return true;
+  return (unsigned __int128)a * (unsigned __int128)b * (unsigned __int128)c <
+         (unsigned __int128)kMaxElems;
+}
+
+cmm_status too_large(const std::string& fn, const char* what) {
+  set_error(fn + ": " + what + " would hold 2^31 or more elements, beyond the kernels' "
+            "index range");
+  return CMM_EUNSUPPORTED;
+}
 constexpr size_t kLdsBytes = 160 * 1024;
 constexpr int64_t kMaxHashDomain = (int64_t)1 << 32;
 
@@ -196,7 +213,15 @@ cmm_status validate_problem(const cmm_problem* pr, const char* fn) {
     if (!is_f64_or_f32(pr->out_dtype))
       return invalid(std::string(fn) + ": out_dtype must be CMM_F64 or CMM_F32");
     if (pr->n_rows > 0 && pr->ldc < pr->n_cols) return invalid(std::string(fn) + ": ldc < n_cols");
+    if (!fits_elems(pr->n_rows, pr->ldc)) return too_large(fn, "C_hat (n_rows x ldc)");
   }
+  if (!fits_elems(pr->n_rows, pr->lda) || !fits_elems(pr->n_rows, pr->n_inner))
+    return too_large(fn, "A (n_rows x lda)");
+  if (!fits_elems(pr->n_inner, pr->ldb) || !fits_elems(pr->n_inner, pr->n_cols))
+    return too_large(fn, "B (n_inner x ldb)");
+  if (!fits_elems(pr->d, (int64_t)1 << pr->log2b)) return too_large(fn, "p (d x 2^log2b)");
+  if (!fits_elems(pr->d, pr->n_rows) || !fits_elems(pr->d, pr->n_cols))
+    return too_large(fn, "a hash table (d x n)");
   return CMM_OK;
 }
 
@@ -693,6 +718,9 @@ cmm_status cmm_sketch(int side, const void* M, cmm_dtype dtype, int64_t rows, in
   const int64_t n_inner = side == 0 ? cols : rows;
   if (k0 + kc > n_inner) return invalid("cmm_sketch: k0 + kc exceeds the inner dimension");
   if (kc == 0) return CMM_OK;
+  if (!fits_elems(rows, ld) || !fits_elems(d, kc, (int64_t)1 << log2b) ||
+      !fits_elems(d, side == 0 ? rows : cols))
+    return too_large("cmm_sketch", "M, out or the table");
   if (!out || !tab || (rows > 0 && cols > 0 && !M)) return invalid("cmm_sketch: null pointer");
   return launch_sketch(side, M, dtype, rows, cols, ld, tab, d, log2b, k0, kc, out,
                        as_stream(stream));
@@ -708,6 +736,7 @@ cmm_status cmm_fwht(void* x, cmm_dtype dtype, int64_t batch, int log2b, double s
   const double m = std::frexp(scale, &ex);
   if (!(scale > 0) || m != 0.5) return invalid("cmm_fwht: scale must be a positive power of two");
   if (batch == 0) return CMM_OK;
+  if (!fits_elems(batch, (int64_t)1 << log2b)) return too_large("cmm_fwht", "x (batch x 2^log2b)");
   if (!x) return invalid("cmm_fwht: x is null");
   return launch_fwht(x, dtype, batch, log2b, scale, as_stream(stream));
 }
@@ -720,6 +749,8 @@ cmm_status cmm_accumulate(const void* X, const void* Y, cmm_dtype dtype, int d, 
   if ((s = check_log2b(log2b, "cmm_accumulate")) != CMM_OK) return s;
   if (kc < 0) return invalid("cmm_accumulate: negative kc");
   if (kc == 0) return CMM_OK;
+  if (!fits_elems(d, kc, (int64_t)1 << log2b))
+    return too_large("cmm_accumulate", "X and Y (d x kc x 2^log2b)");
   if (!X || !Y || !p_hat) return invalid("cmm_accumulate: null pointer");
   return launch_accumulate(X, Y, dtype, d, kc, log2b, p_hat, as_stream(stream));
 }
@@ -744,6 +775,9 @@ cmm_status cmm_extract(const double* p, const uint32_t* tab1, const uint32_t* ta
     return invalid("cmm_extract: sizes must be <= 2^32");
   if (ldc < n_cols) return invalid("cmm_extract: ldc < n_cols");
   if (n_rows == 0 || n_cols == 0) return CMM_OK;
+  if (!fits_elems(n_rows, ldc)) return too_large("cmm_extract", "C_hat (n_rows x ldc)");
+  if (!fits_elems(d, (int64_t)1 << log2b) || !fits_elems(d, n_rows) || !fits_elems(d, n_cols))
+    return too_large("cmm_extract", "p or a table");
   if (!p || !tab1 || !tab2 || !C_hat) return invalid("cmm_extract: null pointer");
   return launch_extract(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat, out_dtype,
                         ldc, as_stream(stream));
@@ -769,6 +803,8 @@ static cmm_status check_decompress(const double* p, const uint32_t* tab1, const 
     return invalid(std::string(fn) + ": sizes must be <= 2^32");
   if ((n_rows > 0 && n_cols > 0) && (!p || !tab1 || !tab2))
     return invalid(std::string(fn) + ": null pointer");
+  if (!fits_elems(d, (int64_t)1 << log2b) || !fits_elems(d, n_rows) || !fits_elems(d, n_cols))
+    return too_large(fn, "p or a table");
   return CMM_OK;
 }
 
@@ -781,6 +817,7 @@ cmm_status cmm_extract_entries(const double* p, const uint32_t* tab1, const uint
   if (s != CMM_OK) return s;
   if (count < 0) return invalid("cmm_extract_entries: negative count");
   if (count == 0) return CMM_OK;
+  if (!fits_elems(count, 1)) return too_large("cmm_extract_entries", "the entry list");
   if (!rows || !cols || !out) return invalid("cmm_extract_entries: null pointer");
   return launch_extract_entries(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, rows, cols,
                                 count, out, out_dtype, as_stream(stream));
@@ -799,6 +836,8 @@ cmm_status cmm_extract_heavy(const double* p, const uint32_t* tab1, const uint32
   if (capacity > 0 && (!out_rows || !out_cols || !out_vals))
     return invalid("cmm_extract_heavy: null output list");
   if (!(threshold >= 0.0)) return invalid("cmm_extract_heavy: threshold must be >= 0 (not NaN)");
+  if (!fits_elems(capacity, 1) || !fits_elems(n_rows, n_cols))
+    return too_large("cmm_extract_heavy", "the output list or the scanned block");
   return launch_extract_heavy(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, threshold,
                               out_rows, out_cols, out_vals, out_dtype, capacity, count,
                               as_stream(stream));
@@ -814,6 +853,7 @@ cmm_status cmm_extract_reps(const double* p, const uint32_t* tab1, const uint32_
   if (s != CMM_OK) return s;
   if (count < 0) return invalid("cmm_extract_reps: negative count");
   if (count == 0) return CMM_OK;
+  if (!fits_elems(d, count)) return too_large("cmm_extract_reps", "out (d x count)");
   if (!rows || !cols || !out) return invalid("cmm_extract_reps: null pointer");
   return launch_extract_reps(p, tab1, tab2, d, n_rows, n_cols, log2b, rows, cols, count, out,
                              out_dtype, as_stream(stream));
@@ -833,6 +873,9 @@ cmm_status cmm_correctness_counts(const void* C_hat, cmm_dtype C_hat_dtype, int6
   if (!(threshold >= 0.0) || !(tolerance >= 0.0))
     return invalid(std::string(fn) + ": threshold and tolerance must be >= 0 (not NaN)");
   if (!counts) return invalid(std::string(fn) + ": counts is null");
+  if (n_rows > 0 && n_cols > 0 && (!fits_elems(n_rows, ldh) || !fits_elems(n_rows, ldc)))
+    return too_large(fn, "C_hat or C (n_rows x leading dimension)");
+  if (!fits_elems(n_big, 1)) return too_large(fn, "the big-entry list");
   if (n_rows > 0 && n_cols > 0 && (!C_hat || !C)) return invalid(std::string(fn) + ": null matrix");
   if (n_big > 0 && (!big_rows || !big_cols)) return invalid(std::string(fn) + ": null big list");
   return launch_correctness(C_hat, C_hat_dtype, ldh, C, ldc, n_rows, n_cols, big_rows, big_cols,
@@ -897,6 +940,10 @@ cmm_status validate_fft_problem(const cmm_problem* pr, const char* fn) {
   if (s != CMM_OK) return s;
   if (pr->compute != CMM_F64 || pr->in_dtype != CMM_F64) {
     set_error(std::string(fn) + ": the FFT form runs in float64 only (compute and in_dtype CMM_F64)");
+    return CMM_EUNSUPPORTED;
+  }
+  if (pr->log2b > kMaxFftLog2) {
+    set_error(std::string(fn) + ": the FFT form's transform supports log2b <= 24");
     return CMM_EUNSUPPORTED;
   }
   if (pr->d > 63 && pr->estimator == CMM_MEDIAN && pr->C_hat) {
@@ -986,6 +1033,7 @@ cmm_status cmm_fft(const void* in, void* out, int64_t batch, int log2n, int inve
   if (inverse != 0 && inverse != 1) return invalid("cmm_fft: inverse must be 0 or 1");
   if (!std::isfinite(scale)) return invalid("cmm_fft: scale must be finite");
   if (batch == 0) return CMM_OK;
+  if (!fits_elems(batch, (int64_t)1 << log2n)) return too_large("cmm_fft", "x (batch x 2^log2n)");
   if (!in || !out) return invalid("cmm_fft: null pointer");
   if (log2n > 12 && in == out) return invalid("cmm_fft: in and out must differ when log2n > 12");
   return launch_fft(in, out, batch, log2n, inverse, scale, as_stream(stream));
@@ -1021,6 +1069,7 @@ cmm_status cmm_extract_cyclic(const double* p, const uint32_t* tab1, const uint3
   if (s != CMM_OK) return s;
   if (ldc < n_cols) return invalid("cmm_extract_cyclic: ldc < n_cols");
   if (n_rows == 0 || n_cols == 0) return CMM_OK;
+  if (!fits_elems(n_rows, ldc)) return too_large("cmm_extract_cyclic", "C_hat (n_rows x ldc)");
   if (!C_hat) return invalid("cmm_extract_cyclic: C_hat is null");
   return launch_extract(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat, out_dtype, ldc,
                         as_stream(stream), true);
@@ -1079,6 +1128,9 @@ cmm_status cmm_estimate_backward(const cmm_problem* prob, const void* W, int64_t
     return invalid("cmm_estimate_backward: lddb < n_cols");
   if ((pr->n_rows > 0 && pr->n_inner > 0 && !dA) || (pr->n_inner > 0 && pr->n_cols > 0 && !dB))
     return invalid("cmm_estimate_backward: dA / dB is null");
+  if (!fits_elems(pr->n_rows, ldw) || !fits_elems(pr->n_rows, ldda) ||
+      !fits_elems(pr->n_inner, lddb))
+    return too_large("cmm_estimate_backward", "W, dA or dB");
   const BackwardPlan P = make_backward_plan(pr);
   if (!P.ok) {
     set_error("cmm_estimate_backward: the rows do not fit the adjoint kernel's LDS");

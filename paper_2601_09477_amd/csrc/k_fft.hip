@@ -90,6 +90,10 @@ cmm_status launch_pass(const double2* in, double2* out, const PassGeom& G, int l
   const int L = 1 << logL;
   int ns = kTile / L;
   if (ns > G.S) ns = (int)G.S;
+  if (ns < 1) {
+    set_error("cmm_fft: a pass longer than the LDS tile is not supported (log2n <= 24)");
+    return CMM_EUNSUPPORTED;
+  }
   const int64_t gx = G.S / ns;
   if (gx > 0x7FFFFFFF || batch > 65535) {
     set_error("cmm_fft: batch above 65535 vectors per launch is not supported");

@@ -261,3 +261,74 @@ def test_gather_probe_binding_rejects_strided_tables():
     with pytest.raises(TypeError):
         cmm.cmm_gather_probe(torch.zeros(4, dtype=torch.float32), 16,
                              torch.zeros(1, dtype=torch.float64))
+
+
+@pytest.mark.parametrize("kw", [
+    dict(log2b=25),                 # the transform's two LDS-tile passes stop at 2^24 points
+    dict(log2b=30, d=1),
+])
+def test_fft_form_transform_length_limit(kw):
+    # refused before any launch (a pass longer than the tile used to divide
+    # by zero on the host)
+    L = _lib_or_skip()
+    n = ctypes.c_size_t(0)
+    pr = _problem(**kw)
+    assert L.cmm_fft_workspace_size(ctypes.byref(pr), ctypes.byref(n)) == cmm.CMM_EUNSUPPORTED
+    assert b"log2b <= 24" in L.cmm_last_error()
+    assert L.cmm_estimate_fft(ctypes.byref(pr), 1, 1 << 40, None) == cmm.CMM_EUNSUPPORTED
+
+
+# Buffers of 2^31 or more elements are refused on the host: the kernels'
+# index arithmetic is not audited past that.  46341^2 > 2^31 > 46340^2.
+@pytest.mark.parametrize("kw", [
+    dict(n_rows=46341, n_inner=46341, n_cols=8, lda=46341, ldb=8),   # A
+    dict(n_rows=8, n_inner=46341, n_cols=46341, lda=46341, ldb=46341),  # B
+    dict(n_rows=46341, n_inner=8, n_cols=46341, lda=8, ldb=46341, C_hat=1,
+         out_dtype=cmm.CMM_F64, ldc=46341),                          # C_hat
+    dict(n_rows=8, n_inner=8, n_cols=8, lda=8, ldb=1 << 31),         # B's leading dimension
+    dict(d=3, log2b=30),                                             # p: 3 x 2^30
+    dict(d=9999, n_rows=1 << 18, n_inner=1, lda=1),                  # table d x n_rows
+])
+def test_problem_beyond_index_range(kw):
+    L = _lib_or_skip()
+    n = ctypes.c_size_t(0)
+    pr = _problem(**kw)
+    assert L.cmm_workspace_size(ctypes.byref(pr), ctypes.byref(n)) == cmm.CMM_EUNSUPPORTED
+    assert b"2^31" in L.cmm_last_error()
+    assert L.cmm_estimate(ctypes.byref(pr), 1, 1 << 62, None) == cmm.CMM_EUNSUPPORTED
+    assert L.cmm_estimate_fft(ctypes.byref(pr), 1, 1 << 62, None) == cmm.CMM_EUNSUPPORTED
+
+
+def test_problem_just_inside_index_range():
+    # 46340^2 < 2^31: the size checks pass (only the workspace is sized)
+    L = _lib_or_skip()
+    n = ctypes.c_size_t(0)
+    pr = _problem(n_rows=46340, n_inner=46340, n_cols=8, lda=46340, ldb=8)
+    assert L.cmm_workspace_size(ctypes.byref(pr), ctypes.byref(n)) == cmm.CMM_OK
+
+
+@pytest.mark.parametrize("call", [
+    lambda L: L.cmm_sketch(0, 1, 0, 46341, 46341, 46341, 1, 1, 8, 0, 1, 1, None),  # M
+    lambda L: L.cmm_sketch(0, 1, 0, 8, 1 << 20, 1 << 20, 1, 9, 20, 0, 1 << 20, 1, None),  # out
+    lambda L: L.cmm_fwht(1, 0, 1 << 12, 20, 1.0, None),                  # 2^32 elements
+    lambda L: L.cmm_accumulate(1, 1, 0, 9, 1 << 12, 20, 1, None),
+    lambda L: L.cmm_extract(1, 1, 1, 3, 46341, 46341, 8, 0, 1, 0, 46341, None),
+    lambda L: L.cmm_extract_cyclic(1, 1, 1, 3, 46341, 46341, 8, 0, 1, 0, 46341, None),
+    lambda L: L.cmm_extract_reps(1, 1, 1, 1000, 8, 8, 8, 1, 1, 1 << 22, 1, 0, None),
+    lambda L: L.cmm_extract_entries(1, 1, 1, 3, 8, 8, 30, 0, 1, 1, 4, 1, 0, None),  # p 3 x 2^30
+    lambda L: L.cmm_correctness_counts(1, 0, 46341, 1, 46341, 46341, 46341, 1, 1, 1, 0.5, 0.1,
+                                       1, None),
+    lambda L: L.cmm_fft(1, 2, 1 << 12, 20, 0, 1.0, None),
+])
+def test_standalone_calls_beyond_index_range(call):
+    L = _lib_or_skip()
+    assert call(L) == cmm.CMM_EUNSUPPORTED
+    assert b"2^31" in L.cmm_last_error()
+
+
+def test_backward_beyond_index_range():
+    L = _lib_or_skip()
+    pr = _problem(estimator=cmm.CMM_MEAN, log2b=12)
+    # W with a leading dimension of 2^28 over 8 rows: 2^31 elements
+    assert L.cmm_estimate_backward(ctypes.byref(pr), 1, 1 << 28, 1, 8, 1, 8, 1, 1 << 40,
+                                   None) == cmm.CMM_EUNSUPPORTED

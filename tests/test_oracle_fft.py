@@ -61,6 +61,55 @@ def test_injective_tables_recover_product():
     assert np.array_equal(O.extract_cyclic(p, t1, t2, "mean"), C)
 
 
+def test_extract_cyclic_wrapping_tables_recover_product():
+    # h1(i) = 40 + i, h2(j) = (30 + 8 j) mod 64 with b = 64: the sums
+    # h1 + h2 = 70 + i + 8 j carry past b and wrap, and (h1 + h2) mod b =
+    # 6 + i + 8 j (mod 64) is injective over the 8 x 8 entries, so
+    # Decompress of the cyclic bucket sums returns C exactly.  Gathering at
+    # h1 xor h2 or at the unwrapped sum would not (checked below), so this
+    # pins the index of Pagh's Decompress, h = h1 + h2 mod b (Section 3.1).
+    rng = np.random.default_rng(12)
+    A = rng.integers(-4, 5, (8, 6)).astype(float)
+    B = rng.integers(-4, 5, (6, 8)).astype(float)
+    C = A @ B
+    h1 = 40 + np.arange(8)
+    h2 = (30 + 8 * np.arange(8)) % 64
+    t1 = np.vstack([_tabs(h1, rng.integers(0, 2, 8)) for _ in range(3)])
+    t2 = np.vstack([_tabs(h2, rng.integers(0, 2, 8)) for _ in range(3)])
+    p = O.bucket_sums_cyclic(C, t1, t2, 6)
+    assert np.array_equal(O.extract_cyclic(p, t1, t2, "median"), C)
+    assert np.array_equal(O.extract_cyclic(p, t1, t2, "mean"), C)
+    # the mutations a wrong index would make fail to recover C
+    s = O.sign(t1[0])[:, None] * O.sign(t2[0])[None, :]
+    xor_idx = h1[:, None] ^ h2[None, :]
+    assert not np.array_equal(s * p[0][xor_idx], C)
+    assert ((h1[:, None] + h2[None, :]) >= 64).any()      # the unwrapped sum leaves the table
+
+
+def test_extract_cyclic_against_entrywise_loop():
+    # tables whose sums carry and wrap (b = 64): h1(i) = 40 + i, h2(j) = 30 + 5 j;
+    # the estimate of every entry from its own loop over repetitions, with
+    # Python integers for the bucket and the median as the middle of the sorted values
+    rng = np.random.default_rng(13)
+    d, nr, nc, b = 5, 9, 7, 64
+    h1 = 40 + np.arange(nr)
+    h2 = (30 + 5 * np.arange(nc)) % b
+    t1 = np.vstack([_tabs(h1, rng.integers(0, 2, nr)) for _ in range(d)])
+    t2 = np.vstack([_tabs(h2, rng.integers(0, 2, nc)) for _ in range(d)])
+    p = rng.standard_normal((d, b))
+    med = O.extract_cyclic(p, t1, t2, "median")
+    mean = O.extract_cyclic(p, t1, t2, "mean")
+    for i in range(nr):
+        for j in range(nc):
+            vals = []
+            for t in range(d):
+                bucket = (int(h1[i]) + int(h2[j])) % b
+                sgn = (-1.0 if t1[t][i] >> 31 else 1.0) * (-1.0 if t2[t][j] >> 31 else 1.0)
+                vals.append(sgn * p[t][bucket])
+            assert med[i, j] == sorted(vals)[d // 2]
+            assert abs(mean[i, j] - sum(vals) / d) <= 1e-15 * max(1.0, max(map(abs, vals)))
+
+
 def test_plain_definition_brute_force():
     w = small_random(7, 4, 5, 3, 2, seed=3, integer=True)
     t1, t2 = O.hash_tables(w.keys, 7, 5, 3)
@@ -98,8 +147,8 @@ def test_cyclic_estimator_unbiased_with_variance_bound():
     t1, t2 = O.hash_tables(keys, 12, 14, log2b)
     p = O.bucket_sums_cyclic(C, t1, t2, log2b)
     i, j = 3, 7
-    x = np.array([O.sign(t1[t][i]) * O.sign(t2[t][j]) *
-                  p[t][(O.bucket(t1[t][i]) + O.bucket(t2[t][j])) % (1 << log2b)]
+    # each draw's estimate through Decompress itself (one repetition at a time)
+    x = np.array([O.extract_cyclic(p[t:t + 1], t1[t:t + 1], t2[t:t + 1], "median")[i, j]
                   for t in range(draws)])
     bound = (np.linalg.norm(C) ** 2 - C[i, j] ** 2) / (1 << log2b)
     assert abs(x.mean() - C[i, j]) <= 4 * np.sqrt(bound / draws)
