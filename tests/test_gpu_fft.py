@@ -105,23 +105,24 @@ def test_estimate_fft_degenerate_and_tables():
 
 
 def test_estimate_fft_planted_4096_full_size():
-    """n = 4096, b = 2^16, d = 9: the FFT form on the headline workload;
-    sampled entries of p against the oracle (bucket sums of the exact
-    integer product on 64 sampled rows would not give whole buckets, so p is
-    checked through its integrality and the recall of every planted pair)."""
+    """n = 4096, b = 2^16, d = 9: the FFT form on the headline workload.
+    Every entry of p against the oracle's cyclic bucket sums of the exact
+    integer product: the float64 transform's rounding stays far below 1/2,
+    so p rounds to the oracle's integers exactly; C_hat on every 37th row
+    against the oracle's cyclic Decompress; every planted pair recalled."""
     from workloads.metrics import planted_recall
     announce("estimate fft planted n=4096")
     w = planted_4096(0)
     res = cmm.estimate_fft(dev(w.A), dev(w.B), w.d, w.log2b, keys=w.keys)
     p = host(res.p)
-    # integer data: every bucket sum is an integer; the transform's rounding
-    # stays far below 1/2
-    assert np.abs(p - np.rint(p)).max() < 1e-6
+    t1, t2 = O.hash_tables(w.keys, 4096, 4096, w.log2b)
+    p_ref = O.bucket_sums_cyclic(O.product(w.A, w.B), t1, t2, w.log2b)
+    dp = np.abs(p - p_ref).max()
+    print(f"fft full size: max|p - p_ref| = {dp:.3e}", flush=True)
+    assert dp < 1e-6
+    assert np.array_equal(np.rint(p), p_ref)
+    rows = np.arange(0, 4096, 37)
+    C_ref = O.extract_cyclic(p_ref, t1[:, rows], t2, "median")
+    assert np.abs(host(res.C_hat)[rows] - C_ref).max() < 1e-6
     rec = planted_recall(host(res.C_hat), w.rows, w.cols, w.tau)
     assert rec["recalled"] == rec["planted"]
-    # the cyclic sketch of the rows' planted structure: sum over all buckets
-    # of p_t equals sum_ij s1 s2 C_ij, i.e. (s1^T A)(B s2)
-    t1, t2 = O.hash_tables(w.keys, 4096, 4096, w.log2b)
-    for t in range(2):
-        s1, s2 = O.sign(t1[t]), O.sign(t2[t])
-        assert abs(p[t].sum() - (s1 @ w.A) @ (w.B @ s2)) <= 1e-6 * np.abs(p[t]).sum()

@@ -11,6 +11,7 @@ import oracle as O
 import paper_2601_09477_amd as cmm
 from workloads import draw_keys, exact_sparse_256, hadamard_sparse, small_random
 from tests.gpu_util import announce, dev, host, tables_dev, torch
+from tests.numerics import f32_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -270,8 +271,12 @@ def test_estimate_f32_compute():
     C = O.product(A32, B32)
     p_ref = O.bucket_sums(C, t1, t2, w.log2b)
     C_ref = O.extract(p_ref, t1, t2, "median")
-    scale = np.linalg.norm(C) / 128
-    assert np.max(np.abs(host(res.C_hat) - C_ref)) <= 1e-4 * scale
+    # the float32 tolerance derived in tests/numerics.py (every butterfly
+    # level and the accumulation over the 128 values of k round)
+    tol = f32_tolerance(A32, B32, w.log2b, k_run=128)
+    print(f"f32: max|dp| {np.abs(host(res.p) - p_ref).max() / tol:.3f} of tol", flush=True)
+    assert np.max(np.abs(host(res.p) - p_ref)) <= tol
+    assert np.max(np.abs(host(res.C_hat) - C_ref)) <= tol
 
 
 def test_estimate_zero_inner_dimension():
