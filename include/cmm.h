@@ -266,6 +266,23 @@ cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes);
 cmm_status cmm_estimate(const cmm_problem* prob, void* workspace, size_t workspace_bytes,
                         void* stream);
 
+/* cmm_estimate without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same problem, outputs, kernels and results as
+ * cmm_estimate; the scratch the workspace would hold comes from a static
+ * device array of CMM_STATIC_SCRATCH_BYTES per device, so the call allocates
+ * nothing (and creates no timing events: kernels run untimed even while
+ * cmm_profile_enable is on).  A problem whose cmm_workspace_size exceeds
+ * CMM_STATIC_SCRATCH_BYTES is rejected with CMM_EUNSUPPORTED before any
+ * launch (about n <= 1024 at b = 16 n, d = 7 in float64).  Every call on
+ * one device shares that device's array and finds the previous call's
+ * contents in it (every kernel writes what it reads first): calls that
+ * overlap in time on one device, on any streams or threads, race and must be
+ * serialised by the caller.  The array is taken from the device current at
+ * the call. */
+#define CMM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+cmm_status cmm_estimate_static(const cmm_problem* prob, void* stream);
+
 /* Pagh's FFT form end to end (Section 3.1): the same problem description,
  * float64 only (compute and in_dtype CMM_F64, else CMM_EUNSUPPORTED); p
  * receives the cyclic sketch and C_hat the cyclic Decompress.  Composed of

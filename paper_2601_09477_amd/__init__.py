@@ -34,7 +34,8 @@ EXPORTED = ["cmm_hash", "cmm_hash_family", "cmm_sketch", "cmm_fwht", "cmm_accumu
             "cmm_extract_entries", "cmm_extract_heavy", "cmm_extract_reps",
             "cmm_correctness_counts", "cmm_fft", "cmm_extract_cyclic", "cmm_fft_workspace_size",
             "cmm_estimate_fft",
-            "cmm_workspace_size", "cmm_estimate", "cmm_backward_workspace_size",
+            "cmm_workspace_size", "cmm_estimate", "cmm_estimate_static",
+            "cmm_backward_workspace_size",
             "cmm_estimate_backward", "cmm_batch_create", "cmm_batch_destroy",
             "cmm_batch_workspace_size", "cmm_batch_autotune", "cmm_batch_set_config",
             "cmm_batch_get_config", "cmm_estimate_batched", "cmm_status_string", "cmm_last_error",
@@ -98,6 +99,7 @@ def lib() -> ctypes.CDLL:
         "cmm_correctness_counts": [vp, i32, i64, vp, i64, i64, i64, vp, vp, i64, dbl, dbl, vp, vp],
         "cmm_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
         "cmm_estimate": [ctypes.POINTER(Problem), vp, ctypes.c_size_t, vp],
+        "cmm_estimate_static": [ctypes.POINTER(Problem), vp],
         "cmm_backward_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
         "cmm_estimate_backward": [ctypes.POINTER(Problem), vp, i64, vp, i64, vp, i64, vp,
                                   ctypes.c_size_t, vp],
@@ -373,6 +375,12 @@ def cmm_estimate(prob: Problem, workspace, workspace_bytes: int, stream=None) ->
                                               workspace_bytes, _stream(stream)))
 
 
+def cmm_estimate_static(prob: Problem, stream=None) -> None:
+    """cmm_estimate with the library's static scratch instead of a workspace
+    (allocates nothing; problems up to CMM_STATIC_SCRATCH_BYTES of scratch)."""
+    _check("cmm_estimate_static", lib().cmm_estimate_static(ctypes.byref(prob), _stream(stream)))
+
+
 def cmm_fft_workspace_size(prob: Problem) -> int:
     n = ctypes.c_size_t(0)
     _check("cmm_fft_workspace_size",
@@ -565,11 +573,14 @@ class Estimate:
 
 def estimate(A, B, d: int, log2b: int, *, keys=None, tab1=None, tab2=None,
              compute: str = "f64", estimator: str = "median", out_dtype=None,
-             dense: bool = True, workspace=None, stream=None) -> Estimate:
+             dense: bool = True, workspace=None, static_scratch: bool = False,
+             stream=None) -> Estimate:
     """Compressed product of A (n_rows x n_inner) and B (n_inner x n_cols).
 
     Give either ``keys`` (uint64[d][4][2], numpy or an int64 device tensor)
-    or explicit tables ``tab1`` / ``tab2`` (int32 device tensors)."""
+    or explicit tables ``tab1`` / ``tab2`` (int32 device tensors).  With
+    ``static_scratch`` the library's static scratch replaces the workspace
+    (cmm_estimate_static)."""
     torch = _torch()
     dev = A.device
     n_rows, n_cols = A.shape[0], B.shape[1]
@@ -584,6 +595,9 @@ def estimate(A, B, d: int, log2b: int, *, keys=None, tab1=None, tab2=None,
         C_hat = torch.empty((n_rows, n_cols), dtype=out_dtype or A.dtype, device=dev)
     pr = make_problem(A, B, d, log2b, keys=keys, tab1=tab1, tab2=tab2, p=p, C_hat=C_hat,
                       compute=compute, estimator=estimator)
+    if static_scratch:
+        cmm_estimate_static(pr, stream)
+        return Estimate(C_hat, p, tab1, tab2)
     nbytes = cmm_workspace_size(pr)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)

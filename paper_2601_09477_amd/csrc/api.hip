@@ -53,8 +53,12 @@ void prof_clear_locked() {
 }
 }  // namespace
 
+// Set on the calling thread while an entry point that must not create any
+// runtime object (cmm_estimate_static) runs: its kernels are not timed.
+thread_local bool t_prof_suppressed = false;
+
 ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), stream_(s) {
-  if (!g_prof_on.load(std::memory_order_relaxed)) return;
+  if (t_prof_suppressed || !g_prof_on.load(std::memory_order_relaxed)) return;
   {
     std::lock_guard<std::mutex> g(g_prof_mu);
     if (!g_prof_only.empty() && g_prof_only != name_) return;
@@ -1073,6 +1077,74 @@ cmm_status cmm_extract_cyclic(const double* p, const uint32_t* tab1, const uint3
   if (!C_hat) return invalid("cmm_extract_cyclic: C_hat is null");
   return launch_extract(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, C_hat, out_dtype, ldc,
                         as_stream(stream), true);
+}
+
+}  // extern "C"
+
+// ------------------------------------------- estimate without allocation
+// Scratch of cmm_estimate_static: a file-scope device array, one copy per
+// device, held until the process ends.  In host code its name stands for a
+// host-side shadow, not device memory: kernels only ever receive the
+// per-device address hipGetSymbolAddress returns (taken once per device,
+// with that device current, on the entry point's first call there).
+namespace {
+static __device__ __align__(256) unsigned char scratch[CMM_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+cmm_status static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_check(e, "cmm_estimate_static: current device");
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("cmm_estimate_static: device ordinal out of range");
+    return CMM_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_check(e, "cmm_estimate_static: scratch address");
+    if (!ptr) {
+      set_error("cmm_estimate_static: no scratch address on this device");
+      return CMM_EHIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CMM_OK;
+}
+
+// Kernel timing off on this thread for the lifetime of the guard.
+struct NoProfiling {
+  NoProfiling() { t_prof_suppressed = true; }
+  ~NoProfiling() { t_prof_suppressed = false; }
+};
+}  // namespace
+
+extern "C" {
+
+cmm_status cmm_estimate_static(const cmm_problem* prob, void* stream) {
+  cmm_status s = validate_problem(prob, "cmm_estimate_static");
+  if (s != CMM_OK) return s;
+  if (prob->d > 63 && prob->estimator == CMM_MEDIAN && prob->C_hat) {
+    set_error("cmm_estimate_static: median over more than 63 repetitions is not implemented");
+    return CMM_EUNSUPPORTED;
+  }
+  const EstimatePlan P = make_plan(prob);
+  if (P.bytes > (size_t)CMM_STATIC_SCRATCH_BYTES) {
+    set_error("cmm_estimate_static: the problem needs " + std::to_string(P.bytes) +
+              " bytes of scratch, more than the " +
+              std::to_string((size_t)CMM_STATIC_SCRATCH_BYTES) +
+              " of the static array; use cmm_estimate with a workspace");
+    return CMM_EUNSUPPORTED;
+  }
+  void* ws = nullptr;
+  if ((s = static_scratch(&ws)) != CMM_OK) return s;
+  NoProfiling guard;
+  return run_estimate(prob, static_cast<char*>(ws), as_stream(stream));
 }
 
 cmm_status cmm_workspace_size(const cmm_problem* prob, size_t* bytes) {
