@@ -107,14 +107,16 @@ template <typename IN, int NT>
 __device__ __forceinline__ void stage_row_lp(IN* __restrict__ dst, const IN* __restrict__ src,
                                              int64_t n, bool dma) {
   if (dma) {
-    const int64_t chunks = n / 8;
+    // the wave's first chunk is wave-uniform (readfirstlane), so the LDS
+    // destination of every load is a scalar value; chunks < 2^31 (n < 2^34)
+    const int chunks = (int)(n / 8);
     const int lane = threadIdx.x & 63;
-    const int64_t wbase = threadIdx.x & ~63;
-    for (int64_t c0 = wbase; c0 < chunks; c0 += NT) {
+    const int wbase = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * 64;
+    for (int c0 = wbase; c0 < chunks; c0 += NT) {
       if (c0 + lane < chunks)
         __builtin_amdgcn_global_load_lds(
-            (const void*)(src + (c0 + lane) * 8),
-            (__attribute__((address_space(3))) void*)(dst + c0 * 8), 16, 0, 0);
+            (const void*)(src + (size_t)(c0 + lane) * 8),
+            (__attribute__((address_space(3))) void*)(dst + (size_t)c0 * 8), 16, 0, 0);
     }
   } else {
     for (int64_t i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
@@ -140,6 +142,12 @@ __device__ __forceinline__ uint32_t pack2(float x, float y, _Float16*) {
 // They are separate instances because the chain-walking code alone, even
 // unexecuted, costs the loop a quarter of its speed.
 constexpr int kSlots = 4;      // descriptor slots per thread and operand
+
+struct RareLists {
+  const int32_t* gc[2];   // chain starts per operand
+  const uint2* gp[2];     // chain entries per operand
+  int nch[2];             // chains per operand
+};
 constexpr int kDescLds = 2 * kSlots * kNT * 12;   // three words per descriptor
 
 template <typename IN, bool DESC>
@@ -388,16 +396,35 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
         asm volatile("" : "+v"(q0[op][j]));
       }
   }
-  auto fix_desc = [&](const int32_t* gcA_, const uint2* gpA_, const int32_t* gcB_, const uint2* gpB_) {
-    // Every slot's target and first row, straight-line so that all the reads
-    // are in flight together (an absent slot reads its lane's spare element
-    // and the zero pad, and writes the spare back unchanged).
+  // The chain lists the rare pass of the fix-ups walks, kept in LDS rather
+  // than in scalar registers for the whole k loop (read through volatile
+  // loads there, so they are not hoisted back into registers).
+  __shared__ RareLists s_rare;
+  if (threadIdx.x == 0) {
+    s_rare.gc[0] = gcA; s_rare.gc[1] = gcB;
+    s_rare.gp[0] = gA; s_rare.gp[1] = gB;
+    s_rare.nch[0] = nchA; s_rare.nch[1] = nchB;
+  }
+  auto fix_desc = [&]() {
+    // A slot is live in a wave when one of the wave's positions in it holds
+    // a chain (wave-uniform; every position is live when the chains exceed
+    // the slots).  Every live slot's target and first row are read
+    // straight-line so that all the reads are in flight together (an absent
+    // position of a live slot reads its lane's spare element and the zero
+    // pad, and writes the spare back unchanged).
+    bool live[2][kSlots];
+#pragma unroll
+    for (int op = 0; op < 2; ++op)
+#pragma unroll
+      for (int j = 0; j < kSlots; ++j)
+        live[op][j] = ndesc[op] > kSlots * kNT || wave_pos + j * kNT < ndesc[op];
     IN r0[2][kSlots], r1[2][kSlots];
 #pragma unroll
     for (int op = 0; op < 2; ++op) {
       const IN* row = op ? rowB : rowA;
 #pragma unroll
       for (int j = 0; j < kSlots; ++j) {
+        if (!live[op][j]) continue;
         r0[op][j] = row[q0[op][j] & 0x7FFFu];
         r1[op][j] = row[(q0[op][j] >> 15) & 0x7FFFu];
       }
@@ -407,6 +434,7 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
     for (int op = 0; op < 2; ++op)
 #pragma unroll
       for (int j = 0; j < kSlots; ++j) {
+        if (!live[op][j]) continue;
         const float v1 = to_f(r1[op][j]);
         sum[op][j] = to_f(r0[op][j]) + (((q0[op][j] >> 30) & 1u) ? -v1 : v1);
       }
@@ -418,7 +446,7 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
       const bool all_long = ndesc[op] > kSlots * kNT;
 #pragma unroll
       for (int j = 0; j < kSlots; ++j) {
-        if (all_long || wave_pos + j * kNT < nl) {   // wave-uniform
+        if (live[op][j] && (all_long || wave_pos + j * kNT < nl)) {   // wave-uniform
           const uint32_t w0 = q0[op][j];
           const uint32_t w1 = dref(1, op, j), w2 = dref(2, op, j);
           const float v2 = to_f(row[w1 & 0x7FFFu]), v3 = to_f(row[(w1 >> 15) & 0x7FFFu]);
@@ -444,6 +472,7 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
       const uint32_t spare = (uint32_t)(op ? a.n_cols : a.n_rows) + 1u + (threadIdx.x & 63u);
 #pragma unroll
       for (int j = 0; j < kSlots; ++j) {
+        if (!live[op][j]) continue;
         const bool more = (q0[op][j] >> 31) != 0u;
         rare = rare || more;
         row[more ? spare : (q0[op][j] & 0x7FFFu)] = (IN)sum[op][j];
@@ -451,11 +480,12 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
     }
     const bool extra = ndesc[0] > kSlots * kNT || ndesc[1] > kSlots * kNT;
     if (rare || extra) {
+      const volatile RareLists* rl = &s_rare;
 #pragma unroll
       for (int op = 0; op < 2; ++op) {
         IN* row = op ? rowB : rowA;
-        const int32_t* gc = op ? gcB_ : gcA_;
-        const uint2* gp = op ? gpB_ : gpA_;
+        const int32_t* gc = rl->gc[op];
+        const uint2* gp = rl->gp[op];
         for (int j = 0; j < kSlots; ++j) {
           if (!(q0[op][j] >> 31)) continue;
           // a bucket of seven or more rows: the target and rows 1..3 are
@@ -473,7 +503,7 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
           row[tgt] = (IN)acc_;
         }
         // chains beyond the slots (identity order; disjoint targets)
-        const int nch = op ? nchB : nchA;
+        const int nch = rl->nch[op];
         for (int c = kSlots * kNT + (int)threadIdx.x; c < nch; c += kNT) {
           const int beg = gc[c], end = gc[c + 1];
           const uint32_t tgt = gp[beg].x >> 16;
@@ -630,7 +660,7 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
     __syncthreads();   // rows of k staged; the transpose buffers are free
     if ((DESC ? ndesc[0] + ndesc[1] : nchA + nchB) > 0) {
       if constexpr (DESC) {
-        fix_desc(gcA, gA, gcB, gB);
+        fix_desc();
       } else {
         { if (ex_lds) fix_chains_lp<IN, kNT>(rowA, lexA, lcsA, nchA, uhi); else fix_chains_lp<IN, kNT>(rowA, gA, gcA, nchA, uhi); }
         { if (ex_lds) fix_chains_lp<IN, kNT>(rowB, lexB, lcsB, nchB, uhi); else fix_chains_lp<IN, kNT>(rowB, gB, gcB, nchB, uhi); }
