@@ -168,6 +168,29 @@ cmm_status cmm_extract_heavy(const double* p, const uint32_t* tab1, const uint32
                              void* out_vals, cmm_dtype out_dtype, int64_t capacity,
                              int64_t* count, void* stream);
 
+/* Top-K heavy hitters: the k entries of largest |C_hat| over the dense
+ * n_rows x n_cols block (Algorithm 1's Decompress at every entry, keeping
+ * only the largest ones: the large entries of the product are what the
+ * method is for, Section 1), without writing the dense C_hat.  out_rows,
+ * out_cols (device int64[k]) and out_vals (device out_dtype[k]) receive them
+ * sorted by |C_hat| descending, ties by the smaller row-major index
+ * i * n_cols + j; the values are those cmm_extract gives, bit for bit (a NaN
+ * estimate ranks above every number).  0 <= k <= n_rows * n_cols (k = 0 is a
+ * no-op), k < 2^31 - 2^15; CMM_MEDIAN needs odd d <= 63.  An exact radix
+ * selection on 12-bit digits of the key (|C_hat|, index), all on the device
+ * with no host synchronisation: a few passes that evaluate the estimates
+ * (two at the benchmark sizes, at most eight), one that collects at most
+ * k + 16384 candidates, and a stable sort of those.  The workspace, from
+ * cmm_topk_workspace_size, holds the selection state and the candidates;
+ * the size query reads the current device's sort configuration, so it needs
+ * a current device (CMM_EHIP otherwise). */
+cmm_status cmm_topk_workspace_size(int64_t k, size_t* bytes);
+cmm_status cmm_extract_topk(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                            int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
+                            int64_t k, int64_t* out_rows, int64_t* out_cols, void* out_vals,
+                            cmm_dtype out_dtype, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
 /* The d single-repetition estimates at a list of entries, before the median
  * or mean of Decompress (Algorithm 1):
  *   out[t][q] = s1_t(rows[q]) s2_t(cols[q]) p[t][h1_t(rows[q]) xor h2_t(cols[q])]
@@ -368,7 +391,7 @@ cmm_status cmm_estimate_backward(const cmm_problem* prob, const void* W, int64_t
  * launches of one kernel ("hash", "transpose", "plan", "compress",
  * "reduce", "fwht", "extract", "sketch", "accumulate", "wscatter",
  * "adjoint", "adjoint_reduce", "extract_entries", "extract_heavy",
- * "extract_reps", "correctness", "fft", "pairs") since the last
+ * "extract_reps", "extract_topk", "correctness", "fft", "pairs") since the last
  * cmm_profile_enable call.  Enabling or disabling discards the records.
  * query waits for the recorded events.  Off by default.
  *

@@ -288,6 +288,20 @@ def extract(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, estimator: str = 
     return out
 
 
+def extract_topk(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, k: int,
+                 estimator: str = "median"):
+    """The k entries of largest |C_hat| of Algorithm 1's Decompress over the
+    whole block (the large entries of the product, Section 1): the dense
+    estimate, then a plain sort by |C_hat| descending with ties broken by the
+    smaller row-major index.  Returns (rows, cols, vals)."""
+    C_hat = extract(p, tab1, tab2, estimator)
+    n_cols = C_hat.shape[1]
+    flat = C_hat.ravel()
+    idx = np.arange(flat.size)
+    order = np.lexsort((idx, -np.abs(flat)))[:k]
+    return order // n_cols, order % n_cols, flat[order]
+
+
 def extract_entries(p: np.ndarray, tab1: np.ndarray, tab2: np.ndarray, rows, cols,
                     estimator: str = "median") -> np.ndarray:
     """Algorithm 1, Decompress, at a list of entries (rows[q], cols[q]): the

@@ -31,7 +31,8 @@ HASH_FAMILIES = {"multiply_add_shift": CMM_HASH_MULTIPLY_ADD_SHIFT,
                  "multiply_shift": CMM_HASH_MULTIPLY_SHIFT, "tabulation": CMM_HASH_TABULATION}
 
 EXPORTED = ["cmm_hash", "cmm_hash_family", "cmm_sketch", "cmm_fwht", "cmm_accumulate", "cmm_extract",
-            "cmm_extract_entries", "cmm_extract_heavy", "cmm_extract_reps",
+            "cmm_extract_entries", "cmm_extract_heavy", "cmm_topk_workspace_size",
+            "cmm_extract_topk", "cmm_extract_reps",
             "cmm_correctness_counts", "cmm_fft", "cmm_extract_cyclic", "cmm_fft_workspace_size",
             "cmm_estimate_fft",
             "cmm_workspace_size", "cmm_estimate", "cmm_estimate_static",
@@ -92,6 +93,9 @@ def lib() -> ctypes.CDLL:
         "cmm_extract_heavy": [vp, vp, vp, i32, i64, i64, i32, i32, dbl, vp, vp, vp, i32, i64, vp,
                               vp],
         "cmm_extract_reps": [vp, vp, vp, i32, i64, i64, i32, vp, vp, i64, vp, i32, vp],
+        "cmm_topk_workspace_size": [i64, ctypes.POINTER(ctypes.c_size_t)],
+        "cmm_extract_topk": [vp, vp, vp, i32, i64, i64, i32, i32, i64, vp, vp, vp, i32, vp,
+                             ctypes.c_size_t, vp],
         "cmm_fft": [vp, vp, i64, i32, i32, dbl, vp],
         "cmm_extract_cyclic": [vp, vp, vp, i32, i64, i64, i32, i32, vp, i32, i64, vp],
         "cmm_fft_workspace_size": [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)],
@@ -290,6 +294,48 @@ def cmm_extract_entries(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, rows
     _check("cmm_extract_entries", lib().cmm_extract_entries(
         _ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b, estimator, _ptr(rows),
         _ptr(cols), rows.numel(), _ptr(out), _dtype_code(out), _stream(stream)))
+
+
+def cmm_topk_workspace_size(k: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check("cmm_topk_workspace_size", lib().cmm_topk_workspace_size(k, ctypes.byref(n)))
+    return n.value
+
+
+def cmm_extract_topk(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, k, rows, cols, vals,
+                     workspace=None, stream=None) -> None:
+    """The k entries of largest |C_hat| (sorted by magnitude, ties by the
+    smaller row-major index) into rows, cols (int64 [k]) and vals (float64 or
+    float32 [k]); workspace: uint8 device tensor of cmm_topk_workspace_size(k)
+    bytes (allocated here when None)."""
+    fn = "cmm_extract_topk"
+    torch = _torch()
+    _sketch_p(fn, p, d, log2b)
+    _tables(fn, tab1, tab2, d, n_rows, n_cols)
+    _like(rows, fn, "rows", (torch.int64,), min_numel=k)
+    _like(cols, fn, "cols", (torch.int64,), min_numel=k)
+    _like(vals, fn, "vals", _floats(), min_numel=k)
+    nbytes = cmm_topk_workspace_size(k)
+    if workspace is None:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=p.device)
+    _like(workspace, fn, "workspace", (torch.uint8,), min_numel=nbytes)
+    _check(fn, lib().cmm_extract_topk(_ptr(p), _ptr(tab1), _ptr(tab2), d, n_rows, n_cols, log2b,
+                                      estimator, k, _ptr(rows), _ptr(cols), _ptr(vals),
+                                      _dtype_code(vals), _ptr(workspace), workspace.numel(),
+                                      _stream(stream)))
+
+
+def topk(res, n_rows: int, n_cols: int, k: int, estimator: str = "median", dtype=None):
+    """Top-k entries of an ``Estimate`` (its p and tables): (rows, cols, vals)."""
+    torch = _torch()
+    d, b = res.p.shape
+    log2b = int(b).bit_length() - 1
+    rows = torch.empty(k, dtype=torch.int64, device=res.p.device)
+    cols = torch.empty(k, dtype=torch.int64, device=res.p.device)
+    vals = torch.empty(k, dtype=dtype or torch.float64, device=res.p.device)
+    est = CMM_MEDIAN if estimator == "median" else CMM_MEAN
+    cmm_extract_topk(res.p, res.tab1, res.tab2, d, n_rows, n_cols, log2b, est, k, rows, cols, vals)
+    return rows, cols, vals
 
 
 def cmm_extract_reps(p, tab1, tab2, d, n_rows, n_cols, log2b, rows, cols, out,

@@ -19,7 +19,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.hip", "k_basic.hip", "k_sketch.hip", "k_fwht.hip", "k_extract.hip",
            "k_compress.hip", "k_mfma.hip", "k_adjoint.hip", "batch.hip", "k_fft.hip",
-           "k_fft_compress.hip", "k_probe.hip"]
+           "k_fft_compress.hip", "k_probe.hip", "k_topk.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

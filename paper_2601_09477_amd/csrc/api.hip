@@ -41,7 +41,7 @@ const char* const kProfNames[] = {
     "hash",        "transpose",       "plan",          "compress",    "reduce",
     "fwht",        "extract",         "sketch",        "accumulate",  "wscatter",
     "adjoint",     "adjoint_reduce",  "extract_entries", "extract_heavy",
-    "extract_reps", "correctness",    "fft",           "pairs"};
+    "extract_reps", "extract_topk", "correctness", "fft",        "pairs"};
 
 void prof_clear_locked() {
   for (auto& kv : g_prof)
@@ -125,6 +125,8 @@ constexpr int kMaxFftLog2 = 24;       // two LDS-tile passes of at most 2^12 poi
 // Every buffer the kernels address holds fewer than 2^31 elements: their
 // index arithmetic is not audited beyond that.
 constexpr int64_t kMaxElems = (int64_t)1 << 31;
+// top-K: k plus the last bin's candidates are counted in 32-bit integers
+constexpr int64_t kMaxTopK = ((int64_t)1 << 31) - ((int64_t)1 << 15);
 
 // a * b (* c) < 2^31 for non-negative factors (exact: 128-bit product)
 bool fits_elems(int64_t a, int64_t b, int64_t c = 1) {
@@ -845,6 +847,39 @@ cmm_status cmm_extract_heavy(const double* p, const uint32_t* tab1, const uint32
   return launch_extract_heavy(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, threshold,
                               out_rows, out_cols, out_vals, out_dtype, capacity, count,
                               as_stream(stream));
+}
+
+cmm_status cmm_topk_workspace_size(int64_t k, size_t* bytes) {
+  if (!bytes) return invalid("cmm_topk_workspace_size: bytes is null");
+  if (k < 0) return invalid("cmm_topk_workspace_size: negative k");
+  if (k > kMaxTopK) {
+    set_error("cmm_topk_workspace_size: k above 2^31 - 2^15 is not supported");
+    return CMM_EUNSUPPORTED;
+  }
+  return topk_workspace_bytes(k, bytes);
+}
+
+cmm_status cmm_extract_topk(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                            int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator estimator,
+                            int64_t k, int64_t* out_rows, int64_t* out_cols, void* out_vals,
+                            cmm_dtype out_dtype, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+  const char* fn = "cmm_extract_topk";
+  cmm_status s = check_decompress(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, out_dtype, fn);
+  if (s != CMM_OK) return s;
+  if (k < 0) return invalid("cmm_extract_topk: negative k");
+  if (k == 0) return CMM_OK;
+  if (!fits_elems(n_rows, n_cols)) return too_large(fn, "the scanned block (n_rows x n_cols)");
+  if (k > n_rows * n_cols) return invalid("cmm_extract_topk: k exceeds n_rows * n_cols");
+  if (k > kMaxTopK) {
+    set_error("cmm_extract_topk: k above 2^31 - 2^15 is not supported");
+    return CMM_EUNSUPPORTED;
+  }
+  if (!out_rows || !out_cols || !out_vals) return invalid("cmm_extract_topk: null output");
+  if (!workspace) return invalid("cmm_extract_topk: workspace is null");
+  return launch_extract_topk(p, tab1, tab2, d, n_rows, n_cols, log2b, estimator, k, out_rows,
+                             out_cols, out_vals, out_dtype, workspace, workspace_bytes,
+                             as_stream(stream));
 }
 
 cmm_status cmm_extract_reps(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,

@@ -99,6 +99,12 @@ cmm_status launch_extract_heavy(const double* p, const uint32_t* tab1, const uin
                                 double threshold, int64_t* rows, int64_t* cols, void* vals,
                                 cmm_dtype out_dt, int64_t capacity, int64_t* count,
                                 hipStream_t s);
+// Top-K Decompress (k_topk): workspace bytes for k, and the launch sequence.
+cmm_status topk_workspace_bytes(int64_t k, size_t* bytes);
+cmm_status launch_extract_topk(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
+                               int64_t n_rows, int64_t n_cols, int log2b, cmm_estimator est,
+                               int64_t k, int64_t* rows, int64_t* cols, void* vals,
+                               cmm_dtype out_dt, void* workspace, size_t ws_bytes, hipStream_t s);
 cmm_status launch_extract_reps(const double* p, const uint32_t* tab1, const uint32_t* tab2, int d,
                                int64_t n_rows, int64_t n_cols, int log2b, const int64_t* rows,
                                const int64_t* cols, int64_t count, void* out, cmm_dtype out_dt,

@@ -322,6 +322,29 @@ def test_identity_hash_reduces_to_matmul():
     assert np.array_equal(O.extract(p, t1, t2, "mean"), brute)
 
 
+def test_topk_against_brute_force_on_exact_tables():
+    # Injective tables make Decompress return C = A B exactly (as above), so
+    # the top-k entries are those of C: brute force over every entry with
+    # Python integers, ordered by magnitude and then by the row-major index.
+    # Small integer entries give many ties, which the index order decides.
+    n = 8
+    rng = np.random.default_rng(17)
+    A = rng.integers(-3, 4, (n, n)).astype(float)
+    B = rng.integers(-3, 4, (n, n)).astype(float)
+    log2b = 6
+    t1 = _tables(np.arange(n) * n, rng.integers(0, 2, n), log2b).repeat(3, 0)
+    t2 = _tables(np.arange(n), rng.integers(0, 2, n), log2b).repeat(3, 0)
+    p = O.bucket_sums(O.product(A, B), t1, t2, log2b)
+    C = [[sum(int(A[i, q]) * int(B[q, j]) for q in range(n)) for j in range(n)] for i in range(n)]
+    ranked = sorted(((-abs(C[i][j]), i * n + j) for i in range(n) for j in range(n)))
+    for k in (1, 5, 17, n * n):
+        rows, cols, vals = O.extract_topk(p, t1, t2, k, "median")
+        want = ranked[:k]
+        assert [int(r) * n + int(c) for r, c in zip(rows, cols)] == [ix for _, ix in want]
+        assert [float(v) for v in vals] == [float(C[ix // n][ix % n]) for _, ix in want]
+    assert len({abs(C[i][j]) for i in range(n) for j in range(n)}) < n * n   # ties occur
+
+
 def test_bucket_sums_sparse_equals_dense_definition():
     # the nonzero-entry form of the bucket sums against the dense form on a
     # sparse product, and against brute force over the entries
