@@ -168,6 +168,9 @@ struct EstimatePlan {
   cmm_dtype cdt = CMM_F64;
   size_t off_at = 0, off_bc = 0, off_planA = 0, off_planB = 0, off_part = 0, off_p = 0;
   size_t off_x = 0, off_y = 0;
+  // fused forms with fold bits: tables rotated to the chosen transform window
+  bool window = false;
+  size_t off_rtab1 = 0, off_rtab2 = 0, off_rot = 0;
   // precision form: merged two-row chains (lists, counts, sums) per operand
   int pair_cap[2] = {0, 0};
   size_t off_plist[2] = {0, 0}, off_pcount[2] = {0, 0}, off_pvals[2] = {0, 0};
@@ -233,6 +236,17 @@ cmm_status validate_problem(const cmm_problem* pr, const char* fn) {
 
 namespace {
 
+// Rotated tables and window choices for the fused forms when b > b_lo.
+size_t add_window(EstimatePlan& P, const cmm_problem* pr, size_t off) {
+  P.window = pr->log2b > P.lb;
+  if (!P.window) return off;
+  const int d = pr->d;
+  P.off_rtab1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)d * pr->n_rows, 256);
+  P.off_rtab2 = off; off = align_up(off + sizeof(uint32_t) * (size_t)d * pr->n_cols, 256);
+  P.off_rot = off; off = align_up(off + sizeof(int32_t) * (size_t)d, 256);
+  return off;
+}
+
 EstimatePlan make_plan(const cmm_problem* pr) {
   EstimatePlan P;
   P.cdt = pr->compute == CMM_F64 ? CMM_F64 : CMM_F32;
@@ -251,6 +265,7 @@ EstimatePlan make_plan(const cmm_problem* pr) {
     P.off_bc = off; off = align_up(off + 2 * (size_t)pr->n_inner * pr->n_cols, 256);
     P.off_planA = off; off = align_up(off + plan_bytes(d, pr->n_rows, 14), 256);
     P.off_planB = off; off = align_up(off + plan_bytes(d, pr->n_cols, 14), 256);
+    off = add_window(P, pr, off);
     P.off_part = off; off = align_up(off + sizeof(double) * (size_t)P.groups * d * b, 256);
     P.off_p = off; off = align_up(off + sizeof(double) * (size_t)d * b, 256);
     for (int op = 0; op < 2; ++op) {
@@ -294,6 +309,7 @@ EstimatePlan make_plan(const cmm_problem* pr) {
     }
     P.off_planA = off; off = align_up(off + plan_bytes(d, pr->n_rows, lb), 256);
     P.off_planB = off; off = align_up(off + plan_bytes(d, pr->n_cols, lb), 256);
+    off = add_window(P, pr, off);
     P.off_part = off; off = align_up(off + sizeof(double) * (size_t)P.groups * d * b, 256);
   } else {
     // composed path: standalone sketch / transform / accumulate over k-chunks
@@ -313,6 +329,23 @@ EstimatePlan make_plan(const cmm_problem* pr) {
   P.off_p = off; off = align_up(off + sizeof(double) * (size_t)d * b, 256);
   P.bytes = off;
   return P;
+}
+
+// Choose each repetition's transform window and point the compress at the
+// rotated tables (natural tables and no rotation when b = b_lo); the reduce
+// of the partials restores the natural order.
+cmm_status apply_window(const EstimatePlan& P, const cmm_problem* pr, char* ws, CompressArgs& a,
+                        hipStream_t s) {
+  if (!P.window) return CMM_OK;
+  uint32_t* r1 = reinterpret_cast<uint32_t*>(ws + P.off_rtab1);
+  uint32_t* r2 = reinterpret_cast<uint32_t*>(ws + P.off_rtab2);
+  int32_t* rot = reinterpret_cast<int32_t*>(ws + P.off_rot);
+  cmm_status st = launch_window(pr->tab1, pr->tab2, pr->d, pr->n_rows, pr->n_cols, pr->log2b,
+                                P.lb, r1, r2, rot, s);
+  if (st != CMM_OK) return st;
+  a.tab1 = r1;
+  a.tab2 = r2;
+  return CMM_OK;
 }
 
 cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
@@ -354,8 +387,9 @@ cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
     a.ex_cap = 0;
     a.dma = 0;
     a.variant = 0;
-    if ((st = launch_plan(pr->tab1, d, pr->n_rows, P.lb, a.planA, s)) != CMM_OK) return st;
-    if ((st = launch_plan(pr->tab2, d, pr->n_cols, P.lb, a.planB, s)) != CMM_OK) return st;
+    if ((st = apply_window(P, pr, ws, a, s)) != CMM_OK) return st;
+    if ((st = launch_plan(a.tab1, d, pr->n_rows, P.lb, a.planA, s)) != CMM_OK) return st;
+    if ((st = launch_plan(a.tab2, d, pr->n_cols, P.lb, a.planB, s)) != CMM_OK) return st;
     // the two-row chains merged ahead of the kernel, from the low-precision rows
     for (int op = 0; op < 2; ++op) {
       if (P.pair_cap[op] == 0) continue;
@@ -371,7 +405,10 @@ cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
       else { a.pair_listA = list; a.pair_countA = count; a.pair_valsA = vals; a.pair_capA = P.pair_cap[0]; }
     }
     if ((st = launch_compress_mfma(a, pr->compute, s)) != CMM_OK) return st;
-    if ((st = launch_reduce_partials(a.partial, P.groups, (size_t)d * b, p, s)) != CMM_OK) return st;
+    st = launch_reduce_window(a.partial, P.groups, d, pr->log2b,
+                              P.window ? reinterpret_cast<const int32_t*>(ws + P.off_rot) : nullptr,
+                              p, s);
+    if (st != CMM_OK) return st;
   } else if (P.fused) {
     void* At = ws + P.off_at;
     st = launch_transpose(pr->A, pr->in_dtype, pr->n_rows, pr->n_inner, pr->lda, At, P.cdt, s);
@@ -403,10 +440,14 @@ cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
     a.ex_cap = 0;
     a.dma = 0;
     a.variant = 0;
-    if ((st = launch_plan(pr->tab1, d, pr->n_rows, P.lb, a.planA, s)) != CMM_OK) return st;
-    if ((st = launch_plan(pr->tab2, d, pr->n_cols, P.lb, a.planB, s)) != CMM_OK) return st;
+    if ((st = apply_window(P, pr, ws, a, s)) != CMM_OK) return st;
+    if ((st = launch_plan(a.tab1, d, pr->n_rows, P.lb, a.planA, s)) != CMM_OK) return st;
+    if ((st = launch_plan(a.tab2, d, pr->n_cols, P.lb, a.planB, s)) != CMM_OK) return st;
     if ((st = launch_compress(a, P.cdt, P.lb, s)) != CMM_OK) return st;
-    if ((st = launch_reduce_partials(a.partial, P.groups, (size_t)d * b, p, s)) != CMM_OK) return st;
+    st = launch_reduce_window(a.partial, P.groups, d, pr->log2b,
+                              P.window ? reinterpret_cast<const int32_t*>(ws + P.off_rot) : nullptr,
+                              p, s);
+    if (st != CMM_OK) return st;
   } else {
     const void* A = pr->A;
     const void* B = pr->B;

@@ -163,6 +163,22 @@ struct CompressArgs {
   int pair_capA = 0, pair_capB = 0;
 };
 
+// Transform window per repetition for the fused Compress with b_lo = 2^lb:
+// the window s (0 <= s <= min(log2b - lb, kMaxWindow)) whose bits s .. s +
+// lb - 1 of the bucket index leave the fewest collisions in both tables,
+// and the tables with their bucket bits rotated right by s (rtab1
+// [d][n_rows], rtab2 [d][n_cols], rot [d]).  A compress on the rotated
+// tables yields p_hat in the rotated frame; launch_reduce_window sums its
+// partials and restores the natural order.
+constexpr int kMaxWindow = 5;
+cmm_status launch_window(const uint32_t* tab1, const uint32_t* tab2, int d, int64_t n_rows,
+                         int64_t n_cols, int log2b, int lb, uint32_t* rtab1, uint32_t* rtab2,
+                         int32_t* rot, hipStream_t s);
+// out[t][u] = sum over q < g, in order, of parts[q][t][rotr(u, rot[t])]
+// (rotation of the log2b bucket bits; rot = nullptr: none).
+cmm_status launch_reduce_window(const double* parts, int g, int d, int log2b, const int32_t* rot,
+                                double* out, hipStream_t s);
+
 size_t plan_bytes(int d, int64_t n, int lb);
 size_t plan_lds_bytes(int64_t n, int lb);
 // The plan's arrays at p (plan_bytes(d, n, lb) bytes), in this order.

@@ -163,7 +163,138 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const uint32_t* __re
   }
 }
 
+// ----------------------------------------------------------------- window
+// The transform is the same for any order of the bucket bits (the
+// Walsh-Hadamard matrix of 2^m points is the Kronecker product of m 2-point
+// ones), so a work unit may transform any lb of the m bits and fold the
+// others.  Multiply-add-shift hashes of consecutive indices can crowd a
+// window of bits onto few values (long collision chains, whose fix-ups
+// dominate the unit's time), while another window spreads them.  One
+// work-group per repetition counts, for every window s, the rows beyond the
+// first in each bucket of the window and (weighted 8) the rows beyond the
+// sixth, over both tables; the cheapest window (the lowest s on ties) is
+// applied by rotating the bucket bits right by s.  Windows are tried up to
+// s = kMaxWindow (the tile of the reduce that restores the order).
+__global__ __launch_bounds__(kPlanThreads) void window_kernel(
+    const uint32_t* __restrict__ tab1, const uint32_t* __restrict__ tab2, int64_t n1, int64_t n2,
+    int log2b, int lb, uint32_t* __restrict__ rtab1, uint32_t* __restrict__ rtab2,
+    int32_t* __restrict__ rot) {
+  const int t = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int blo = 1 << lb;
+  const uint32_t lomask = (uint32_t)blo - 1u;
+  const uint32_t mmask = (uint32_t)(((uint64_t)1 << log2b) - 1u);
+  extern __shared__ int32_t cnt[];   // [b_lo]
+  __shared__ int32_t s_part[kPlanThreads / 64];
+  __shared__ int32_t s_best;
+  const int smax = log2b - lb < kMaxWindow ? log2b - lb : kMaxWindow;
+  int32_t best_cost = 0x7FFFFFFF, best_s = 0;
+  for (int sh = 0; sh <= smax; ++sh) {
+    int32_t cost = 0;
+    for (int op = 0; op < 2; ++op) {
+      const uint32_t* tb = (op ? tab2 : tab1) + (size_t)t * (op ? n2 : n1);
+      const int64_t n = op ? n2 : n1;
+      for (int r = tid; r < blo; r += kPlanThreads) cnt[r] = 0;
+      __syncthreads();
+      for (int64_t i = tid; i < n; i += kPlanThreads)
+        atomicAdd(&cnt[((tb[i] & mmask) >> sh) & lomask], 1);
+      __syncthreads();
+      int32_t mine = 0;
+      for (int r = tid; r < blo; r += kPlanThreads) {
+        const int32_t c = cnt[r];
+        mine += (c > 1 ? c - 1 : 0) + 8 * (c > 6 ? c - 6 : 0);
+      }
+      for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+      if ((tid & 63) == 0) s_part[tid >> 6] = mine;
+      __syncthreads();
+      for (int q = 0; q < kPlanThreads / 64; ++q) cost += s_part[q];
+      __syncthreads();   // s_part and cnt are reused
+    }
+    if (cost < best_cost) { best_cost = cost; best_s = sh; }   // uniform
+  }
+  if (tid == 0) { s_best = best_s; rot[t] = best_s; }
+  __syncthreads();
+  const int sh = s_best;
+  for (int op = 0; op < 2; ++op) {
+    const int64_t n = op ? n2 : n1;
+    const uint32_t* tb = (op ? tab2 : tab1) + (size_t)t * n;
+    uint32_t* ro = (op ? rtab2 : rtab1) + (size_t)t * n;
+    for (int64_t i = tid; i < n; i += kPlanThreads) {
+      const uint32_t e = tb[i];
+      const uint32_t h = e & mmask;
+      const uint32_t hr = sh == 0 ? h : ((h >> sh) | (h << (log2b - sh))) & mmask;
+      ro[i] = hr | (e & kSignBit);
+    }
+  }
+}
+
+// Sum of the partials of a rotated frame back into natural order.  Natural
+// index u = a 2^s + c (c < 2^s) sits at rotated position c 2^(m - s) + a, so
+// a tile of 2048 consecutive natural indices is, for each of the 2^s values
+// of c, a run of 2048 / 2^s consecutive rotated positions: read per c
+// (coalesced, partials summed in group order), transposed through LDS,
+// written in natural order.
+constexpr int kRedTile = 2048;
+__global__ __launch_bounds__(256) void reduce_window_kernel(const double* __restrict__ parts,
+                                                            int g, int d, int log2b,
+                                                            const int32_t* __restrict__ rot,
+                                                            double* __restrict__ out) {
+  __shared__ double tile[kRedTile + (1 << kMaxWindow)];
+  const int t = blockIdx.y;
+  const int s = rot[t];
+  const int64_t b = (int64_t)1 << log2b;
+  const int64_t u0 = (int64_t)blockIdx.x * kRedTile;   // natural tile start
+  const int C = 1 << s, A = kRedTile >> s;              // values of c; run length per c
+  const int64_t a0 = u0 >> s;
+  const size_t len = (size_t)d * b;
+  for (int i = threadIdx.x; i < kRedTile; i += 256) {
+    const int c = i / A, j = i - c * A;
+    const int64_t up = ((int64_t)c << (log2b - s)) + a0 + j;   // rotated position
+    const double* src = parts + (size_t)t * b + up;
+    double acc = 0.0;
+    for (int q = 0; q < g; ++q) acc += src[(size_t)q * len];
+    tile[c * (A + 1) + j] = acc;   // padded rows: the transposed reads spread over banks
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kRedTile; i += 256) {
+    const int c = i & (C - 1), j = i >> s;
+    out[(size_t)t * b + u0 + i] = tile[c * (A + 1) + j];
+  }
+}
+
 }  // namespace
+
+cmm_status launch_reduce_window(const double* parts, int g, int d, int log2b, const int32_t* rot,
+                                double* out, hipStream_t s) {
+  const int64_t b = (int64_t)1 << log2b;
+  if (!rot) return launch_reduce_partials(parts, g, (size_t)d * b, out, s);
+  ProfScope prof_("reduce", s);
+  if (b < kRedTile) {
+    set_error("reduce (window): needs b >= 2048");
+    return CMM_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(reduce_window_kernel, dim3((unsigned)(b / kRedTile), d), dim3(256), 0, s,
+                     parts, g, d, log2b, rot, out);
+  return hip_check(hipGetLastError(), "reduce (window) kernel launch");
+}
+
+cmm_status launch_window(const uint32_t* tab1, const uint32_t* tab2, int d, int64_t n_rows,
+                         int64_t n_cols, int log2b, int lb, uint32_t* rtab1, uint32_t* rtab2,
+                         int32_t* rot, hipStream_t s) {
+  ProfScope prof_("plan", s);
+  if (lb > log2b || lb > 14 || log2b > 31) {
+    set_error("window: needs lb <= log2b, lb <= 14, log2b <= 31");
+    return CMM_EUNSUPPORTED;
+  }
+  const size_t lds = sizeof(int32_t) * ((size_t)1 << lb);
+  hipError_t e = hipFuncSetAttribute((const void*)window_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return hip_check(e, "window: set LDS size");
+  hipLaunchKernelGGL(window_kernel, dim3(d), dim3(kPlanThreads), lds, s, tab1, tab2, n_rows,
+                     n_cols, log2b, lb, rtab1, rtab2, rot);
+  return hip_check(hipGetLastError(), "window kernel launch");
+}
+
 }  // namespace cmm
 
 #include "wht_regs.h"
@@ -384,23 +515,43 @@ __host__ __device__ constexpr int64_t pitch16(int64_t n) {
   return row_pitch<T>(DESC ? n + 64 : n);
 }
 
-template <typename T, bool SINGLE, bool DESC>
+// padded transpose buffer of the 16-element layout (pad16 of 2^13 - 1 < it)
+constexpr int64_t kXlen16 = (1 << 13) + (1 << 13) / 64 + 16;
+
+// Elements of one row area of the aliased layout: a staged row with its
+// spare elements, or one operand's padded transpose.
+template <typename T>
+__host__ __device__ constexpr int64_t alias_area16(int64_t n) {
+  return pitch16<T, true>(n) > kXlen16 ? pitch16<T, true>(n) : kXlen16;
+}
+
+// ALIAS: no separate transpose buffer; once a step's rows are gathered into
+// registers, each operand's transpose goes through its own row area, and the
+// rows of the next step are staged after the transposed reads.  This keeps
+// both rows and the descriptors in LDS for rows too long to sit beside a
+// transpose buffer.
+template <typename T, bool SINGLE, bool DESC, bool ALIAS = false>
 __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, int t, uint32_t uhi,
                                                 int64_t k0, int64_t k1, unsigned char* smem) {
   static_assert(!(SINGLE && DESC), "descriptors need both rows staged");
+  static_assert(!ALIAS || DESC, "the aliased layout is a descriptor layout");
   constexpr int LB = 13;
   constexpr int E = 16;
   constexpr int NT = 512;
   constexpr int BLO = 1 << LB;
-  constexpr int XLEN = BLO + BLO / 64 + 16;   // padded transpose buffer
+  constexpr int XLEN = kXlen16;   // padded transpose buffer
   T* xbuf = reinterpret_cast<T*>(smem);
-  T* rowA = xbuf + XLEN;
-  const int64_t pitch1 = SINGLE ? (row_pitch<T>(a.n_rows) > row_pitch<T>(a.n_cols)
+  T* rowA = ALIAS ? xbuf : xbuf + XLEN;
+  const int64_t pitch1 = ALIAS ? alias_area16<T>(a.n_rows)
+                       : SINGLE ? (row_pitch<T>(a.n_rows) > row_pitch<T>(a.n_cols)
                                        ? row_pitch<T>(a.n_rows) : row_pitch<T>(a.n_cols))
                                 : pitch16<T, DESC>(a.n_rows);
   T* rowB = SINGLE ? rowA : rowA + pitch1;
-  uint2* exl = reinterpret_cast<uint2*>(rowB + (SINGLE ? 0 : pitch16<T, DESC>(a.n_cols)) +
-                                        (SINGLE ? pitch1 : 0));
+  const int64_t pitch2 = ALIAS ? alias_area16<T>(a.n_cols) : pitch16<T, DESC>(a.n_cols);
+  uint2* exl = reinterpret_cast<uint2*>(rowB + (SINGLE ? 0 : pitch2) + (SINGLE ? pitch1 : 0));
+  // transpose areas of X and Y
+  T* xa = ALIAS ? rowA : xbuf;
+  T* xb = ALIAS ? rowB : xbuf;
   if (!SINGLE && threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
 
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -468,7 +619,8 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   // chain skip a slot (both tests are wave-uniform); otherwise position c
   // holds chain c.  A chain with more than six rows keeps its index in
   // word 2, adds only its first four rows here and is finished in the rare
-  // pass.
+  // pass; its word 2 then holds where its plan entries start and how many
+  // there are (beg | count << 15, both below n).
   // A third, partial slot (positions kSlots16 NT + i, i < ovf, held by
   // threads i < ovf) uses the LDS the launcher found left over.
   uint32_t* dsc = reinterpret_cast<uint32_t*>(exl);   // [word][operand][slot][NT]
@@ -543,7 +695,8 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
         const uint32_t more = end - beg > 5 ? 1u : 0u;
         dslot(0, op, pos) = m[0] | (m[1] << 15) | (sg[1] << 30) | (more << 31);
         dslot(1, op, pos) = m[2] | (m[3] << 15) | (sg[2] << 30) | (sg[3] << 31);
-        dslot(2, op, pos) = more ? (uint32_t)c : m[4] | (m[5] << 15) | (sg[4] << 30) | (sg[5] << 31);
+        dslot(2, op, pos) = more ? (uint32_t)beg | ((uint32_t)(end - beg) << 15)
+                                 : m[4] | (m[5] << 15) | (sg[4] << 30) | (sg[5] << 31);
       }
     }
   }
@@ -586,7 +739,8 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
           const bool hs = has_slot(jj);
           const uint32_t w1 = hs ? dref(1, op, jj) : padw, w2 = hs ? dref(2, op, jj) : padw;
           const T v2 = row[w1 & 0x7FFFu], v3 = row[(w1 >> 15) & 0x7FFFu];
-          // word 2 of a chain with more rows is its index (< n: in the row)
+          // word 2 of a chain with more rows is beg | count << 15 (both < n:
+          // the reads stay in the row)
           const bool mr = (w0 >> 31) != 0u;
           const T v4 = row[w2 & 0x7FFFu], v5 = row[(w2 >> 15) & 0x7FFFu];
           acc_ = acc_ + flip_sign(v2, ((w1 >> 30) & 1u) << 31);
@@ -616,28 +770,40 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
           if (!has_slot(jj)) continue;
           const uint32_t w0 = dref(0, op, jj);
           if (!(w0 >> 31)) continue;
-          T acc_ = row[w0 & 0x7FFFu];
-          const int c = (int)dref(2, op, jj);
-          const int beg = gc[c], end = gc[c + 1];
-          for (int r = beg + 3; r < end; ++r) {
-            const uint2 y = gp[r];
-            const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
-            acc_ = acc_ + flip_sign(row[y.x & 0xFFFFu], neg << 31);
-          }
-          row[w0 & 0x7FFFu] = acc_;
+          // rows four onwards, eight plan entries per round trip
+          const uint32_t w2 = dref(2, op, jj);
+          const int beg = (int)(w2 & 0x7FFFu), end = beg + (int)((w2 >> 15) & 0x7FFFu);
+          row[w0 & 0x7FFFu] = chain_sum<T, T, 8>(row, gp, beg + 3, end, uhi, row[w0 & 0x7FFFu]);
         }
-        // chains beyond the slots (identity order: disjoint targets)
+        // chains beyond the slots (identity order: disjoint targets), four
+        // per thread at a time: their starts, first entries and first two
+        // rows are each fetched as independent loads
         const int nch = op ? nchB : nchA;
-        for (int c = npos + (int)threadIdx.x; c < nch; c += NT) {
-          const int beg = gc[c], end = gc[c + 1];
-          const uint32_t tgt = gp[beg].x >> 16;
-          T acc_ = row[tgt];
-          for (int r = beg; r < end; ++r) {
-            const uint2 y = gp[r];
-            const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
-            acc_ = acc_ + flip_sign(row[y.x & 0xFFFFu], neg << 31);
+        for (int c0 = npos + (int)threadIdx.x; c0 < nch; c0 += 4 * NT) {
+          int beg[4], end[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int c = c0 + j * NT;
+            beg[j] = c < nch ? gc[c] : 0;
+            end[j] = c < nch ? gc[c + 1] : 0;
           }
-          row[tgt] = acc_;
+          uint2 y[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) y[j] = beg[j] < end[j] ? gp[beg[j]] : make_uint2(0u, 0u);
+          T v0[4], v1[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            v0[j] = beg[j] < end[j] ? row[y[j].x >> 16] : T(0);
+            v1[j] = beg[j] < end[j] ? row[y[j].x & 0xFFFFu] : T(0);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (beg[j] >= end[j]) continue;
+            const uint32_t neg = (y[j].y >> 31) ^ (__popc(uhi & (y[j].y & kBucketMask)) & 1u);
+            T acc_ = v0[j] + flip_sign(v1[j], neg << 31);
+            if (end[j] - beg[j] > 1) acc_ = chain_sum<T, T, 4>(row, gp, beg[j] + 1, end[j], uhi, acc_);
+            row[y[j].x >> 16] = acc_;
+          }
         }
       }
     }
@@ -705,7 +871,39 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
     gather();
     if (SINGLE) single_b(k0);
   }
-  for (int64_t k = k0; k < k1; ++k) {
+  for (int64_t k = k0; k < k1 && ALIAS; ++k) {
+    const bool more = k + 1 < k1;
+    pass1_16(X);
+    __syncthreads();   // every thread's gathers of k are done: the row areas are free
+#pragma unroll
+    for (int e = 0; e < E; ++e) xa[wr_t + wr_e(e)] = X[e];
+    pass1_16(Y);
+#pragma unroll
+    for (int e = 0; e < E; ++e) xb[wr_t + wr_e(e)] = Y[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) X[e] = xa[rd_t + rd_e(e)];
+#pragma unroll
+    for (int e = 0; e < E; ++e) Y[e] = xb[rd_t + rd_e(e)];
+    __syncthreads();   // the transposed reads are done: the areas take the rows of k + 1
+    if (more) {
+      // the transposes overwrote the zero pads
+      if (threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
+      load_k(k + 1);
+    }
+    pass2_16(X, sgn8);
+    pass2_16(Y, sgn8);
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = fma(X[e], Y[e], acc[e]);
+    if (more) {
+      if (dma) wait_dma();
+      __syncthreads();   // rows of k + 1 and the pads are in place
+      fixups();
+      __syncthreads();
+      gather();
+    }
+  }
+  for (int64_t k = k0; k < k1 && !ALIAS; ++k) {
     const bool more = k + 1 < k1;
     pass1_16(X);
 #pragma unroll
@@ -761,7 +959,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
 template <typename T>
 constexpr int waves16() { return 2; }
 
-template <typename T, bool SINGLE, bool DESC>
+template <typename T, bool SINGLE, bool DESC, bool ALIAS>
 __global__ __launch_bounds__(512, waves16<T>()) void compress16_kernel(CompressArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int LB = 13;
@@ -778,7 +976,7 @@ __global__ __launch_bounds__(512, waves16<T>()) void compress16_kernel(CompressA
   const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
   const int64_t k0 = (int64_t)g * k_per;
   const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
-  compress16_unit<T, SINGLE, DESC>(a, g, t, uhi, k0, k1, smem);
+  compress16_unit<T, SINGLE, DESC, ALIAS>(a, g, t, uhi, k0, k1, smem);
 }
 
 // The persistent batched form with the 16-element layout (b_lo = 2^13).
@@ -899,10 +1097,15 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   const size_t desc_lds = sizeof(uint32_t) * 3 * 2 * kSlots16 * 512;
   const size_t base_desc = sizeof(T) * (xlen + (size_t)pitch16<T, true>(a.n_rows) +
                                         (size_t)pitch16<T, true>(a.n_cols));
-  const bool desc = base_desc + desc_lds <= kMax && a.n_rows + 64 < 32768 &&
-                    a.n_cols + 64 < 32768;
+  const bool idx15 = a.n_rows + 64 < 32768 && a.n_cols + 64 < 32768;
+  const bool desc = base_desc + desc_lds <= kMax && idx15;
+  // rows too long for a transpose buffer beside them: transposes through
+  // the row areas
+  const size_t base_alias = sizeof(T) * (size_t)(alias_area16<T>(a.n_rows) + alias_area16<T>(a.n_cols));
+  const bool alias = !desc && idx15 && base_alias + desc_lds <= kMax;
   size_t base = desc ? base_desc
-                     : sizeof(T) * (xlen + (size_t)row_pitch<T>(a.n_rows) + (size_t)row_pitch<T>(a.n_cols));
+              : alias ? base_alias
+                      : sizeof(T) * (xlen + (size_t)row_pitch<T>(a.n_rows) + (size_t)row_pitch<T>(a.n_cols));
   bool single = false;
   if (base > kMax) {
     const size_t p1 = (size_t)(row_pitch<T>(a.n_rows) > row_pitch<T>(a.n_cols)
@@ -914,14 +1117,14 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   // the descriptor slots, and a partial third slot in whatever LDS is left
   // (three words per position and operand)
   a.ovf16 = 0;
-  if (desc && !single) {
+  if ((desc || alias) && !single) {
     size_t left = kMax - base - desc_lds;
     size_t ovf = left / (sizeof(uint32_t) * 3 * 2);
     if (ovf > 512) ovf = 512;
     a.ovf16 = (int)ovf;
   }
   int64_t cap = (int64_t)((kMax - base) / sizeof(uint2));
-  const int64_t want = desc ? (int64_t)((desc_lds + sizeof(uint32_t) * 3 * 2 * (size_t)a.ovf16) /
+  const int64_t want = (desc || alias) ? (int64_t)((desc_lds + sizeof(uint32_t) * 3 * 2 * (size_t)a.ovf16) /
                                         sizeof(uint2))
                             : a.n_rows + a.n_cols;
   if (cap > want) cap = want;
@@ -930,8 +1133,10 @@ static cmm_status launch_compress16(const CompressArgs& a0, hipStream_t s) {
   constexpr int V = 16 / sizeof(T);
   a.dma = (a.n_rows % V == 0) && (a.n_cols % V == 0) && (a.ldb % V == 0) &&
           ((uintptr_t)a.At % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
-  auto kern = single ? compress16_kernel<T, true, false>
-                     : (desc ? compress16_kernel<T, false, true> : compress16_kernel<T, false, false>);
+  auto kern = single ? compress16_kernel<T, true, false, false>
+             : alias  ? compress16_kernel<T, false, true, true>
+             : desc   ? compress16_kernel<T, false, true, false>
+                      : compress16_kernel<T, false, false, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return hip_check(e, "compress: set LDS size");

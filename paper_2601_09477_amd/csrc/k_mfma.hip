@@ -26,6 +26,7 @@
 // The sketch (fold, gather, collision chains) is the one of the float64
 // kernel, on rows staged in the low precision.
 #include "cmm_internal.h"
+#include "wht_regs.h"
 
 namespace cmm {
 namespace {
@@ -285,8 +286,9 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   // pad):
   //   w0 = target | m1 << 15 | s1 << 30 | more << 31
   //   w1 = m2 | m3 << 15 | s2 << 30 | s3 << 31
-  //   w2 = m4 | m5 << 15 | s4 << 30 | s5 << 31, or the chain's index when
-  //        it has more rows (more = 1; the rare pass adds rows 4 onwards)
+  //   w2 = m4 | m5 << 15 | s4 << 30 | s5 << 31, or, when the chain has more
+  //        rows (more = 1; the rare pass adds rows 4 onwards), where its
+  //        plan entries start and how many there are: beg | count << 15
   // Slot position pos = tid + j kNT (j < kSlots) takes the chains in an
   // order with the chains of three or more rows first (stable), so that the
   // fix-up can read and add the rows past the first two only in the waves
@@ -368,7 +370,8 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
       const uint32_t more = end - beg > 5 ? 1u : 0u;
       dslot(0, op, pos) = m[0] | (m[1] << 15) | (sg[1] << 30) | (more << 31);
       dslot(1, op, pos) = m[2] | (m[3] << 15) | (sg[2] << 30) | (sg[3] << 31);
-      dslot(2, op, pos) = more ? (uint32_t)c : m[4] | (m[5] << 15) | (sg[4] << 30) | (sg[5] << 31);
+      dslot(2, op, pos) = more ? (uint32_t)beg | ((uint32_t)(end - beg) << 15)
+                               : m[4] | (m[5] << 15) | (sg[4] << 30) | (sg[5] << 31);
     }
   };
   if (DESC) {
@@ -450,8 +453,8 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
           const uint32_t w0 = q0[op][j];
           const uint32_t w1 = dref(1, op, j), w2 = dref(2, op, j);
           const float v2 = to_f(row[w1 & 0x7FFFu]), v3 = to_f(row[(w1 >> 15) & 0x7FFFu]);
-          // w2 of a slot with more rows is a chain index (< n, so the reads
-          // stay in the row): its values are not added here
+          // w2 of a slot with more rows is beg | count << 15 (both < n, so
+          // the reads stay in the row): its values are not added here
           const bool mr = (w0 >> 31) != 0u;
           float v4 = to_f(row[w2 & 0x7FFFu]), v5 = to_f(row[(w2 >> 15) & 0x7FFFu]);
           v4 = mr ? 0.f : v4;
@@ -489,32 +492,42 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
         for (int j = 0; j < kSlots; ++j) {
           if (!(q0[op][j] >> 31)) continue;
           // a bucket of seven or more rows: the target and rows 1..3 are
-          // summed; the chain index is in w2
+          // summed; rows four onwards, eight plan entries per round trip
           const uint32_t tgt = q0[op][j] & 0x7FFFu;
-          const int c = (int)dref(2, op, j);
-          float acc_ = sum[op][j];
-          const int beg = gc[c], end = gc[c + 1];
-          for (int r = beg + 3; r < end; ++r) {
-            const uint2 y = gp[r];
-            const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
-            const float w = to_f(row[y.x & 0xFFFFu]);
-            acc_ = acc_ + (neg ? -w : w);
-          }
-          row[tgt] = (IN)acc_;
+          const uint32_t w2 = dref(2, op, j);
+          const int beg = (int)(w2 & 0x7FFFu), end = beg + (int)((w2 >> 15) & 0x7FFFu);
+          row[tgt] = (IN)chain_sum<IN, float, 8>(row, gp, beg + 3, end, uhi, sum[op][j]);
         }
-        // chains beyond the slots (identity order; disjoint targets)
+        // chains beyond the slots (identity order; disjoint targets), four
+        // per thread at a time: their starts, first entries and first two
+        // rows are each fetched as independent loads
         const int nch = rl->nch[op];
-        for (int c = kSlots * kNT + (int)threadIdx.x; c < nch; c += kNT) {
-          const int beg = gc[c], end = gc[c + 1];
-          const uint32_t tgt = gp[beg].x >> 16;
-          float acc_ = to_f(row[tgt]);
-          for (int r = beg; r < end; ++r) {
-            const uint2 y = gp[r];
-            const uint32_t neg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
-            const float w = to_f(row[y.x & 0xFFFFu]);
-            acc_ = acc_ + (neg ? -w : w);
+        for (int c0 = kSlots * kNT + (int)threadIdx.x; c0 < nch; c0 += 4 * kNT) {
+          int beg[4], end[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c = c0 + q * kNT;
+            beg[q] = c < nch ? gc[c] : 0;
+            end[q] = c < nch ? gc[c + 1] : 0;
           }
-          row[tgt] = (IN)acc_;
+          uint2 y[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) y[q] = beg[q] < end[q] ? gp[beg[q]] : make_uint2(0u, 0u);
+          float v0[4], v1[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            v0[q] = beg[q] < end[q] ? to_f(row[y[q].x >> 16]) : 0.f;
+            v1[q] = beg[q] < end[q] ? to_f(row[y[q].x & 0xFFFFu]) : 0.f;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (beg[q] >= end[q]) continue;
+            const uint32_t neg = (y[q].y >> 31) ^ (__popc(uhi & (y[q].y & kBucketMask)) & 1u);
+            float acc_ = v0[q] + (neg ? -v1[q] : v1[q]);
+            if (end[q] - beg[q] > 1)
+              acc_ = chain_sum<IN, float, 4>(row, gp, beg[q] + 1, end[q], uhi, acc_);
+            row[y[q].x >> 16] = (IN)acc_;
+          }
         }
       }
     }

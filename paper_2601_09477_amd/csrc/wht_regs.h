@@ -200,20 +200,21 @@ __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" :
 // bucket's chain and adds its rows onto the bucket's first row in rank
 // (ascending index) order, row[first] += +-row[index], so every bucket
 // receives its rows left to right without atomics.  Entries are fetched
-// four at a time (independent loads) and two chains are in flight per
-// thread, so a chain costs a few LDS round trips instead of two per row.
-template <typename T>
-__device__ __forceinline__ T chain_sum(const T* __restrict__ row, const uint2* __restrict__ ex,
-                                       int beg, int end, uint32_t uhi, T accv) {
-  for (int q0 = beg; q0 < end; q0 += 4) {
-    uint2 x[4];
+// KB at a time (independent loads) and two chains are in flight per
+// thread, so a chain costs a few round trips instead of two per row.  The
+// sum is formed in A (the row's type, or float32 for low-precision rows).
+template <typename T, typename A = T, int KB = 4>
+__device__ __forceinline__ A chain_sum(const T* __restrict__ row, const uint2* __restrict__ ex,
+                                       int beg, int end, uint32_t uhi, A accv) {
+  for (int q0 = beg; q0 < end; q0 += KB) {
+    uint2 x[KB];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) x[j] = (q0 + j < end) ? ex[q0 + j] : make_uint2(0u, 0u);
-    T v[4];
+    for (int j = 0; j < KB; ++j) x[j] = (q0 + j < end) ? ex[q0 + j] : make_uint2(0u, 0u);
+    A v[KB];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = (q0 + j < end) ? row[x[j].x & 0xFFFFu] : T(0);
+    for (int j = 0; j < KB; ++j) v[j] = (q0 + j < end) ? (A)row[x[j].x & 0xFFFFu] : A(0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < KB; ++j) {
       if (q0 + j < end) {
         const uint32_t neg = (x[j].y >> 31) ^ (__popc(uhi & (x[j].y & kBucketMask)) & 1u);
         accv = accv + (neg ? -v[j] : v[j]);
