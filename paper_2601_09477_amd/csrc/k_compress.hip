@@ -509,6 +509,11 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_batched_kernel(
 // lists.  Separate instances, because the chain-walking code, even when not
 // executed, slows the loop it sits in.
 constexpr int kSlots16 = 2;   // descriptor slots per thread and operand (512 threads)
+// One-word descriptors of two-row chains: slots per thread and operand in
+// the same LDS (three words per full slot and operand, plus the partial
+// slot's kPairOvf16 positions or more).
+constexpr int kPairSlots16 = 7;
+constexpr int kPairOvf16 = (kPairSlots16 * 512 - 3 * kSlots16 * 512 + 2) / 3;
 
 template <typename T, bool DESC>
 __host__ __device__ constexpr int64_t pitch16(int64_t n) {
@@ -530,7 +535,11 @@ __host__ __device__ constexpr int64_t alias_area16(int64_t n) {
 // rows of the next step are staged after the transposed reads.  This keeps
 // both rows and the descriptors in LDS for rows too long to sit beside a
 // transpose buffer.
-template <typename T, bool SINGLE, bool DESC, bool ALIAS = false>
+// FIX (descriptor layouts): 1 the general descriptors below; 0 the
+// repetition has no collision chains in either operand (no descriptors, no
+// fix-ups: a unit without that code runs faster); 2 every chain of both
+// operands has two rows and they fit kPairSlots16 one-word descriptors.
+template <typename T, bool SINGLE, bool DESC, bool ALIAS = false, int FIX = 1>
 __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, int t, uint32_t uhi,
                                                 int64_t k0, int64_t k1, unsigned char* smem) {
   static_assert(!(SINGLE && DESC), "descriptors need both rows staged");
@@ -638,7 +647,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   // slot j of this thread exists (the partial slot only below novf)
   auto has_slot = [&](int j) -> bool { return j < kSlots16 || (int)threadIdx.x < novf; };
   int nlong[2] = {0, 0};
-  if constexpr (DESC) {
+  if constexpr (DESC && FIX == 1) {
     // the transpose buffer is idle until the k loop: scan scratch
     int32_t* s_scan = reinterpret_cast<int32_t*>(xbuf);
     __syncthreads();   // a previous work unit's last transposed reads are done
@@ -707,6 +716,56 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   // with more rows stores its partial sum (in the row's own type, so no
   // extra rounding) and the rare pass continues from its fifth row.
   const int wave_pos = (int)(threadIdx.x & ~63u);
+  // Two-row chains only (FIX = 2): one word per chain, w = target | m1 << 15
+  // | s1 << 30, in the descriptor LDS; chain c at slot c / NT of thread
+  // c mod NT.  A wave takes a slot when one of its positions holds a chain;
+  // an absent position adds the zero pad onto its lane's spare element.
+  uint32_t* pdsc = reinterpret_cast<uint32_t*>(exl);   // [operand][slot][NT]
+  if constexpr (DESC && FIX == 2) {
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      const int32_t* gc = op ? gcB : gcA;
+      const uint2* gp = op ? gB : gA;
+      const int nch = op ? nchB : nchA;
+      const uint32_t pad = (uint32_t)(op ? a.n_cols : a.n_rows);
+      for (int j = 0; j < kPairSlots16; ++j) {
+        const int c = (int)threadIdx.x + j * NT;
+        uint32_t wd = (pad + 1u + (threadIdx.x & 63u)) | (pad << 15);
+        if (c < nch) {
+          const uint2 y = gp[gc[c]];
+          const uint32_t sg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
+          wd = (y.x >> 16) | ((y.x & 0xFFFFu) << 15) | (sg << 30);
+        }
+        pdsc[(op * kPairSlots16 + j) * NT + threadIdx.x] = wd;
+      }
+    }
+  }
+  auto fix_pairs = [&]() {
+    uint32_t q[2][kPairSlots16];
+    T v0[2][kPairSlots16], v1[2][kPairSlots16];
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      const T* row = op ? rowB : rowA;
+      const int nch = op ? nchB : nchA;
+#pragma unroll
+      for (int j = 0; j < kPairSlots16; ++j) {
+        if (wave_pos + j * NT >= nch) continue;   // wave-uniform
+        q[op][j] = pdsc[(op * kPairSlots16 + j) * NT + threadIdx.x];
+        v0[op][j] = row[q[op][j] & 0x7FFFu];
+        v1[op][j] = row[(q[op][j] >> 15) & 0x7FFFu];
+      }
+    }
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      T* row = op ? rowB : rowA;
+      const int nch = op ? nchB : nchA;
+#pragma unroll
+      for (int j = 0; j < kPairSlots16; ++j) {
+        if (wave_pos + j * NT >= nch) continue;
+        row[q[op][j] & 0x7FFFu] = v0[op][j] + flip_sign(v1[op][j], ((q[op][j] >> 30) & 1u) << 31);
+      }
+    }
+  };
   constexpr int kJ = kSlots16 + 1;   // full slots and the partial one
   auto fix_desc = [&]() {
     bool rare = false;
@@ -833,6 +892,11 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
     if (!SINGLE) stage_row<T, NT>(rowB, Bm + kk * a.ldb, a.n_cols, dma);
   };
   auto fixups = [&]() {
+    if constexpr (DESC && FIX == 0) return;
+    if constexpr (DESC && FIX == 2) {
+      fix_pairs();
+      return;
+    }
     if constexpr (DESC) {
       fix_desc();
       return;
@@ -866,8 +930,10 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
     load_k(k0);
     if (dma) wait_dma();
     __syncthreads();
-    fixups();
-    __syncthreads();
+    if (!DESC || FIX != 0) {
+      fixups();
+      __syncthreads();
+    }
     gather();
     if (SINGLE) single_b(k0);
   }
@@ -898,8 +964,10 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
     if (more) {
       if (dma) wait_dma();
       __syncthreads();   // rows of k + 1 and the pads are in place
-      fixups();
-      __syncthreads();
+      if (FIX != 0) {
+        fixups();
+        __syncthreads();
+      }
       gather();
     }
   }
@@ -961,6 +1029,8 @@ constexpr int waves16() { return 2; }
 
 template <typename T, bool SINGLE, bool DESC, bool ALIAS>
 __global__ __launch_bounds__(512, waves16<T>()) void compress16_kernel(CompressArgs a) {
+  // units of a repetition without collision chains take the instance
+  // without fix-ups
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int LB = 13;
   const int b_hi_bits = a.log2b - LB;
@@ -976,7 +1046,22 @@ __global__ __launch_bounds__(512, waves16<T>()) void compress16_kernel(CompressA
   const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
   const int64_t k0 = (int64_t)g * k_per;
   const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
-  compress16_unit<T, SINGLE, DESC, ALIAS>(a, g, t, uhi, k0, k1, smem);
+  if constexpr (DESC) {
+    const int nA = a.planA.nchains[t], nB = a.planB.nchains[t];
+    if (nA == 0 && nB == 0) {
+      compress16_unit<T, SINGLE, DESC, ALIAS, 0>(a, g, t, uhi, k0, k1, smem);
+      return;
+    }
+    // extras equal chains: every chain has two rows
+    const int xA = a.planA.cstart[(size_t)t * (a.n_rows + 2) + nA];
+    const int xB = a.planB.cstart[(size_t)t * (a.n_cols + 2) + nB];
+    if (xA == nA && xB == nB && nA <= kPairSlots16 * 512 && nB <= kPairSlots16 * 512 &&
+        a.ovf16 >= kPairOvf16) {
+      compress16_unit<T, SINGLE, DESC, ALIAS, 2>(a, g, t, uhi, k0, k1, smem);
+      return;
+    }
+  }
+  compress16_unit<T, SINGLE, DESC, ALIAS, 1>(a, g, t, uhi, k0, k1, smem);
 }
 
 // The persistent batched form with the 16-element layout (b_lo = 2^13).
