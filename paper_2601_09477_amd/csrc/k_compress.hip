@@ -230,11 +230,11 @@ __global__ __launch_bounds__(kPlanThreads) void window_kernel(
 
 // Sum of the partials of a rotated frame back into natural order.  Natural
 // index u = a 2^s + c (c < 2^s) sits at rotated position c 2^(m - s) + a, so
-// a tile of 2048 consecutive natural indices is, for each of the 2^s values
-// of c, a run of 2048 / 2^s consecutive rotated positions: read per c
-// (coalesced, partials summed in group order), transposed through LDS,
-// written in natural order.
-constexpr int kRedTile = 2048;
+// a tile of 512 consecutive natural indices is, for each of the 2^s values
+// of c, a run of 512 / 2^s (>= 16) consecutive rotated positions: read per c
+// (coalesced, partials summed in group order, eight loads in flight),
+// transposed through LDS, written in natural order.
+constexpr int kRedTile = 512;
 __global__ __launch_bounds__(256) void reduce_window_kernel(const double* __restrict__ parts,
                                                             int g, int d, int log2b,
                                                             const int32_t* __restrict__ rot,
@@ -252,7 +252,15 @@ __global__ __launch_bounds__(256) void reduce_window_kernel(const double* __rest
     const int64_t up = ((int64_t)c << (log2b - s)) + a0 + j;   // rotated position
     const double* src = parts + (size_t)t * b + up;
     double acc = 0.0;
-    for (int q = 0; q < g; ++q) acc += src[(size_t)q * len];
+    int q = 0;
+    for (; q + 8 <= g; q += 8) {
+      double v[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = src[(size_t)(q + r) * len];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) acc += v[r];
+    }
+    for (; q < g; ++q) acc += src[(size_t)q * len];
     tile[c * (A + 1) + j] = acc;   // padded rows: the transposed reads spread over banks
   }
   __syncthreads();
@@ -270,7 +278,7 @@ cmm_status launch_reduce_window(const double* parts, int g, int d, int log2b, co
   if (!rot) return launch_reduce_partials(parts, g, (size_t)d * b, out, s);
   ProfScope prof_("reduce", s);
   if (b < kRedTile) {
-    set_error("reduce (window): needs b >= 2048");
+    set_error("reduce (window): needs b >= 512");
     return CMM_EUNSUPPORTED;
   }
   hipLaunchKernelGGL(reduce_window_kernel, dim3((unsigned)(b / kRedTile), d), dim3(256), 0, s,
@@ -722,19 +730,30 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   // an absent position adds the zero pad onto its lane's spare element.
   uint32_t* pdsc = reinterpret_cast<uint32_t*>(exl);   // [operand][slot][NT]
   if constexpr (DESC && FIX == 2) {
+    // slots that some wave takes (j NT < nch); the chain starts of all of
+    // them, then their entries, are fetched as independent loads
 #pragma unroll
     for (int op = 0; op < 2; ++op) {
       const int32_t* gc = op ? gcB : gcA;
       const uint2* gp = op ? gB : gA;
       const int nch = op ? nchB : nchA;
       const uint32_t pad = (uint32_t)(op ? a.n_cols : a.n_rows);
+      int beg[kPairSlots16];
+#pragma unroll
       for (int j = 0; j < kPairSlots16; ++j) {
         const int c = (int)threadIdx.x + j * NT;
+        beg[j] = c < nch ? gc[c] : -1;
+      }
+      uint2 y[kPairSlots16];
+#pragma unroll
+      for (int j = 0; j < kPairSlots16; ++j) y[j] = beg[j] >= 0 ? gp[beg[j]] : make_uint2(0u, 0u);
+#pragma unroll
+      for (int j = 0; j < kPairSlots16; ++j) {
+        if (j * NT >= nch) continue;   // no wave takes the slot
         uint32_t wd = (pad + 1u + (threadIdx.x & 63u)) | (pad << 15);
-        if (c < nch) {
-          const uint2 y = gp[gc[c]];
-          const uint32_t sg = (y.y >> 31) ^ (__popc(uhi & (y.y & kBucketMask)) & 1u);
-          wd = (y.x >> 16) | ((y.x & 0xFFFFu) << 15) | (sg << 30);
+        if (beg[j] >= 0) {
+          const uint32_t sg = (y[j].y >> 31) ^ (__popc(uhi & (y[j].y & kBucketMask)) & 1u);
+          wd = (y[j].x >> 16) | ((y[j].x & 0xFFFFu) << 15) | (sg << 30);
         }
         pdsc[(op * kPairSlots16 + j) * NT + threadIdx.x] = wd;
       }
