@@ -204,7 +204,28 @@ def heavy_hitter_extract(w, p, steps: int) -> dict:
     torch.cuda.synchronize()
     ms, n = cmm.cmm_profile_query("extract_heavy")
     cmm.cmm_profile_enable(False)
-    return {"threshold": w.tau, "hits": int(count.item()), "ms": ms / max(1, n)}
+    out = {"threshold": w.tau, "hits": int(count.item()), "ms": ms / max(1, n)}
+    # the k largest |C_hat| with k = the number of planted entries, sorted,
+    # without the dense output or a host synchronisation
+    k = len(w.rows)
+    trows = torch.empty(k, dtype=torch.int64, device=dev)
+    tcols = torch.empty(k, dtype=torch.int64, device=dev)
+    tvals = torch.empty(k, dtype=torch.float64, device=dev)
+    ws = torch.empty(max(1, cmm.cmm_topk_workspace_size(k)), dtype=torch.uint8, device=dev)
+    targs = (p, tab1, tab2, w.d, w.n, w.n, w.log2b, cmm.CMM_MEDIAN, k, trows, tcols, tvals)
+    cmm.cmm_extract_topk(*targs, workspace=ws)
+    torch.cuda.synchronize()
+    cmm.cmm_profile_enable(True)
+    for _ in range(steps):
+        cmm.cmm_extract_topk(*targs, workspace=ws)
+    torch.cuda.synchronize()
+    ms, n = cmm.cmm_profile_query("extract_topk")
+    cmm.cmm_profile_enable(False)
+    got = set(zip(trows.cpu().tolist(), tcols.cpu().tolist()))
+    planted = set(zip(np.asarray(w.rows).tolist(), np.asarray(w.cols).tolist()))
+    out["topk"] = {"k": k, "ms": ms / max(1, n), "planted_in_topk": len(got & planted),
+                   "planted": len(planted)}
+    return out
 
 
 HBM_PEAK_GBS = 8000.0
