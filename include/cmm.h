@@ -108,12 +108,14 @@ cmm_status cmm_hash_family(cmm_hash_kind kind, const uint64_t* keys, int d, int6
  *   side 1 (M = B, rows x cols, ld):  out[t][kk][x] = sum over j with
  *          bucket(tab[t][j]) = x of sign(tab[t][j]) * B[k0 + kk][j]
  *          (tab is tab2, uint32[d][cols]).
- * dtype CMM_F64 or CMM_F32 (M and out have the same type); out is
+ * dtype (of M) and out_dtype (of out) are each CMM_F64 or CMM_F32; out is
  * [d][kc][2^log2b], fully overwritten.  Terms are added in ascending index
- * order, so results are deterministic. */
+ * order, in float64 when either type is float64 (float32 inputs widen
+ * exactly), and each sum is rounded once to out_dtype, so results are
+ * deterministic. */
 cmm_status cmm_sketch(int side, const void* M, cmm_dtype dtype, int64_t rows, int64_t cols,
                       int64_t ld, const uint32_t* tab, int d, int log2b, int64_t k0, int64_t kc,
-                      void* out, void* stream);
+                      void* out, cmm_dtype out_dtype, void* stream);
 
 /* ------------------------------------------------------------------ FWHT */
 /* Section 3.2: in-place Walsh-Hadamard transform of `batch` contiguous
@@ -427,6 +429,7 @@ cmm_status cmm_gather_probe(const double* table, int64_t len, int64_t gathers, u
 /* ---------------------------------------------------------------- status */
 const char* cmm_status_string(cmm_status s);
 const char* cmm_last_error(void);
+/* 2 since cmm_sketch takes out_dtype. */
 int cmm_abi_version(void);
 
 #ifdef __cplusplus

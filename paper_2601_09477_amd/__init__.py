@@ -85,7 +85,7 @@ def lib() -> ctypes.CDLL:
     sig = {
         "cmm_hash": [vp, i32, i64, i64, i32, vp, vp, vp],
         "cmm_hash_family": [i32, vp, i32, i64, i64, i32, vp, vp, vp],
-        "cmm_sketch": [i32, vp, i32, i64, i64, i64, vp, i32, i32, i64, i64, vp, vp],
+        "cmm_sketch": [i32, vp, i32, i64, i64, i64, vp, i32, i32, i64, i64, vp, i32, vp],
         "cmm_fwht": [vp, i32, i64, i32, dbl, vp],
         "cmm_accumulate": [vp, vp, i32, i32, i64, i32, vp, vp],
         "cmm_extract": [vp, vp, vp, i32, i64, i64, i32, i32, vp, i32, i64, vp],
@@ -240,17 +240,18 @@ def cmm_hash(keys, d, n_rows, n_cols, log2b, tab1, tab2, stream=None) -> None:
 def cmm_sketch(side, M, rows, cols, ld=None, tab=None, d=None, log2b=None, k0=0, kc=None,
                out=None, stream=None) -> None:
     """Count sketches of columns k0 .. k0 + kc - 1 of A (side 0, M = A) or
-    rows of B (side 1, M = B) into out [d][kc][2^log2b] (M's dtype); ld
-    defaults to M's row stride and must equal it when given."""
+    rows of B (side 1, M = B) into out [d][kc][2^log2b] (float64 or float32,
+    either input type); ld defaults to M's row stride and must equal it when
+    given."""
     fn = "cmm_sketch"
     _like(M, fn, "M", _floats(), (rows, cols))
     ld = M.stride(0) if ld is None else ld
     _need(rows <= 1 or ld == M.stride(0), fn, f"ld {ld} differs from M's row stride {M.stride(0)}")
     _like(tab, fn, "tab", (_torch().int32,), (d, rows if side == 0 else cols))
-    _like(out, fn, "out", (M.dtype,), min_numel=d * kc << log2b)
+    _like(out, fn, "out", _floats(), min_numel=d * kc << log2b)
     _check("cmm_sketch", lib().cmm_sketch(side, _ptr(M, True), _dtype_code(M), rows, cols, ld,
                                           _ptr(tab), d, log2b, k0, kc, _ptr(out),
-                                          _stream(stream)))
+                                          _dtype_code(out), _stream(stream)))
 
 
 def cmm_fwht(x, batch, log2b, scale=1.0, stream=None) -> None:

@@ -468,9 +468,9 @@ cmm_status run_estimate(const cmm_problem* pr, char* ws, hipStream_t s) {
     for (int64_t k0 = 0; k0 < pr->n_inner; k0 += P.kc) {
       const int64_t kc = (pr->n_inner - k0) < P.kc ? (pr->n_inner - k0) : P.kc;
       if ((st = launch_sketch(0, A, P.cdt, pr->n_rows, pr->n_inner, lda, pr->tab1, d,
-                              pr->log2b, k0, kc, X, s)) != CMM_OK) return st;
+                              pr->log2b, k0, kc, X, P.cdt, s)) != CMM_OK) return st;
       if ((st = launch_sketch(1, B, P.cdt, pr->n_inner, pr->n_cols, ldb, pr->tab2, d,
-                              pr->log2b, k0, kc, Y, s)) != CMM_OK) return st;
+                              pr->log2b, k0, kc, Y, P.cdt, s)) != CMM_OK) return st;
       if ((st = launch_fwht(X, P.cdt, (int64_t)d * kc, pr->log2b, 1.0, s)) != CMM_OK) return st;
       if ((st = launch_fwht(Y, P.cdt, (int64_t)d * kc, pr->log2b, 1.0, s)) != CMM_OK) return st;
       if ((st = launch_accumulate(X, Y, P.cdt, d, kc, pr->log2b, p_hat, s)) != CMM_OK) return st;
@@ -667,7 +667,7 @@ using namespace cmm;
 
 extern "C" {
 
-int cmm_abi_version(void) { return 1; }
+int cmm_abi_version(void) { return 2; }
 
 void cmm_profile_enable(int on) {
   std::lock_guard<std::mutex> g(g_prof_mu);
@@ -754,10 +754,12 @@ cmm_status cmm_hash_family(cmm_hash_kind kind, const uint64_t* keys, int d, int6
 
 cmm_status cmm_sketch(int side, const void* M, cmm_dtype dtype, int64_t rows, int64_t cols,
                       int64_t ld, const uint32_t* tab, int d, int log2b, int64_t k0, int64_t kc,
-                      void* out, void* stream) {
+                      void* out, cmm_dtype out_dtype, void* stream) {
   cmm_status s;
   if (side != 0 && side != 1) return invalid("cmm_sketch: side must be 0 (A) or 1 (B)");
   if (!is_f64_or_f32(dtype)) return invalid("cmm_sketch: dtype must be CMM_F64 or CMM_F32");
+  if (!is_f64_or_f32(out_dtype))
+    return invalid("cmm_sketch: out_dtype must be CMM_F64 or CMM_F32");
   if ((s = check_d(d, "cmm_sketch")) != CMM_OK) return s;
   if ((s = check_log2b(log2b, "cmm_sketch")) != CMM_OK) return s;
   if (rows < 0 || cols < 0 || k0 < 0 || kc < 0) return invalid("cmm_sketch: negative size");
@@ -769,7 +771,7 @@ cmm_status cmm_sketch(int side, const void* M, cmm_dtype dtype, int64_t rows, in
       !fits_elems(d, side == 0 ? rows : cols))
     return too_large("cmm_sketch", "M, out or the table");
   if (!out || !tab || (rows > 0 && cols > 0 && !M)) return invalid("cmm_sketch: null pointer");
-  return launch_sketch(side, M, dtype, rows, cols, ld, tab, d, log2b, k0, kc, out,
+  return launch_sketch(side, M, dtype, rows, cols, ld, tab, d, log2b, k0, kc, out, out_dtype,
                        as_stream(stream));
 }
 
@@ -1083,9 +1085,9 @@ cmm_status run_estimate_fft(const cmm_problem* pr, char* ws, hipStream_t s) {
     for (int64_t k0 = 0; !P.fused && k0 < pr->n_inner; k0 += P.kc) {
       const int64_t kc = (pr->n_inner - k0) < P.kc ? (pr->n_inner - k0) : P.kc;
       if ((st = launch_sketch(0, pr->A, CMM_F64, pr->n_rows, pr->n_inner, pr->lda, pr->tab1, d,
-                              pr->log2b, k0, kc, X, s)) != CMM_OK) return st;
+                              pr->log2b, k0, kc, X, CMM_F64, s)) != CMM_OK) return st;
       if ((st = launch_sketch(1, pr->B, CMM_F64, pr->n_inner, pr->n_cols, pr->ldb, pr->tab2, d,
-                              pr->log2b, k0, kc, Y, s)) != CMM_OK) return st;
+                              pr->log2b, k0, kc, Y, CMM_F64, s)) != CMM_OK) return st;
       if ((st = launch_pack(X, Y, Z, (size_t)d * kc * b, s)) != CMM_OK) return st;
       if ((st = launch_fft(Z, Z2, (int64_t)d * kc, pr->log2b, 0, 1.0, s)) != CMM_OK) return st;
       if ((st = launch_accumulate_cyclic(Z2, d, kc, pr->log2b, Pacc, s)) != CMM_OK) return st;

@@ -66,7 +66,7 @@ cmm_status launch_hash_family(cmm_hash_kind kind, const uint64_t* keys, int d, i
 
 cmm_status launch_sketch(int side, const void* M, cmm_dtype dt, int64_t rows, int64_t cols,
                          int64_t ld, const uint32_t* tab, int d, int log2b, int64_t k0,
-                         int64_t kc, void* out, hipStream_t s);
+                         int64_t kc, void* out, cmm_dtype out_dt, hipStream_t s);
 
 cmm_status launch_fwht(void* x, cmm_dtype dt, int64_t batch, int log2b, double scale,
                        hipStream_t s);

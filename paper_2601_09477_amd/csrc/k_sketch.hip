@@ -11,6 +11,8 @@
 // The list is built once per work-group when the window's hits fit it
 // (always, unless b is small against n); otherwise it is rebuilt segment by
 // segment for every tile.
+#include <type_traits>
+
 #include "cmm_internal.h"
 
 namespace cmm {
@@ -26,13 +28,19 @@ constexpr int32_t kSkNone = 0x7FFFFFFF;
 template <typename T>
 struct SkTile { static constexpr int value = sizeof(T) == 8 ? 4 : 8; };   // 32 KB of LDS
 
-template <typename T>
+// Input type T, output type O; the sums are formed in float64 when either
+// is float64 (float32 inputs widen exactly), and rounded once to O.
+template <typename T, typename O>
+struct SkAcc { typedef typename std::conditional<sizeof(T) == 8 || sizeof(O) == 8, double, float>::type type; };
+
+template <typename T, typename O>
 __global__ __launch_bounds__(kSkThreads) void sketch_kernel(
     int side, const T* __restrict__ M, int64_t ld, const uint32_t* __restrict__ tab,
     int64_t n_idx, int log2b, int log2w, int64_t nwin, int64_t tiles_per_group, int64_t k0,
-    int64_t kc, int d, T* __restrict__ out) {
-  constexpr int KT = SkTile<T>::value;
-  __shared__ T acc[KT << kSkLogW];           // [kk][bucket in window]
+    int64_t kc, int d, O* __restrict__ out) {
+  typedef typename SkAcc<T, O>::type A;
+  constexpr int KT = SkTile<A>::value;
+  __shared__ A acc[KT << kSkLogW];           // [kk][bucket in window]
   __shared__ uint32_t hidx[kSkHC];           // hit index
   __shared__ uint32_t hkey[kSkHC];           // bucket in window | rank << 16 | sign bit
   __shared__ int32_t tag[1 << kSkLogW];
@@ -52,7 +60,7 @@ __global__ __launch_bounds__(kSkThreads) void sketch_kernel(
   const int64_t kt0 = grp * tiles_per_group;
   const int64_t kt1 = kt0 + tiles_per_group < ntiles ? kt0 + tiles_per_group : ntiles;
 
-  for (int e = tid; e < (KT << log2w); e += kSkThreads) acc[e] = T(0);
+  for (int e = tid; e < (KT << log2w); e += kSkThreads) acc[e] = A(0);
   for (int e = tid; e < W; e += kSkThreads) tag[e] = kSkNone;
   __syncthreads();
 
@@ -150,7 +158,7 @@ __global__ __launch_bounds__(kSkThreads) void sketch_kernel(
           const int kk = e - h * KT;
           const uint32_t hk = hkey[h];
           if ((int)((hk >> 16) & 0x7FFFu) != r || kb + kk >= kc) continue;
-          const T m = M[(int64_t)hidx[h] * idim + (k0 + kb + kk) * kdim];
+          const A m = (A)M[(int64_t)hidx[h] * idim + (k0 + kb + kk) * kdim];
           acc[(kk << log2w) + (hk & 0xFFFFu)] += (hk & kSignBit) ? -m : m;
         }
         __syncthreads();
@@ -160,9 +168,9 @@ __global__ __launch_bounds__(kSkThreads) void sketch_kernel(
     for (int e = tid; e < (KT << log2w); e += kSkThreads) {
       const int kk = e >> log2w;
       const int x = e & (W - 1);
-      const T v = acc[e];
-      acc[e] = T(0);
-      if (kb + kk < kc) out[((size_t)t * kc + kb + kk) * b + w * W + x] = v;
+      const A v = acc[e];
+      acc[e] = A(0);
+      if (kb + kk < kc) out[((size_t)t * kc + kb + kk) * b + w * W + x] = (O)v;
     }
     __syncthreads();
   }
@@ -170,14 +178,24 @@ __global__ __launch_bounds__(kSkThreads) void sketch_kernel(
 
 }  // namespace
 
+template <typename T, typename O>
+static void launch_sketch_t(dim3 grid, hipStream_t s, int side, const void* M, int64_t ld,
+                            const uint32_t* tab, int64_t n_idx, int log2b, int log2w,
+                            int64_t nwin, int64_t per, int64_t k0, int64_t kc, int d, void* out) {
+  hipLaunchKernelGGL((sketch_kernel<T, O>), grid, dim3(kSkThreads), 0, s, side,
+                     (const T*)M, ld, tab, n_idx, log2b, log2w, nwin, per, k0, kc, d, (O*)out);
+}
+
 cmm_status launch_sketch(int side, const void* M, cmm_dtype dt, int64_t rows, int64_t cols,
                          int64_t ld, const uint32_t* tab, int d, int log2b, int64_t k0,
-                         int64_t kc, void* out, hipStream_t s) {
+                         int64_t kc, void* out, cmm_dtype out_dt, hipStream_t s) {
   ProfScope prof_("sketch", s);
   const int64_t n_idx = side == 0 ? rows : cols;
   const int log2w = log2b < kSkLogW ? log2b : kSkLogW;
   const int64_t nwin = (int64_t)1 << (log2b - log2w);
-  const int kt = dt == CMM_F64 ? SkTile<double>::value : SkTile<float>::value;
+  // the tile follows the accumulation type (float64 when either side is)
+  const int kt = (dt == CMM_F64 || out_dt == CMM_F64) ? SkTile<double>::value
+                                                     : SkTile<float>::value;
   const int64_t ntiles = (kc + kt - 1) / kt;
   const int64_t base = (int64_t)d * nwin;
   int64_t groups = (kSkTarget + base - 1) / base;
@@ -186,14 +204,15 @@ cmm_status launch_sketch(int side, const void* M, cmm_dtype dt, int64_t rows, in
   groups = (ntiles + per - 1) / per;
   const int64_t blocks = base * groups;
   if (blocks > 0x7FFFFFFF) return invalid("cmm_sketch: d * 2^log2b too large");
-  if (dt == CMM_F64)
-    hipLaunchKernelGGL(sketch_kernel<double>, dim3((unsigned)blocks), dim3(kSkThreads), 0, s,
-                       side, (const double*)M, ld, tab, n_idx, log2b, log2w, nwin, per, k0, kc,
-                       d, (double*)out);
+  const dim3 grid((unsigned)blocks);
+  if (dt == CMM_F64 && out_dt == CMM_F64)
+    launch_sketch_t<double, double>(grid, s, side, M, ld, tab, n_idx, log2b, log2w, nwin, per, k0, kc, d, out);
+  else if (dt == CMM_F64)
+    launch_sketch_t<double, float>(grid, s, side, M, ld, tab, n_idx, log2b, log2w, nwin, per, k0, kc, d, out);
+  else if (out_dt == CMM_F64)
+    launch_sketch_t<float, double>(grid, s, side, M, ld, tab, n_idx, log2b, log2w, nwin, per, k0, kc, d, out);
   else
-    hipLaunchKernelGGL(sketch_kernel<float>, dim3((unsigned)blocks), dim3(kSkThreads), 0, s,
-                       side, (const float*)M, ld, tab, n_idx, log2b, log2w, nwin, per, k0, kc,
-                       d, (float*)out);
+    launch_sketch_t<float, float>(grid, s, side, M, ld, tab, n_idx, log2b, log2w, nwin, per, k0, kc, d, out);
   return hip_check(hipGetLastError(), "sketch kernel launch");
 }
 

@@ -36,7 +36,7 @@ def test_library_exports_every_header_symbol():
     L = _lib_or_skip()
     for name in _header_functions():
         assert hasattr(L, name), name
-    assert L.cmm_abi_version() == 1
+    assert L.cmm_abi_version() == 2
     assert L.cmm_status_string(1) == b"CMM_EINVAL"
 
 
@@ -59,10 +59,11 @@ def test_problem_struct_layout_matches_header():
     lambda L: L.cmm_hash_family(2, None, 3, 4, 4, 8, 1, 1, None),       # null keys
     lambda L: L.cmm_hash_family(1, 1, 0, 4, 4, 8, 1, 1, None),          # d = 0
     lambda L: L.cmm_hash_family(2, 1, 3, 4, 4, 8, 1, None, None),       # null tab2
-    lambda L: L.cmm_sketch(2, 1, 0, 4, 4, 4, 1, 1, 8, 0, 1, 1, None),   # bad side
-    lambda L: L.cmm_sketch(0, 1, 2, 4, 4, 4, 1, 1, 8, 0, 1, 1, None),   # bf16 not a sketch type
-    lambda L: L.cmm_sketch(0, 1, 0, 4, 4, 3, 1, 1, 8, 0, 1, 1, None),   # ld < cols
-    lambda L: L.cmm_sketch(0, 1, 0, 4, 4, 4, 1, 1, 8, 3, 2, 1, None),   # k0 + kc > inner
+    lambda L: L.cmm_sketch(2, 1, 0, 4, 4, 4, 1, 1, 8, 0, 1, 1, 0, None),   # bad side
+    lambda L: L.cmm_sketch(0, 1, 2, 4, 4, 4, 1, 1, 8, 0, 1, 1, 0, None),   # bf16 not a sketch type
+    lambda L: L.cmm_sketch(0, 1, 0, 4, 4, 4, 1, 1, 8, 0, 1, 1, 3, None),   # fp16 not an output type
+    lambda L: L.cmm_sketch(0, 1, 0, 4, 4, 3, 1, 1, 8, 0, 1, 1, 0, None),   # ld < cols
+    lambda L: L.cmm_sketch(0, 1, 0, 4, 4, 4, 1, 1, 8, 3, 2, 1, 0, None),   # k0 + kc > inner
     lambda L: L.cmm_fwht(1, 0, 4, 8, 3.0, None),                        # scale not a power of 2
     lambda L: L.cmm_fwht(1, 0, 4, 0, 1.0, None),                        # log2b = 0
     lambda L: L.cmm_fwht(None, 0, 4, 8, 1.0, None),                     # null x
@@ -308,8 +309,8 @@ def test_problem_just_inside_index_range():
 
 
 @pytest.mark.parametrize("call", [
-    lambda L: L.cmm_sketch(0, 1, 0, 46341, 46341, 46341, 1, 1, 8, 0, 1, 1, None),  # M
-    lambda L: L.cmm_sketch(0, 1, 0, 8, 1 << 20, 1 << 20, 1, 9, 20, 0, 1 << 20, 1, None),  # out
+    lambda L: L.cmm_sketch(0, 1, 0, 46341, 46341, 46341, 1, 1, 8, 0, 1, 1, 0, None),  # M
+    lambda L: L.cmm_sketch(0, 1, 0, 8, 1 << 20, 1 << 20, 1, 9, 20, 0, 1 << 20, 1, 0, None),  # out
     lambda L: L.cmm_fwht(1, 0, 1 << 12, 20, 1.0, None),                  # 2^32 elements
     lambda L: L.cmm_accumulate(1, 1, 0, 9, 1 << 12, 20, 1, None),
     lambda L: L.cmm_extract(1, 1, 1, 3, 46341, 46341, 8, 0, 1, 0, 46341, None),

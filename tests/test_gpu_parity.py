@@ -66,6 +66,37 @@ def test_sketch_f64_bit_exact(side, rows, cols, log2b, k0, kc):
     assert np.array_equal(host(out), want)
 
 
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("rows,cols,log2b,k0,kc", [(300, 129, 14, 7, 100), (5000, 40, 4, 3, 30)])
+def test_sketch_mixed_dtypes_bit_exact(side, rows, cols, log2b, k0, kc):
+    # float32 input into float64 sketches (the values widen exactly and are
+    # summed in float64 in ascending index order), and float64 input into
+    # float32 sketches (summed in float64, rounded once)
+    if side == 1:
+        rows, cols = cols, rows
+    n_inner = cols if side == 0 else rows
+    if k0 + kc > n_inner:
+        k0 = max(0, n_inner - kc)
+        kc = min(kc, n_inner)
+    announce(f"sketch mixed dtypes side={side} {rows}x{cols} log2b={log2b} k0={k0} kc={kc}")
+    t = torch()
+    rng = np.random.default_rng(rows + 3 * cols + log2b)
+    M = rng.standard_normal((rows, cols))
+    M32 = M.astype(np.float32)
+    d = 3
+    n_idx = rows if side == 0 else cols
+    tab = O.hash_tables(draw_keys(d, 15 + side), n_idx, n_idx, log2b)[side]
+    out64 = t.empty((d, kc, 1 << log2b), dtype=t.float64, device="cuda")
+    cmm.cmm_sketch(side, dev(M32, t.float32), rows, cols, cols, tables_dev(tab), d, log2b, k0, kc,
+                   out64)
+    assert np.array_equal(host(out64), O.count_sketch(M32.astype(np.float64), tab, side, k0, kc,
+                                                      log2b))
+    out32 = t.empty((d, kc, 1 << log2b), dtype=t.float32, device="cuda")
+    cmm.cmm_sketch(side, dev(M), rows, cols, cols, tables_dev(tab), d, log2b, k0, kc, out32)
+    want = O.count_sketch(M, tab, side, k0, kc, log2b).astype(np.float32)
+    assert np.array_equal(out32.cpu().numpy(), want)
+
+
 def test_sketch_f32_close():
     announce("sketch f32")
     t = torch()
