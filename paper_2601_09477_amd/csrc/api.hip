@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "cmm_internal.h"
 
 namespace cmm {
@@ -58,6 +60,10 @@ void prof_clear_locked() {
 thread_local bool t_prof_suppressed = false;
 
 ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), stream_(s) {
+  // a host range per launch step, named as its timing category (seen by
+  // tracing tools such as rocprofv3 --marker-trace; a few tens of ns when
+  // no tool is attached)
+  roctxRangePushA(name_);
   if (t_prof_suppressed || !g_prof_on.load(std::memory_order_relaxed)) return;
   {
     std::lock_guard<std::mutex> g(g_prof_mu);
@@ -71,6 +77,7 @@ ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), stream_(s) 
 }
 
 ProfScope::~ProfScope() {
+  roctxRangePop();
   if (!start_) return;
   hipEvent_t stop = nullptr;
   if (hipEventCreate(&stop) != hipSuccess) { (void)hipEventDestroy(start_); return; }

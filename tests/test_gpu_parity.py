@@ -291,6 +291,20 @@ def test_estimate_deterministic():
     assert torch().equal(r1.p, r2.p) and torch().equal(r1.C_hat, r2.C_hat)
 
 
+def test_estimate_deterministic_full_size():
+    # real-valued data at the headline shape (n = 4096, b = 2^16, d = 9):
+    # collision sums, window reduce and k-range partials run in a fixed
+    # order, so two runs agree bit for bit
+    announce("estimate determinism n=4096 b=2^16 d=9 N(0,1)")
+    rng = np.random.default_rng(4096)
+    A = dev(rng.standard_normal((4096, 4096)))
+    B = dev(rng.standard_normal((4096, 4096)))
+    keys = draw_keys(9, 77)
+    r1 = cmm.estimate(A, B, 9, 16, keys=keys)
+    r2 = cmm.estimate(A, B, 9, 16, keys=keys)
+    assert torch().equal(r1.p, r2.p) and torch().equal(r1.C_hat, r2.C_hat)
+
+
 def test_estimate_f32_compute():
     announce("estimate f32 compute")
     w = small_random(256, 128, 200, 14, 5, seed=5)
