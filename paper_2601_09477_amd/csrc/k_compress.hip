@@ -539,10 +539,10 @@ __host__ __device__ constexpr int64_t alias_area16(int64_t n) {
 }
 
 // ALIAS: no separate transpose buffer; once a step's rows are gathered into
-// registers, each operand's transpose goes through its own row area, and the
-// rows of the next step are staged after the transposed reads.  This keeps
-// both rows and the descriptors in LDS for rows too long to sit beside a
-// transpose buffer.
+// registers, A's row area takes the next step's row at once and both
+// transposes go through B's row area, whose next row is staged after the
+// second transpose.  This keeps both rows and the descriptors in LDS for
+// rows too long to sit beside a transpose buffer.
 // FIX (descriptor layouts): 1 the general descriptors below; 0 the
 // repetition has no collision chains in either operand (no descriptors, no
 // fix-ups: a unit without that code runs faster); 2 every chain of both
@@ -566,8 +566,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
   T* rowB = SINGLE ? rowA : rowA + pitch1;
   const int64_t pitch2 = ALIAS ? alias_area16<T>(a.n_cols) : pitch16<T, DESC>(a.n_cols);
   uint2* exl = reinterpret_cast<uint2*>(rowB + (SINGLE ? 0 : pitch2) + (SINGLE ? pitch1 : 0));
-  // transpose areas of X and Y
-  T* xa = ALIAS ? rowA : xbuf;
+  // transpose area of X and Y
   T* xb = ALIAS ? rowB : xbuf;
   if (!SINGLE && threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
 
@@ -960,29 +959,34 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
     const bool more = k + 1 < k1;
     pass1_16(X);
     __syncthreads();   // every thread's gathers of k are done: the row areas are free
+    // The row of A for k + 1 is copied while both transforms run; both
+    // transposes go through B's row area, one operand after the other, and
+    // the row of B for k + 1 follows the second transpose.
+    if (more) stage_row<T, NT>(rowA, At + (k + 1) * a.n_rows, a.n_rows, dma);
 #pragma unroll
-    for (int e = 0; e < E; ++e) xa[wr_t + wr_e(e)] = X[e];
+    for (int e = 0; e < E; ++e) xb[wr_t + wr_e(e)] = X[e];
     pass1_16(Y);
-#pragma unroll
-    for (int e = 0; e < E; ++e) xb[wr_t + wr_e(e)] = Y[e];
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) X[e] = xa[rd_t + rd_e(e)];
+    for (int e = 0; e < E; ++e) X[e] = xb[rd_t + rd_e(e)];
+    __syncthreads();   // the transposed reads of X are done
+#pragma unroll
+    for (int e = 0; e < E; ++e) xb[wr_t + wr_e(e)] = Y[e];
+    pass2_16(X, sgn8);
+    __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) Y[e] = xb[rd_t + rd_e(e)];
-    __syncthreads();   // the transposed reads are done: the areas take the rows of k + 1
+    __syncthreads();   // the transposed reads of Y are done: the area takes B's row of k + 1
     if (more) {
-      // the transposes overwrote the zero pads
-      if (threadIdx.x == 0) { rowA[a.n_rows] = T(0); rowB[a.n_cols] = T(0); }
-      load_k(k + 1);
+      if (threadIdx.x == 0) rowB[a.n_cols] = T(0);   // the transposes overwrote the pad
+      stage_row<T, NT>(rowB, Bm + (k + 1) * a.ldb, a.n_cols, dma);
     }
-    pass2_16(X, sgn8);
     pass2_16(Y, sgn8);
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = fma(X[e], Y[e], acc[e]);
     if (more) {
       if (dma) wait_dma();
-      __syncthreads();   // rows of k + 1 and the pads are in place
+      __syncthreads();   // rows of k + 1 and the pad are in place
       if (FIX != 0) {
         fixups();
         __syncthreads();
