@@ -758,7 +758,46 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
       }
     }
   }
+  // Slots of this wave that hold chains, per operand (slot j is live when
+  // one of the wave's positions j NT + lane has a chain), fixed for the
+  // unit and kept scalar: with few chains most waves skip the fix-up with
+  // one test, and the waves with one live slot per operand take a short path
+  // instead of testing every slot on every k.
+  int nsl[2] = {0, 0};
+  if constexpr (DESC && FIX == 2 && !ALIAS) {
+    const int wp = __builtin_amdgcn_readfirstlane(wave_pos);
+#pragma unroll
+    for (int op = 0; op < 2; ++op) {
+      const int nch = op ? nchB : nchA;
+      const int m = nch > wp ? (nch - wp + NT - 1) / NT : 0;
+      nsl[op] = __builtin_amdgcn_readfirstlane(m < kPairSlots16 ? m : kPairSlots16);
+    }
+  }
   auto fix_pairs = [&]() {
+    // (the aliased layout's units hold many chains: there every slot is
+    // tested, which keeps the code short)
+    if constexpr (!ALIAS) {
+      if (nsl[0] + nsl[1] == 0) return;
+      if (nsl[0] <= 1 && nsl[1] <= 1) {
+        uint32_t q[2];
+        T v0[2], v1[2];
+#pragma unroll
+        for (int op = 0; op < 2; ++op) {
+          if (nsl[op] == 0) continue;
+          const T* row = op ? rowB : rowA;
+          q[op] = pdsc[(op * kPairSlots16) * NT + threadIdx.x];
+          v0[op] = row[q[op] & 0x7FFFu];
+          v1[op] = row[(q[op] >> 15) & 0x7FFFu];
+        }
+#pragma unroll
+        for (int op = 0; op < 2; ++op) {
+          if (nsl[op] == 0) continue;
+          T* row = op ? rowB : rowA;
+          row[q[op] & 0x7FFFu] = v0[op] + flip_sign(v1[op], ((q[op] >> 30) & 1u) << 31);
+        }
+        return;
+      }
+    }
     uint32_t q[2][kPairSlots16];
     T v0[2][kPairSlots16], v1[2][kPairSlots16];
 #pragma unroll
@@ -767,7 +806,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
       const int nch = op ? nchB : nchA;
 #pragma unroll
       for (int j = 0; j < kPairSlots16; ++j) {
-        if (wave_pos + j * NT >= nch) continue;   // wave-uniform
+        if (ALIAS ? wave_pos + j * NT >= nch : j >= nsl[op]) continue;   // wave-uniform
         q[op][j] = pdsc[(op * kPairSlots16 + j) * NT + threadIdx.x];
         v0[op][j] = row[q[op][j] & 0x7FFFu];
         v1[op][j] = row[(q[op][j] >> 15) & 0x7FFFu];
@@ -779,7 +818,7 @@ __device__ __forceinline__ void compress16_unit(const CompressArgs& a, int g, in
       const int nch = op ? nchB : nchA;
 #pragma unroll
       for (int j = 0; j < kPairSlots16; ++j) {
-        if (wave_pos + j * NT >= nch) continue;
+        if (ALIAS ? wave_pos + j * NT >= nch : j >= nsl[op]) continue;
         row[q[op][j] & 0x7FFFu] = v0[op][j] + flip_sign(v1[op][j], ((q[op][j] >> 30) & 1u) << 31);
       }
     }
