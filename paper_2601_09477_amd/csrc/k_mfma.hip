@@ -142,7 +142,10 @@ __device__ __forceinline__ uint32_t pack2(float x, float y, _Float16*) {
 // case, when their LDS fits); DESC = false walks the plan's chain lists.
 // They are separate instances because the chain-walking code alone, even
 // unexecuted, costs the loop a quarter of its speed.
-constexpr int kSlots = 4;      // descriptor slots per thread and operand
+// Descriptor slots per thread and operand.  Two keep 24 KB of LDS for them;
+// the rest of the LDS stages merged two-row chains, which at n = 8192 hold
+// every chain the transform windows leave, so no descriptor is used there.
+constexpr int kSlots = 2;
 
 struct RareLists {
   const int32_t* gc[2];   // chain starts per operand
@@ -500,8 +503,10 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
         }
         // chains beyond the slots (identity order; disjoint targets), four
         // per thread at a time: their starts, first entries and first two
-        // rows are each fetched as independent loads
-        const int nch = rl->nch[op];
+        // rows are each fetched as independent loads.  Only an operand in
+        // identity order has them: in slot order every chain is either
+        // merged or in a slot, however many chains the operand has.
+        const int nch = ndesc[op] > kSlots * kNT ? rl->nch[op] : 0;
         for (int c0 = kSlots * kNT + (int)threadIdx.x; c0 < nch; c0 += 4 * kNT) {
           int beg[4], end[4];
 #pragma unroll

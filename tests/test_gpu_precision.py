@@ -221,20 +221,23 @@ def test_mfma_gaussian_8192_against_oracle():
         torch().cuda.empty_cache()
 
 
-@pytest.mark.parametrize("n", [10000, 12000])
+@pytest.mark.parametrize("n,key_seed", [(10000, 10005), (10500, 10501), (12000, 12005)])
 @pytest.mark.parametrize("compute", ["f16", "bf16"])
-def test_mfma_merged_chains_overflow(n, compute):
-    # At n = 10000 the two-row chains outnumber the sums the kernel can stage
-    # beside a row (the rest take collision descriptors); at n = 12000 the
-    # chains left to descriptors exceed their slots, so no chain is merged
-    # ahead of the kernel.  Every entry of p against the oracle on the
-    # rounded operands, within the derived tolerance.
+def test_mfma_merged_chains_overflow(n, key_seed, compute):
+    # Per repetition and operand (counted from the oracle's tables): at
+    # n = 10000 one operand's two-row chains are merged and its chains of
+    # three or more rows take collision descriptors; at n = 10500 the
+    # two-row chains outnumber the sums the kernel can stage beside a row,
+    # so the rest take descriptors; at n = 12000 (and in one operand of each
+    # of the others) the chains left to descriptors exceed their slots, so
+    # none is merged ahead of the kernel.  Every entry of p against the
+    # oracle on the rounded operands, within the derived tolerance.
     announce(f"mfma {compute} merged-chain overflow n={n}")
     rng = np.random.default_rng(n)
     n_inner, log2b, d = 16, 14, 3
     A = rng.standard_normal((n, n_inner))
     B = rng.standard_normal((n_inner, n))
-    keys = draw_keys(d, 5 + n)
+    keys = draw_keys(d, key_seed)
     rnd, u = _rounder(compute)
     res = cmm.estimate(dev(A), dev(B), d, log2b, keys=keys, compute=compute)
     Ar, Br = rnd(A), rnd(B)
