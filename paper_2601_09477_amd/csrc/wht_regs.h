@@ -162,17 +162,21 @@ __device__ __forceinline__ void stage_row(T* __restrict__ dst, const T* __restri
                                           int64_t n, bool dma) {
   if (dma) {
     // the wave's first chunk is wave-uniform (readfirstlane), so the LDS
-    // destination of every load is a scalar value; chunks < 2^31
+    // destination of every load is a scalar value; rounds with all 64
+    // chunks in the row skip the per-lane test; chunks < 2^31
     constexpr int V = 16 / sizeof(T);
     const int chunks = (int)(n / V);
     const int lane = threadIdx.x & 63;
     const int wbase = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * 64;
-    for (int c0 = wbase; c0 < chunks; c0 += NT) {
-      if (c0 + lane < chunks)
-        __builtin_amdgcn_global_load_lds(
-            (const void*)(src + (size_t)(c0 + lane) * V),
-            (__attribute__((address_space(3))) void*)(dst + (size_t)c0 * V), 16, 0, 0);
-    }
+    int c0 = wbase;
+    for (; c0 + 64 <= chunks; c0 += NT)
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(src + (size_t)(c0 + lane) * V),
+          (__attribute__((address_space(3))) void*)(dst + (size_t)c0 * V), 16, 0, 0);
+    if (c0 < chunks && c0 + lane < chunks)
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(src + (size_t)(c0 + lane) * V),
+          (__attribute__((address_space(3))) void*)(dst + (size_t)c0 * V), 16, 0, 0);
   } else {
     for (int64_t i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
   }
