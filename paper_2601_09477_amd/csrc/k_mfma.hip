@@ -52,7 +52,7 @@ template <> struct Mf<_Float16> {
 constexpr int kLB = 14;
 constexpr int kNT = 512;
 constexpr int kTiles = 8;
-constexpr int kFlush = 64;   // k steps summed in float32 before the float64 flush
+constexpr int kFlush = 128;   // k steps summed in float32 before the float64 flush
 
 template <typename IN>
 __device__ __forceinline__ IN neg_if(IN x, uint32_t neg) {

@@ -19,7 +19,7 @@ from workloads import draw_keys, planted_8192, small_random
 from tests.gpu_util import announce, dev, host, torch
 from tests.numerics import U_BF16, U_F16, p_tolerance, round_bf16, round_f16
 
-K_FLUSH = 64     # values of k summed in float32 between float64 flushes
+K_FLUSH = 128    # values of k summed in float32 between float64 flushes
 LEVELS_LP = 4    # low-precision roundings after the operand copy: collision sums, passes 1-3
 LEVELS_32 = 16   # float32 roundings inside the matrix passes (4 passes of 16-term sums)
 
@@ -76,9 +76,9 @@ def _exact_operands(n_rows, n_inner, n_cols, compute, seed):
     # Column k of A and row k of B have `per` entries +-1: every sketch
     # value, collision sum and partial transform is an integer of magnitude
     # <= per (exact in bf16 for per <= 256, in fp16 for per <= 2048), every
-    # product |X_u Y_u| <= per^2 and a float32 run of 64 such products stays
-    # below 2^24, so the form computes p exactly.
-    per = 192 if compute == "bf16" else 400
+    # product |X_u Y_u| <= per^2 and a float32 run of K_FLUSH such products
+    # stays below 2^24, so the form computes p exactly.
+    per = 192 if compute == "bf16" else 360
     rng = np.random.default_rng(seed)
     A = np.ascontiguousarray(_sparse_pm1(rng, n_inner, n_rows, per).T)
     B = _sparse_pm1(rng, n_inner, n_cols, per)
