@@ -660,19 +660,21 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
   f32x4 acc[kTiles];
 #pragma unroll
   for (int c = 0; c < kTiles; ++c) acc[c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  // the float64 sums of the flushes stay in registers; the slice of the
+  // partials is written once, after the last flush
+  double acc64[kTiles][4];
+#pragma unroll
+  for (int c = 0; c < kTiles; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc64[c][v] = 0.0;
   int pending = 0;
-  bool first_flush = true;
   auto flush = [&]() {
 #pragma unroll
     for (int c = 0; c < kTiles; ++c) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double* q = dst + (fin | (uint32_t)v | ((uint32_t)c << 2));
-        *q = (first_flush ? 0.0 : *q) + (double)acc[c][v];
-      }
+      for (int v = 0; v < 4; ++v) acc64[c][v] = acc64[c][v] + (double)acc[c][v];
       acc[c] = (f32x4){0.f, 0.f, 0.f, 0.f};
     }
-    first_flush = false;
     pending = 0;
   };
 
@@ -720,7 +722,11 @@ __global__ __launch_bounds__(kNT) void compress_mfma_kernel(CompressArgs a) {
     }
     if (++pending == kFlush) flush();
   }
-  if (pending > 0 || first_flush) flush();
+  if (pending > 0) flush();
+#pragma unroll
+  for (int c = 0; c < kTiles; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[fin | (uint32_t)v | ((uint32_t)c << 2)] = acc64[c][v];
 }
 
 }  // namespace
