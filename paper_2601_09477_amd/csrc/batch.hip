@@ -167,6 +167,7 @@ BatchLayout make_layout(const cmm_batch& b, const BatchConfig& c) {
     BatchPair& bp = L.pairs[i];
     bp = BatchPair{};
     bp.bc = -1;
+    bp.rtab1 = bp.rtab2 = bp.rot = -1;
     bp.d = p.d;
     bp.log2b = p.log2b;
     bp.n_rows = p.n_rows;
@@ -187,6 +188,11 @@ BatchLayout make_layout(const cmm_batch& b, const BatchConfig& c) {
     }
     bp.planA = (int64_t)off; off = align_up(off + plan_bytes(p.d, p.n_rows, c.lb), 256);
     bp.planB = (int64_t)off; off = align_up(off + plan_bytes(p.d, p.n_cols, c.lb), 256);
+    if (p.log2b > c.lb) {   // transform windows, as in the single-problem path
+      bp.rtab1 = (int64_t)off; off = align_up(off + sizeof(uint32_t) * (size_t)p.d * p.n_rows, 256);
+      bp.rtab2 = (int64_t)off; off = align_up(off + sizeof(uint32_t) * (size_t)p.d * p.n_cols, 256);
+      bp.rot = (int64_t)off; off = align_up(off + sizeof(int32_t) * (size_t)p.d, 256);
+    }
     bp.partial = (int64_t)off; off = align_up(off + sizeof(double) * groups[i] * p.d * blen, 256);
     const size_t base = lds_base(b.cdt, c, p.n_rows, p.n_cols);
     int64_t cap = (int64_t)((lds - std::min(lds, base)) / sizeof(uint2));
@@ -268,9 +274,23 @@ cmm_status prepare(const cmm_batch& b, const BatchLayout& L, int lb, char* ws, h
         if (st != CMM_OK) return st;
       }
     }
-    if ((st = launch_plan(p.tab1, p.d, p.n_rows, lb, carve_plan(ws + bp.planA, p.d, p.n_rows, lb), s)) != CMM_OK)
+    // each repetition's transform window (it depends on b_lo, so it is
+    // chosen again whenever the plans are), then the plans on the rotated
+    // tables
+    const uint32_t* t1 = p.tab1;
+    const uint32_t* t2 = p.tab2;
+    if (bp.rot >= 0) {
+      uint32_t* r1 = reinterpret_cast<uint32_t*>(ws + bp.rtab1);
+      uint32_t* r2 = reinterpret_cast<uint32_t*>(ws + bp.rtab2);
+      st = launch_window(p.tab1, p.tab2, p.d, p.n_rows, p.n_cols, p.log2b, lb, r1, r2,
+                         reinterpret_cast<int32_t*>(ws + bp.rot), s);
+      if (st != CMM_OK) return st;
+      t1 = r1;
+      t2 = r2;
+    }
+    if ((st = launch_plan(t1, p.d, p.n_rows, lb, carve_plan(ws + bp.planA, p.d, p.n_rows, lb), s)) != CMM_OK)
       return st;
-    if ((st = launch_plan(p.tab2, p.d, p.n_cols, lb, carve_plan(ws + bp.planB, p.d, p.n_cols, lb), s)) != CMM_OK)
+    if ((st = launch_plan(t2, p.d, p.n_cols, lb, carve_plan(ws + bp.planB, p.d, p.n_cols, lb), s)) != CMM_OK)
       return st;
   }
   return CMM_OK;
@@ -303,8 +323,13 @@ cmm_status finish(const cmm_batch& b, const BatchLayout& L, char* ws, hipStream_
     const size_t blen = (size_t)1 << p.log2b;
     double* pp = p.p ? p.p : reinterpret_cast<double*>(ws + L.off_p[i]);
     if (active(p)) {
-      st = launch_reduce_partials(reinterpret_cast<const double*>(ws + bp.partial), bp.groups,
-                                  (size_t)p.d * blen, pp, s);
+      if (bp.rot >= 0)   // partials in each repetition's rotated frame
+        st = launch_reduce_window(reinterpret_cast<const double*>(ws + bp.partial), bp.groups,
+                                  p.d, p.log2b, reinterpret_cast<const int32_t*>(ws + bp.rot),
+                                  pp, s);
+      else
+        st = launch_reduce_partials(reinterpret_cast<const double*>(ws + bp.partial), bp.groups,
+                                    (size_t)p.d * blen, pp, s);
       if (st != CMM_OK) return st;
       if ((st = launch_fwht(pp, CMM_F64, p.d, p.log2b, std::ldexp(1.0, -p.log2b), s)) != CMM_OK)
         return st;

@@ -223,7 +223,11 @@ struct BatchPair {
   const uint32_t* tab1;
   const uint32_t* tab2;
   int64_t planA, planB;    // plans (carve_plan layout)
-  int64_t partial;         // [groups][d][2^log2b] float64
+  // per-repetition transform windows: the tables rotated to them
+  // ([d][n_rows], [d][n_cols] u32) and the rotations ([d] i32), or -1 when
+  // the bucket has no bits beyond the slice
+  int64_t rtab1, rtab2, rot;
+  int64_t partial;         // [groups][d][2^log2b] float64, in the rotated frame
   int64_t ex_cap;
   int d, log2b, groups, dma;
   int ovf16;               // partial third descriptor slot (16-element layout)

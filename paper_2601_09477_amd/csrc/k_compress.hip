@@ -486,8 +486,8 @@ __global__ __launch_bounds__((1 << LB) / 32) void compress_batched_kernel(
     a.n_rows = bp.n_rows;
     a.n_cols = bp.n_cols;
     a.n_inner = bp.n_inner;
-    a.tab1 = bp.tab1;
-    a.tab2 = bp.tab2;
+    a.tab1 = bp.rtab1 >= 0 ? reinterpret_cast<const uint32_t*>(ws + bp.rtab1) : bp.tab1;
+    a.tab2 = bp.rtab2 >= 0 ? reinterpret_cast<const uint32_t*>(ws + bp.rtab2) : bp.tab2;
     a.planA = carve_plan(ws + bp.planA, bp.d, bp.n_rows, LB);
     a.planB = carve_plan(ws + bp.planB, bp.d, bp.n_cols, LB);
     a.d = bp.d;
@@ -1149,8 +1149,8 @@ __global__ __launch_bounds__(512, waves16<T>()) void compress16_batched_kernel(
     a.n_rows = bp.n_rows;
     a.n_cols = bp.n_cols;
     a.n_inner = bp.n_inner;
-    a.tab1 = bp.tab1;
-    a.tab2 = bp.tab2;
+    a.tab1 = bp.rtab1 >= 0 ? reinterpret_cast<const uint32_t*>(ws + bp.rtab1) : bp.tab1;
+    a.tab2 = bp.rtab2 >= 0 ? reinterpret_cast<const uint32_t*>(ws + bp.rtab2) : bp.tab2;
     a.planA = carve_plan(ws + bp.planA, bp.d, bp.n_rows, LB);
     a.planB = carve_plan(ws + bp.planB, bp.d, bp.n_cols, LB);
     a.d = bp.d;
@@ -1167,6 +1167,22 @@ __global__ __launch_bounds__(512, waves16<T>()) void compress16_batched_kernel(
     const int64_t k_per = (a.n_inner + a.groups - 1) / a.groups;
     const int64_t k0 = (int64_t)bi.group * k_per;
     const int64_t k1 = (k0 + k_per) < a.n_inner ? (k0 + k_per) : a.n_inner;
+    if constexpr (DESC) {
+      // as in the single-problem kernel: repetitions without chains, or
+      // with two-row chains only, take the shorter instances
+      const int nA = a.planA.nchains[t], nB = a.planB.nchains[t];
+      if (nA == 0 && nB == 0) {
+        compress16_unit<T, false, DESC, false, 0>(a, (int)bi.group, t, uhi, k0, k1, smem);
+        continue;
+      }
+      const int xA = a.planA.cstart[(size_t)t * (a.n_rows + 2) + nA];
+      const int xB = a.planB.cstart[(size_t)t * (a.n_cols + 2) + nB];
+      if (xA == nA && xB == nB && nA <= kPairSlots16 * 512 && nB <= kPairSlots16 * 512 &&
+          a.ovf16 >= kPairOvf16) {
+        compress16_unit<T, false, DESC, false, 2>(a, (int)bi.group, t, uhi, k0, k1, smem);
+        continue;
+      }
+    }
     compress16_unit<T, false, DESC>(a, (int)bi.group, t, uhi, k0, k1, smem);
   }
 }
